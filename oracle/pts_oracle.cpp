@@ -1,0 +1,450 @@
+// pts_oracle.cpp -- plain double-precision reference for the pointwise signed
+// distance of "Points as Tori" (Feng, Gkioulekas, Crane; ACM TOG 45(4), 2026).
+//
+// TEST INFRASTRUCTURE ONLY.  The product library never links, loads or calls
+// this file; only the test suite, the smoke check and the CPU-baseline leg of
+// the benchmark do.  It shares no code, header, table or constant with the GPU
+// path.
+//
+// Every step follows the paper in its own order and notation:
+//   * torus fitting            Sec. 4.1, Eqs. (BivariatePolynomial),
+//                              (MeanAndGaussCurvatures), (PrincipalDirections),
+//                              (TorusSigns), (SingleTorusSDF); App. C
+//   * blended evaluation       Sec. 4.2, Eqs. (BasicFormulaShifted),
+//                              (RelationshipBetweenLambdaAndRadius)
+//   * sphere tracing           Sec. 5.3 ("Direct visualization")
+// There is no blocking, fusion or reordering beyond those definitions.
+//
+// Derivatives (d phi/dx, d phi/da) are not hand-derived here: the same
+// templated code is evaluated on forward-mode dual numbers, so they are the
+// exact derivatives of what this file computes.  The GPU path implements the
+// closed-form gradient of App. D (plus the x-dependence of lambda_x) instead.
+//
+// Readings of the paper where it is silent or inconsistent (kept identical on
+// both sides; each is listed in the design notes):
+//   R-frame   tangent frame: e = x-hat if |n_x| < 0.9 else y-hat;
+//             s = normalize(e - <e,n>n), t = n x s.
+//   R-disc    H^2 - K < 0 from rounding is clamped to 0.
+//   R-tie     |kappa_+| == |kappa_-|  ->  kappa_min = kappa_-.
+//   R-floor   |kappa| <- max(|kappa|, kappa_floor) keeping the sign,
+//             sign(0) = -1; kappa_floor is an input (1e-6 / bbox diagonal).
+//   R-umbilic principal direction from the longer of the two row solutions of
+//             (II - kappa I) w = 0; if both vanish, v_min = s.
+//   R-center  c = Q*(0,0) + n*/kappa_min with the signed, floored kappa_min.
+//             (The printed c = Q* - sign(T)/|kappa_min| n* is kept as
+//             center_mode = 1 for comparison; it disagrees on saddles.)
+//   R-lambda  sum over all points with the per-query sigma_x, lambda_x;
+//             if max distance is 0 the weights are uniform.
+//   R-argmax  lambda_x depends on x through the farthest point; ties go to
+//             the lowest index (first maximum).
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+#include <algorithm>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Forward-mode dual numbers with K tangent directions.
+// ---------------------------------------------------------------------------
+template <int K>
+struct Dual {
+  double v;
+  double d[K];
+  Dual() : v(0.0) { for (int k = 0; k < K; ++k) d[k] = 0.0; }
+  Dual(double x) : v(x) { for (int k = 0; k < K; ++k) d[k] = 0.0; }
+};
+
+template <int K> inline Dual<K> operator+(const Dual<K>& a, const Dual<K>& b) {
+  Dual<K> r; r.v = a.v + b.v; for (int k = 0; k < K; ++k) r.d[k] = a.d[k] + b.d[k]; return r; }
+template <int K> inline Dual<K> operator-(const Dual<K>& a, const Dual<K>& b) {
+  Dual<K> r; r.v = a.v - b.v; for (int k = 0; k < K; ++k) r.d[k] = a.d[k] - b.d[k]; return r; }
+template <int K> inline Dual<K> operator-(const Dual<K>& a) {
+  Dual<K> r; r.v = -a.v; for (int k = 0; k < K; ++k) r.d[k] = -a.d[k]; return r; }
+template <int K> inline Dual<K> operator*(const Dual<K>& a, const Dual<K>& b) {
+  Dual<K> r; r.v = a.v * b.v; for (int k = 0; k < K; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k]; return r; }
+template <int K> inline Dual<K> operator/(const Dual<K>& a, const Dual<K>& b) {
+  Dual<K> r; r.v = a.v / b.v;
+  for (int k = 0; k < K; ++k) r.d[k] = (a.d[k] * b.v - a.v * b.d[k]) / (b.v * b.v);
+  return r; }
+template <int K> inline Dual<K> operator+(const Dual<K>& a, double b) { return a + Dual<K>(b); }
+template <int K> inline Dual<K> operator+(double a, const Dual<K>& b) { return Dual<K>(a) + b; }
+template <int K> inline Dual<K> operator-(const Dual<K>& a, double b) { return a - Dual<K>(b); }
+template <int K> inline Dual<K> operator-(double a, const Dual<K>& b) { return Dual<K>(a) - b; }
+template <int K> inline Dual<K> operator*(const Dual<K>& a, double b) { return a * Dual<K>(b); }
+template <int K> inline Dual<K> operator*(double a, const Dual<K>& b) { return Dual<K>(a) * b; }
+template <int K> inline Dual<K> operator/(const Dual<K>& a, double b) { return a / Dual<K>(b); }
+template <int K> inline Dual<K> operator/(double a, const Dual<K>& b) { return Dual<K>(a) / b; }
+
+inline double val(double x) { return x; }
+template <int K> inline double val(const Dual<K>& x) { return x.v; }
+
+inline double Sqrt(double x) { return std::sqrt(x); }
+inline double Exp(double x) { return std::exp(x); }
+inline double Abs(double x) { return std::fabs(x); }
+// At 0 the square root has no derivative; 0 is used (a subgradient choice).
+template <int K> inline Dual<K> Sqrt(const Dual<K>& a) {
+  Dual<K> r; r.v = std::sqrt(a.v);
+  for (int k = 0; k < K; ++k) r.d[k] = (r.v > 0.0) ? a.d[k] / (2.0 * r.v) : 0.0;
+  return r; }
+template <int K> inline Dual<K> Exp(const Dual<K>& a) {
+  Dual<K> r; r.v = std::exp(a.v); for (int k = 0; k < K; ++k) r.d[k] = r.v * a.d[k]; return r; }
+template <int K> inline Dual<K> Abs(const Dual<K>& a) { return (a.v < 0.0) ? -a : a; }
+
+template <class T> inline T dot3(const T* a, const T* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+template <class T> inline void cross3(const T* a, const T* b, T* o) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+template <class T> inline T norm3(const T* a) { return Sqrt(dot3(a, a)); }
+
+// ---------------------------------------------------------------------------
+// Torus fitted at one point (Sec. 4.1).
+// ---------------------------------------------------------------------------
+template <class T>
+struct Torus {
+  T c[3], u[3];       // center, unit axis of revolution
+  T R, r;             // major, minor radius
+  double sgn;         // sign(T_i), Eq. (TorusSigns)
+  // diagnostics
+  T kplus, kminus, kmin, kmax, kminf, kmaxf, H, K;
+  T nstar[3], vmin[3], o[3];
+  int umbilic;
+};
+
+// R-frame: the fixed orthonormal basis (s, t, n) at a point.
+void local_frame(const double* n_in, double* nh, double* s, double* t) {
+  double len = std::sqrt(n_in[0] * n_in[0] + n_in[1] * n_in[1] + n_in[2] * n_in[2]);
+  for (int k = 0; k < 3; ++k) nh[k] = n_in[k] / len;
+  double e[3] = {0.0, 0.0, 0.0};
+  if (std::fabs(nh[0]) < 0.9) e[0] = 1.0; else e[1] = 1.0;
+  double en = dot3(e, nh);
+  for (int k = 0; k < 3; ++k) s[k] = e[k] - en * nh[k];
+  double sl = norm3(s);
+  for (int k = 0; k < 3; ++k) s[k] /= sl;
+  cross3(nh, s, t);
+}
+
+// R-floor
+template <class T> T floor_curvature(const T& k, double kfloor) {
+  if (Abs(val(k)) >= kfloor) return k;
+  if (val(k) > 0.0) return T(kfloor);
+  return T(-kfloor);  // includes sign(0) = -1
+}
+
+// Torus fitting of Sec. 4.1 for one point.  a = (a00, a01, a10, a11, a02, a20).
+template <class T>
+Torus<T> fit_torus(const double* p, const double* n_in, const T* a, double kfloor, int center_mode) {
+  Torus<T> tor;
+  const T& a00 = a[0]; const T& a01 = a[1]; const T& a10 = a[2];
+  const T& a11 = a[3]; const T& a02 = a[4]; const T& a20 = a[5];
+  double nh[3], s[3], t[3];
+  local_frame(n_in, nh, s, t);
+
+  // Fundamental forms at (0,0) and Eq. (MeanAndGaussCurvatures).
+  T A = Sqrt(1.0 + a01 * a01 + a10 * a10);
+  T A3 = A * A * A;
+  T A4 = A3 * A;
+  T H = (a02 * (1.0 + a10 * a10) + a20 * (1.0 + a01 * a01) - a11 * a10 * a01) / A3;
+  T K = (4.0 * a02 * a20 - a11 * a11) / A4;
+  T disc = H * H - K;
+  if (val(disc) < 0.0) disc = T(0.0);  // R-disc
+  T sq = Sqrt(disc);
+  T kp = H + sq;
+  T km = H - sq;
+  tor.H = H; tor.K = K; tor.kplus = kp; tor.kminus = km;
+
+  // kappa_min / kappa_max by magnitude; R-tie.
+  T kmin, kmax;
+  if (Abs(val(kp)) < Abs(val(km))) { kmin = kp; kmax = km; }
+  else { kmin = km; kmax = kp; }
+  tor.kmin = kmin; tor.kmax = kmax;
+
+  // Eq. (PrincipalDirections) for kappa_min, both rows of (II - kappa I) w = 0.
+  T w1x = kmin * a10 * a01 * A - a11;
+  T w1y = 2.0 * a20 - kmin * (1.0 + a10 * a10) * A;
+  T w2x = 2.0 * a02 - kmin * (1.0 + a01 * a01) * A;
+  T w2y = kmin * a10 * a01 * A - a11;
+  double n1 = val(w1x) * val(w1x) + val(w1y) * val(w1y);
+  double n2 = val(w2x) * val(w2x) + val(w2y) * val(w2y);
+  T wx = w1x, wy = w1y;
+  double nw = n1;
+  if (n2 > n1) { wx = w2x; wy = w2y; nw = n2; }
+  double scale = std::fabs(val(a11)) + 2.0 * std::fabs(val(a20)) + 2.0 * std::fabs(val(a02)) +
+                 std::fabs(val(kmin)) * val(A) * (1.0 + val(a10) * val(a10) + val(a01) * val(a01));
+  T vmin[3];
+  tor.umbilic = 0;
+  if (!(std::sqrt(nw) > 1e-12 * scale)) {
+    tor.umbilic = 1;  // R-umbilic
+    for (int k = 0; k < 3; ++k) vmin[k] = T(s[k]);
+  } else {
+    T v[3];
+    for (int k = 0; k < 3; ++k) v[k] = wx * (s[k] + a10 * nh[k]) + wy * (t[k] + a01 * nh[k]);
+    T vl = norm3(v);
+    for (int k = 0; k < 3; ++k) vmin[k] = v[k] / vl;
+  }
+
+  // Polynomial normal n*(0,0).
+  T nstar[3];
+  for (int k = 0; k < 3; ++k) nstar[k] = (nh[k] - a10 * s[k] - a01 * t[k]) / A;
+
+  // R-floor, radii, Eq. (TorusSigns).
+  T kminf = floor_curvature(kmin, kfloor);
+  T kmaxf = floor_curvature(kmax, kfloor);
+  tor.kminf = kminf; tor.kmaxf = kmaxf;
+  double sgn_prod = (val(kminf) * val(kmaxf) > 0.0) ? 1.0 : -1.0;
+  tor.r = 1.0 / Abs(kmaxf);
+  tor.R = 1.0 / Abs(kminf) - sgn_prod * tor.r;
+  tor.sgn = (val(kmaxf) < 0.0) ? 1.0 : -1.0;
+
+  // Center (R-center) and axis.
+  T o[3];
+  for (int k = 0; k < 3; ++k) o[k] = p[k] + a00 * nh[k];
+  for (int k = 0; k < 3; ++k) {
+    if (center_mode == 1) tor.c[k] = o[k] - (tor.sgn / Abs(kminf)) * nstar[k];
+    else tor.c[k] = o[k] + nstar[k] / kminf;
+  }
+  cross3(nstar, vmin, tor.u);
+  for (int k = 0; k < 3; ++k) { tor.nstar[k] = nstar[k]; tor.vmin[k] = vmin[k]; tor.o[k] = o[k]; }
+  return tor;
+}
+
+// Eq. (SingleTorusSDF) and the signed g_i = sign(T_i) phi_T.
+template <class T, class X>
+auto torus_g(const Torus<T>& tor, const X* x) -> decltype(T() * X()) {
+  using V = decltype(T() * X());
+  V v[3], cr[3], u[3];
+  for (int k = 0; k < 3; ++k) { v[k] = x[k] - tor.c[k]; u[k] = V(0.0) + tor.u[k]; }
+  cross3(v, u, cr);
+  V rho = norm3(cr);
+  V h = dot3(v, u);
+  V e = rho - tor.R;
+  V q = Sqrt(e * e + h * h);
+  return tor.sgn * (q - tor.r);
+}
+
+// Stored torus layout (doubles per point).
+constexpr int TSTRIDE = 32;
+
+void store_torus(const Torus<double>& t, double* o) {
+  for (int k = 0; k < TSTRIDE; ++k) o[k] = 0.0;
+  for (int k = 0; k < 3; ++k) { o[k] = t.c[k]; o[3 + k] = t.u[k]; }
+  o[6] = t.R; o[7] = t.r; o[8] = t.sgn;
+  o[9] = t.kmin; o[10] = t.kmax; o[11] = t.kminf; o[12] = t.kmaxf;
+  for (int k = 0; k < 3; ++k) { o[13 + k] = t.nstar[k]; o[16 + k] = t.vmin[k]; o[19 + k] = t.o[k]; }
+  o[22] = t.H; o[23] = t.K; o[24] = t.umbilic; o[25] = t.kplus; o[26] = t.kminus;
+}
+
+Torus<double> load_torus(const double* o) {
+  Torus<double> t{};
+  for (int k = 0; k < 3; ++k) { t.c[k] = o[k]; t.u[k] = o[3 + k]; }
+  t.R = o[6]; t.r = o[7]; t.sgn = o[8];
+  return t;
+}
+
+// Eq. (BasicFormulaShifted) with (RelationshipBetweenLambdaAndRadius) at one
+// query, templated on the query type so that dual queries give d phi/dx.
+template <class X>
+X blend_at(int64_t N, const double* P, const std::vector<Torus<double>>& tori, const X* x,
+           double C, double* M_out, double* W_out) {
+  std::vector<X> d(N);
+  int64_t imax = 0;
+  for (int64_t i = 0; i < N; ++i) {
+    X dv[3];
+    for (int k = 0; k < 3; ++k) dv[k] = x[k] - P[3 * i + k];
+    d[i] = norm3(dv);
+    if (val(d[i]) > val(d[imax])) imax = i;  // R-argmax: first maximum
+  }
+  // NaN queries: propagate.
+  bool bad = false;
+  for (int k = 0; k < 3; ++k) if (!std::isfinite(val(x[k]))) bad = true;
+  if (bad) { if (M_out) *M_out = NAN; if (W_out) *W_out = NAN; return X(NAN); }
+  X M = d[imax];
+  X sigma = 0.5 * M;
+  X num(0.0), den(0.0);
+  if (val(M) == 0.0) {
+    for (int64_t i = 0; i < N; ++i) { num = num + torus_g(tori[i], x); den = den + 1.0; }
+  } else {
+    X lambda = C / sigma;
+    for (int64_t i = 0; i < N; ++i) {
+      X w = Exp(-lambda * (d[i] - sigma));
+      num = num + w * torus_g(tori[i], x);
+      den = den + w;
+    }
+  }
+  if (M_out) *M_out = val(M);
+  if (W_out) *W_out = val(den);
+  return num / den;
+}
+
+int set_threads(int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+  return omp_get_max_threads();
+#else
+  (void)nthreads;
+  return 1;
+#endif
+}
+
+}  // namespace
+
+extern "C" {
+
+int orc_version(void) { return 1; }
+
+int orc_threads(int nthreads) { return set_threads(nthreads); }
+
+// Length of the diagonal of the axis-aligned bounding box of N points.
+double orc_bbox_diag(int64_t N, const double* p) {
+  if (N <= 0) return 0.0;
+  double lo[3], hi[3];
+  for (int k = 0; k < 3; ++k) lo[k] = hi[k] = p[k];
+  for (int64_t i = 1; i < N; ++i)
+    for (int k = 0; k < 3; ++k) { lo[k] = std::min(lo[k], p[3 * i + k]); hi[k] = std::max(hi[k], p[3 * i + k]); }
+  double s = 0.0;
+  for (int k = 0; k < 3; ++k) s += (hi[k] - lo[k]) * (hi[k] - lo[k]);
+  return std::sqrt(s);
+}
+
+// The frame of R-frame for N normals: out is [N, 9] = (s, t, n-hat).
+void orc_frame(int64_t N, const double* n, double* out) {
+  for (int64_t i = 0; i < N; ++i) local_frame(n + 3 * i, out + 9 * i + 6, out + 9 * i, out + 9 * i + 3);
+}
+
+// Torus fitting (Sec. 4.1) for N points; out is [N, 32] (see store_torus).
+int orc_fit(int64_t N, const double* p, const double* n, const double* a, double kfloor,
+            int center_mode, double* out) {
+  for (int64_t i = 0; i < N; ++i) {
+    double nl = std::sqrt(n[3 * i] * n[3 * i] + n[3 * i + 1] * n[3 * i + 1] + n[3 * i + 2] * n[3 * i + 2]);
+    if (!(nl > 0.0)) return 1;
+    Torus<double> t = fit_torus<double>(p + 3 * i, n + 3 * i, a + 6 * i, kfloor, center_mode);
+    store_torus(t, out + (size_t)TSTRIDE * i);
+  }
+  return 0;
+}
+
+// g_i(x_q) for all pairs: out is [Q, N].
+void orc_torus_g(int64_t N, const double* tor, int64_t Q, const double* x, double* out) {
+  std::vector<Torus<double>> tt(N);
+  for (int64_t i = 0; i < N; ++i) tt[i] = load_torus(tor + (size_t)TSTRIDE * i);
+  for (int64_t q = 0; q < Q; ++q)
+    for (int64_t i = 0; i < N; ++i) out[q * N + i] = torus_g(tt[i], x + 3 * q);
+}
+
+// phi at Q queries (Eq. BasicFormulaShifted).  grad [Q,3] and stats [Q,3] =
+// (max distance M, shifted weight sum W, phi) are optional (NULL).
+int orc_eval(int64_t N, const double* p, const double* tor, int64_t Q, const double* x, double C,
+             int nthreads, double* phi, double* grad, double* stats) {
+  if (N <= 0) return 1;
+  set_threads(nthreads);
+  std::vector<Torus<double>> tt(N);
+  for (int64_t i = 0; i < N; ++i) tt[i] = load_torus(tor + (size_t)TSTRIDE * i);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t q = 0; q < Q; ++q) {
+    double M, W;
+    if (grad) {
+      Dual<3> xd[3];
+      for (int k = 0; k < 3; ++k) { xd[k] = Dual<3>(x[3 * q + k]); xd[k].d[k] = 1.0; }
+      Dual<3> f = blend_at(N, p, tt, xd, C, &M, &W);
+      phi[q] = f.v;
+      for (int k = 0; k < 3; ++k) grad[3 * q + k] = f.d[k];
+    } else {
+      phi[q] = blend_at(N, p, tt, x + 3 * q, C, &M, &W);
+    }
+    if (stats) { stats[3 * q] = M; stats[3 * q + 1] = W; stats[3 * q + 2] = phi[q]; }
+  }
+  return 0;
+}
+
+// dL/da for L = sum_q gout_q phi(x_q): [N, 6].  The weights do not depend on a,
+// so d phi_q / d a_i = (w_qi / W_q) d g_i(x_q) / d a_i, with the torus of
+// point i refitted on dual coefficients.
+int orc_grad_a(int64_t N, const double* p, const double* n, const double* a, double kfloor,
+               int center_mode, int64_t Q, const double* x, double C, const double* gout,
+               int nthreads, double* ga) {
+  if (N <= 0) return 1;
+  set_threads(nthreads);
+  // Per-query M and W from the definition.
+  std::vector<double> M(Q), W(Q);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t q = 0; q < Q; ++q) {
+    double m = -1.0;
+    for (int64_t i = 0; i < N; ++i) {
+      double dv[3] = {x[3 * q] - p[3 * i], x[3 * q + 1] - p[3 * i + 1], x[3 * q + 2] - p[3 * i + 2]};
+      m = std::max(m, norm3(dv));
+    }
+    M[q] = m;
+    double s = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+      double dv[3] = {x[3 * q] - p[3 * i], x[3 * q + 1] - p[3 * i + 1], x[3 * q + 2] - p[3 * i + 2]};
+      double di = norm3(dv);
+      s += (m == 0.0) ? 1.0 : std::exp(-(C / (0.5 * m)) * (di - 0.5 * m));
+    }
+    W[q] = s;
+  }
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < N; ++i) {
+    Dual<6> ad[6];
+    for (int j = 0; j < 6; ++j) { ad[j] = Dual<6>(a[6 * i + j]); ad[j].d[j] = 1.0; }
+    Torus<Dual<6>> t = fit_torus<Dual<6>>(p + 3 * i, n + 3 * i, ad, kfloor, center_mode);
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t q = 0; q < Q; ++q) {
+      if (gout[q] == 0.0) continue;
+      double dv[3] = {x[3 * q] - p[3 * i], x[3 * q + 1] - p[3 * i + 1], x[3 * q + 2] - p[3 * i + 2]};
+      double di = norm3(dv);
+      double w = (M[q] == 0.0) ? 1.0 : std::exp(-(C / (0.5 * M[q])) * (di - 0.5 * M[q]));
+      Dual<6> g = torus_g(t, x + 3 * q);
+      double f = gout[q] * w / W[q];
+      for (int j = 0; j < 6; ++j) acc[j] += f * g.d[j];
+    }
+    for (int j = 0; j < 6; ++j) ga[6 * i + j] = acc[j];
+  }
+  return 0;
+}
+
+// Sphere tracing (Sec. 5.3): march x = o + t d with step phi(x) until
+// |phi| < eps (hit), t > tmax (miss) or `steps` evaluations.  Outputs the
+// final t, a hit flag, the number of steps taken and, for hits, the unit
+// normal grad phi / |grad phi| at the hit point.
+int orc_trace(int64_t N, const double* p, const double* tor, int64_t Rn, const double* org,
+              const double* dir, int steps, double eps, double tmax, double C, int nthreads,
+              double* t_out, int* hit_out, int* nsteps_out, double* normal_out) {
+  if (N <= 0) return 1;
+  set_threads(nthreads);
+  std::vector<Torus<double>> tt(N);
+  for (int64_t i = 0; i < N; ++i) tt[i] = load_torus(tor + (size_t)TSTRIDE * i);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t r = 0; r < Rn; ++r) {
+    double t = 0.0;
+    int hit = 0, k = 0;
+    double xq[3];
+    for (k = 0; k < steps; ++k) {
+      for (int j = 0; j < 3; ++j) xq[j] = org[3 * r + j] + t * dir[3 * r + j];
+      double f = blend_at(N, p, tt, xq, C, nullptr, nullptr);
+      if (std::fabs(f) < eps) { hit = 1; break; }
+      t += f;
+      if (t > tmax) break;
+    }
+    t_out[r] = t;
+    hit_out[r] = hit;
+    nsteps_out[r] = k;
+    for (int j = 0; j < 3; ++j) normal_out[3 * r + j] = 0.0;
+    if (hit) {
+      Dual<3> xd[3];
+      for (int j = 0; j < 3; ++j) { xd[j] = Dual<3>(org[3 * r + j] + t * dir[3 * r + j]); xd[j].d[j] = 1.0; }
+      Dual<3> f = blend_at(N, p, tt, xd, C, nullptr, nullptr);
+      double gl = std::sqrt(f.d[0] * f.d[0] + f.d[1] * f.d[1] + f.d[2] * f.d[2]);
+      if (gl > 0.0) for (int j = 0; j < 3; ++j) normal_out[3 * r + j] = f.d[j] / gl;
+    }
+  }
+  return 0;
+}
+
+}  // extern "C"
