@@ -1,0 +1,174 @@
+/*
+ * pts.h -- C ABI of the MI355X (gfx950) library for pointwise signed distance
+ * to point clouds, after "Points as Tori: Fast Pointwise Signed Distance for
+ * Point Clouds" (Feng, Gkioulekas, Crane; ACM TOG 45(4), 2026).
+ *
+ * Problem statement (Algorithm 1): given oriented points (p_i, n_i) and, per
+ * point, the six coefficients of a quadratic height function over the point's
+ * supporting plane (Sec. 4.1, Eq. BivariatePolynomial), precompute one torus
+ * per point ("precomputation", pts_cloud_build), then evaluate
+ *
+ *     phi(x) = sum_i g_i(x) w_i(x) / sum_i w_i(x),
+ *     w_i(x) = exp(-lambda_x (|x - p_i| - sigma_x)),
+ *     sigma_x = max_i |x - p_i| / 2,  lambda_x = C / sigma_x,
+ *
+ * at arbitrary query points ("inference", pts_eval), where g_i is the signed
+ * distance to point i's torus (Sec. 4.2, Eqs. BasicFormulaShifted,
+ * RelationshipBetweenLambdaAndRadius, SingleTorusSDF).  The sum runs over all
+ * points.
+ *
+ * Conventions for every call:
+ *  - Pointers marked "device" are HIP device pointers on the current device;
+ *    the caller owns them.  Arrays are dense, row-major, float32 unless stated.
+ *  - Calls enqueue work on `stream` (a hipStream_t; NULL = default stream) and
+ *    return without waiting unless stated.  Results are valid after the stream
+ *    has been synchronised.
+ *  - Every call returns a status (PTS_OK = 0 on success).  On failure nothing
+ *    has been enqueued, and pts_last_error() returns a message for the calling
+ *    thread.  No C++ exception crosses this boundary.
+ *  - No entry point allocates device memory except the server (pts_server_*),
+ *    which allocates from its own budget; scratch memory is passed in by the
+ *    caller, sized by the matching *_ws_bytes call.
+ *
+ * Input format of the coefficients (the paper's network output, Sec. 4.3):
+ *   a = (a00, a01, a10, a11, a02, a20) per point, for
+ *   Q_i(s,t) = sum a_nm s^n t^m over the frame (s_i, t_i, n_i), with
+ *   n_i normalised internally and the frame fixed as
+ *   e = (1,0,0) if |n_x| < 0.9 else (0,1,0),
+ *   s = normalize(e - <e,n> n),  t = n x s.
+ *   Curvature is signed along +n: a convex surface with outward normals has
+ *   negative a02, a20 (a02 = a20 = -1/2 is the tangent unit sphere).
+ */
+#ifndef PTS_H
+#define PTS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define PTS_OK 0
+#define PTS_EINVAL 1      /* invalid argument (null pointer, size, layout)   */
+#define PTS_EBUDGET 2     /* request does not fit the server's memory budget */
+#define PTS_ENOMEM 3      /* device allocation failed (server only)         */
+#define PTS_EHIP 4        /* a HIP runtime call failed                       */
+#define PTS_EBUSY 5       /* server queue full                               */
+#define PTS_ECANCELLED 6  /* request cancelled                               */
+#define PTS_ENOTFOUND 7   /* unknown cloud id or ticket                      */
+#define PTS_ETIMEOUT 8    /* wait timed out                                  */
+
+/* Library version (major * 100 + minor). */
+int pts_version(void);
+
+/* Message for the last non-zero status returned on the calling thread. */
+const char* pts_last_error(void);
+
+/* Parameters.  A NULL pointer means the defaults below. */
+typedef struct pts_params {
+  float C;           /* screening constant of Eq. (RelationshipBetweenLambdaAndRadius);
+                        default 64 (Sec. 4.2).  0 < C <= 87 (FP32 range of e^-C). */
+  float kfloor_rel;  /* curvature floor kappa_floor = kfloor_rel / D, D = bbox
+                        diagonal of the cloud (D = 1 if it is 0); default 1e-6.
+                        Applied at build time.  Principal curvatures smaller in
+                        magnitude are raised to +-kappa_floor (sign(0) = -1),
+                        which keeps planar and cylindrical points at finite,
+                        very large torus radii (Sec. 6, "Sharp feature extraction"). */
+  int splits;        /* 0 = automatic.  Otherwise the number of point ranges a
+                        query's sum is split over (power of two, <= 64); results
+                        depend on it only through FP32 rounding order. */
+  int reserved;
+} pts_params;
+
+/* ---------------------------------------------------------------------------
+ * Precomputation (Algorithm 1, first stage; torus fitting of Sec. 4.1).
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of the opaque per-cloud record buffer for N points (N >= 1). */
+int pts_record_bytes(int64_t N, size_t* out_bytes);
+
+/* Fit one torus per point and lay the cloud out for evaluation.
+ *   p [N,3], n [N,3], a [N,6]  device, float32 (layout above).
+ *   rec                        device, rec_bytes >= pts_record_bytes(N);
+ *                              256-byte aligned; written entirely.
+ * The torus of point i (Sec. 4.1): principal curvatures kappa_+- = H +- sqrt(H^2-K)
+ * (Eq. MeanAndGaussCurvatures; H^2-K < 0 from rounding is clamped to 0),
+ * kappa_min / kappa_max by magnitude (ties: kappa_min = kappa_-), radii
+ * r = 1/|kappa_max|, R = 1/|kappa_min| - sign(kappa_+ kappa_-) r, sign
+ * (Eq. TorusSigns) +1 iff kappa_max < 0, center c = Q*(0,0) + n* / kappa_min
+ * with kappa_min signed (this equals the printed center on elliptic points and
+ * keeps saddle points on the correct side), axis u = n* x v_min with v_min
+ * from Eq. (PrincipalDirections) (the longer of the two row solutions; the
+ * frame vector s at umbilics).  Derivation runs in FP64; the record is FP32.
+ * Blocks until the build has finished (it reads back a status word).
+ * Errors: PTS_EINVAL for N < 1, null pointers, a short buffer, or a normal
+ * with |n| <= 1e-20 or a non-finite input (detected on the device). */
+int pts_cloud_build(const float* p, const float* n, const float* a, int64_t N,
+                    const pts_params* prm, void* rec, size_t rec_bytes, void* stream);
+
+/* Summary of a built record (copied to the host; blocks). */
+typedef struct pts_cloud_info {
+  int64_t N;          /* points */
+  int64_t n_direct;   /* points evaluated with the direct torus formula */
+  int64_t n_anchored; /* points with radius L > 4 D, evaluated in the anchored form */
+  float bbox_lo[3], bbox_hi[3];
+  float diag;         /* bbox diagonal D */
+  float kfloor;       /* curvature floor used */
+  int version;
+  int reserved;
+} pts_cloud_info;
+int pts_cloud_info_get(const void* rec, pts_cloud_info* out, void* stream);
+
+/* Per-point torus in the caller's original point order, for inspection:
+ * out [N,12] device float32 = (c.x, c.y, c.z, u.x, u.y, u.z, R, r, sign,
+ * L = 1/|kappa_min|, anchored flag, 0).  Asynchronous. */
+int pts_cloud_decode(const void* rec, int64_t N, float* out, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Inference (Algorithm 1, second stage; Sec. 4.2).
+ * ------------------------------------------------------------------------- */
+
+/* Scratch bytes pts_eval needs for N points and Q queries (given params). */
+int pts_eval_ws_bytes(int64_t N, int64_t Q, const pts_params* prm, size_t* out_bytes);
+
+/* phi at Q queries.
+ *   rec         device, built by pts_cloud_build for the same N.
+ *   x [Q,3]     device float32 queries.
+ *   sdf [Q]     device float32 output phi(x).
+ *   grad [Q,3]  device float32 output grad phi(x), or NULL.  The gradient is
+ *               the exact derivative of phi including the dependence of
+ *               lambda_x on x (App. D holds lambda fixed; the extra term is
+ *               (2C/M^2) e_* sum_i (w_i/W)(g_i - phi) d_i with M the largest
+ *               distance and e_* the unit vector from that point to x).
+ *   stats [Q,3] device float32 output (M, W, phi) or NULL: M = max_i |x-p_i|,
+ *               W = sum_i 2^(C log2(e) - lambda_x log2(e) |x - p_i|) (the shifted
+ *               weight sum of Eq. BasicFormulaShifted).  Used by the backward calls.
+ *   ws          device scratch of ws_bytes >= pts_eval_ws_bytes(N, Q, prm).
+ * A query with a NaN or infinite coordinate gives NaN.  Q = 0 is a no-op. */
+int pts_eval(const void* rec, int64_t N, const float* x, int64_t Q, float* sdf, float* grad,
+             float* stats, const pts_params* prm, void* ws, size_t ws_bytes, void* stream);
+
+/* The three launches of pts_eval as separate calls, with the same arguments
+ * and workspace, for callers that time or schedule them individually
+ * (pts_eval is exactly these three in order):
+ *   pts_eval_far      farthest-point sweep: M = max_i |x - p_i| per query and
+ *                     point split (Eq. RelationshipBetweenLambdaAndRadius);
+ *   pts_eval_blend    weighted sweep: per split, sum_i w_i g_i and sum_i w_i
+ *                     (Eq. BasicFormulaShifted); needs pts_eval_far's output;
+ *   pts_eval_combine  fixed-order sum over splits, phi = num / den, and the
+ *                     optional (M, W, phi) statistics.
+ * Errors as pts_eval. */
+int pts_eval_far(const void* rec, int64_t N, const float* x, int64_t Q, const pts_params* prm,
+                 void* ws, size_t ws_bytes, void* stream);
+int pts_eval_blend(const void* rec, int64_t N, const float* x, int64_t Q, const pts_params* prm,
+                   void* ws, size_t ws_bytes, void* stream);
+int pts_eval_combine(int64_t N, int64_t Q, float* sdf, float* stats, const pts_params* prm,
+                     void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PTS_H */

@@ -1,0 +1,222 @@
+"""ctypes binding of libpts (include/pts.h): argument marshalling only.
+
+Every function here checks tensor placement/dtype/shape, passes raw device
+pointers and the current HIP stream to the C ABI, and raises ``PtsError`` on a
+non-zero status.  All arithmetic runs in the library's HIP kernels; if the
+library is not built this module raises instead of falling back to anything.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpts.so")
+
+PTS_OK = 0
+PTS_EINVAL = 1
+PTS_EBUDGET = 2
+PTS_ENOMEM = 3
+PTS_EHIP = 4
+PTS_EBUSY = 5
+PTS_ECANCELLED = 6
+PTS_ENOTFOUND = 7
+PTS_ETIMEOUT = 8
+
+
+class PtsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"pts error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("C", ctypes.c_float), ("kfloor_rel", ctypes.c_float), ("splits", ctypes.c_int),
+                ("reserved", ctypes.c_int)]
+
+
+class CloudInfo(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int64), ("n_direct", ctypes.c_int64), ("n_anchored", ctypes.c_int64),
+                ("bbox_lo", ctypes.c_float * 3), ("bbox_hi", ctypes.c_float * 3), ("diag", ctypes.c_float),
+                ("kfloor", ctypes.c_float), ("version", ctypes.c_int), ("reserved", ctypes.c_int)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_SZ = ctypes.c_size_t
+
+# name -> (restype, argtypes); the list of symbols include/pts.h declares.
+SIGNATURES = {
+    "pts_version": (ctypes.c_int, []),
+    "pts_last_error": (ctypes.c_char_p, []),
+    "pts_record_bytes": (ctypes.c_int, [_I64, ctypes.POINTER(_SZ)]),
+    "pts_cloud_build": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.POINTER(Params), _P, _SZ, _P]),
+    "pts_cloud_info_get": (ctypes.c_int, [_P, ctypes.POINTER(CloudInfo), _P]),
+    "pts_cloud_decode": (ctypes.c_int, [_P, _I64, _P, _P]),
+    "pts_eval_ws_bytes": (ctypes.c_int, [_I64, _I64, ctypes.POINTER(Params), ctypes.POINTER(_SZ)]),
+    "pts_eval": (ctypes.c_int, [_P, _I64, _P, _I64, _P, _P, _P, ctypes.POINTER(Params), _P, _SZ, _P]),
+    "pts_eval_far": (ctypes.c_int, [_P, _I64, _P, _I64, ctypes.POINTER(Params), _P, _SZ, _P]),
+    "pts_eval_blend": (ctypes.c_int, [_P, _I64, _P, _I64, ctypes.POINTER(Params), _P, _SZ, _P]),
+    "pts_eval_combine": (ctypes.c_int, [_I64, _I64, _P, _P, ctypes.POINTER(Params), _P, _SZ, _P]),
+}
+
+
+def lib():
+    """Load libpts.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_2607_16946_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> None:
+    if rc != PTS_OK:
+        raise PtsError(rc, lib().pts_last_error().decode(errors="replace"))
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _dev(t: torch.Tensor, name: str, cols: int | None = None, dtype=torch.float32) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if cols is not None and (t.dim() != 2 or t.shape[1] != cols):
+        raise ValueError(f"{name} must have shape [n, {cols}], got {tuple(t.shape)}")
+    return t
+
+
+def make_params(C: float = 64.0, kfloor_rel: float = 1e-6, splits: int = 0) -> Params:
+    return Params(float(C), float(kfloor_rel), int(splits), 0)
+
+
+# ---------------------------------------------------------------------------
+# Functions named after the C ABI
+# ---------------------------------------------------------------------------
+
+def version() -> int:
+    return int(lib().pts_version())
+
+
+def record_bytes(N: int) -> int:
+    out = _SZ(0)
+    _check(lib().pts_record_bytes(int(N), ctypes.byref(out)))
+    return int(out.value)
+
+
+def cloud_build(p: torch.Tensor, n: torch.Tensor, a: torch.Tensor, params: Params | None = None,
+                rec: torch.Tensor | None = None) -> torch.Tensor:
+    """Fit the tori (Algorithm 1 precomputation); returns the record buffer (uint8 tensor)."""
+    _dev(p, "p", 3)
+    _dev(n, "n", 3)
+    _dev(a, "a", 6)
+    N = p.shape[0]
+    if n.shape[0] != N or a.shape[0] != N:
+        raise ValueError("p, n, a must have the same number of rows")
+    nb = record_bytes(N)
+    if rec is None:
+        rec = torch.empty(nb, dtype=torch.uint8, device=p.device)
+    _dev(rec, "rec", dtype=torch.uint8)
+    prm = params if params is not None else make_params()
+    _check(lib().pts_cloud_build(_ptr(p), _ptr(n), _ptr(a), N, ctypes.byref(prm), _ptr(rec), rec.numel(),
+                                 _stream()))
+    return rec
+
+
+def cloud_info(rec: torch.Tensor) -> CloudInfo:
+    info = CloudInfo()
+    _check(lib().pts_cloud_info_get(_ptr(rec), ctypes.byref(info), _stream()))
+    return info
+
+
+def cloud_decode(rec: torch.Tensor, N: int) -> torch.Tensor:
+    out = torch.empty((N, 12), dtype=torch.float32, device=rec.device)
+    _check(lib().pts_cloud_decode(_ptr(rec), int(N), _ptr(out), _stream()))
+    return out
+
+
+def eval_ws_bytes(N: int, Q: int, params: Params | None = None) -> int:
+    out = _SZ(0)
+    prm = params if params is not None else make_params()
+    _check(lib().pts_eval_ws_bytes(int(N), int(Q), ctypes.byref(prm), ctypes.byref(out)))
+    return int(out.value)
+
+
+def eval(rec: torch.Tensor, N: int, x: torch.Tensor, params: Params | None = None, grad: bool = False,
+         stats: bool = False, ws: torch.Tensor | None = None, out: torch.Tensor | None = None):
+    """phi(x) at queries x [Q,3] (Sec. 4.2); optionally grad phi [Q,3] and (M, W, phi) [Q,3]."""
+    _dev(x, "x", 3)
+    Q = x.shape[0]
+    prm = params if params is not None else make_params()
+    sdf = out if out is not None else torch.empty(Q, dtype=torch.float32, device=x.device)
+    g = torch.empty((Q, 3), dtype=torch.float32, device=x.device) if grad else None
+    st = torch.empty((Q, 3), dtype=torch.float32, device=x.device) if stats else None
+    need = eval_ws_bytes(N, Q, prm)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device=x.device)
+    _check(lib().pts_eval(_ptr(rec), int(N), _ptr(x), Q, _ptr(sdf), _ptr(g), _ptr(st), ctypes.byref(prm), _ptr(ws),
+                          ws.numel(), _stream()))
+    res = [sdf]
+    if grad:
+        res.append(g)
+    if stats:
+        res.append(st)
+    return res[0] if len(res) == 1 else tuple(res)
+
+
+def eval_far(rec, N: int, x: torch.Tensor, params: Params, ws: torch.Tensor) -> None:
+    _check(lib().pts_eval_far(_ptr(rec), int(N), _ptr(x), x.shape[0], ctypes.byref(params), _ptr(ws), ws.numel(),
+                              _stream()))
+
+
+def eval_blend(rec, N: int, x: torch.Tensor, params: Params, ws: torch.Tensor) -> None:
+    _check(lib().pts_eval_blend(_ptr(rec), int(N), _ptr(x), x.shape[0], ctypes.byref(params), _ptr(ws),
+                                ws.numel(), _stream()))
+
+
+def eval_combine(N: int, Q: int, sdf: torch.Tensor, params: Params, ws: torch.Tensor,
+                 stats: torch.Tensor | None = None) -> None:
+    _check(lib().pts_eval_combine(int(N), int(Q), _ptr(sdf), _ptr(stats), ctypes.byref(params), _ptr(ws),
+                                  ws.numel(), _stream()))
+
+
+class Cloud:
+    """A built point cloud resident in device memory (record buffer + parameters)."""
+
+    def __init__(self, p: torch.Tensor, n: torch.Tensor, a: torch.Tensor, C: float = 64.0,
+                 kfloor_rel: float = 1e-6, splits: int = 0):
+        self.params = make_params(C, kfloor_rel, splits)
+        self.N = int(p.shape[0])
+        self.rec = cloud_build(p, n, a, self.params)
+        self._ws = None
+
+    def info(self) -> CloudInfo:
+        return cloud_info(self.rec)
+
+    def decode(self) -> torch.Tensor:
+        return cloud_decode(self.rec, self.N)
+
+    def __call__(self, x: torch.Tensor, grad: bool = False, stats: bool = False):
+        need = eval_ws_bytes(self.N, x.shape[0], self.params)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device=x.device)
+        return eval(self.rec, self.N, x, self.params, grad=grad, stats=stats, ws=self._ws)

@@ -1,0 +1,183 @@
+// pts_api.hip -- C ABI entry points of libpts: argument checks, launch plans,
+// thread-local error messages.  All device work is in pts_build.hip and
+// pts_eval.hip; this file only validates, sizes and dispatches.
+#include "pts_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+namespace pts {
+
+namespace {
+thread_local std::string g_last_error;
+
+pts_params resolve(const pts_params* prm) {
+  pts_params r;
+  r.C = 64.0f;
+  r.kfloor_rel = 1e-6f;
+  r.splits = 0;
+  r.reserved = 0;
+  if (prm) {
+    if (prm->C != 0.0f) r.C = prm->C;
+    if (prm->kfloor_rel != 0.0f) r.kfloor_rel = prm->kfloor_rel;
+    r.splits = prm->splits;
+  }
+  return r;
+}
+
+int check_params(const pts_params& p) {
+  if (!(p.C > 0.0f && p.C <= 87.0f)) return fail(PTS_EINVAL, "C must be in (0, 87]");
+  if (!(p.kfloor_rel > 0.0f && std::isfinite(p.kfloor_rel))) return fail(PTS_EINVAL, "kfloor_rel must be > 0");
+  if (p.splits < 0 || p.splits > 64 || (p.splits & (p.splits - 1)) != 0)
+    return fail(PTS_EINVAL, "splits must be 0 or a power of two <= 64");
+  return PTS_OK;
+}
+}  // namespace
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int check_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return PTS_OK;
+  return fail(PTS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+Plan make_plan(int64_t N, int64_t Q, const pts_params* prm) {
+  Plan p;
+  // queries per lane: 4 once there are enough queries to fill the device
+  p.qpl = Q >= 4 * 256 * kBlock ? 4 : (Q >= 2 * 64 * kBlock ? 2 : 1);
+  p.nqb = (Q + int64_t(kBlock) * p.qpl - 1) / (int64_t(kBlock) * p.qpl);
+  const int64_t tiles = (N + kTile1 - 1) / kTile1;
+  int S;
+  if (prm && prm->splits > 0) {
+    S = prm->splits;
+  } else {
+    // one split per XCD when there are enough points; more splits while the
+    // grid is too small to fill 256 CUs and each split keeps >= 2 tiles
+    S = 1;
+    while (S < 8 && tiles >= int64_t(2) * S * 2) S *= 2;
+    while (S < 64 && p.nqb * S < 2048 && tiles >= int64_t(2) * S * 2) S *= 2;
+  }
+  const int64_t tiles_per = (tiles + S - 1) / S;
+  p.per_split = std::max<int64_t>(1, tiles_per) * kTile1;
+  // drop empty trailing splits
+  while (S > 1 && int64_t(S - 1) * p.per_split >= N) S /= 2;
+  p.S = S;
+  return p;
+}
+
+}  // namespace pts
+
+using namespace pts;
+
+extern "C" {
+
+int pts_version(void) { return 100; }
+
+const char* pts_last_error(void) { return g_last_error.c_str(); }
+
+int pts_record_bytes(int64_t N, size_t* out_bytes) {
+  if (!out_bytes) return fail(PTS_EINVAL, "out_bytes is NULL");
+  if (N < 1 || N > (int64_t(1) << 31) - 1) return fail(PTS_EINVAL, "N must be in [1, 2^31)");
+  *out_bytes = Layout(N).total;
+  return PTS_OK;
+}
+
+int pts_cloud_build(const float* p, const float* n, const float* a, int64_t N, const pts_params* prm, void* rec,
+                    size_t rec_bytes, void* stream) {
+  if (!p || !n || !a || !rec) return fail(PTS_EINVAL, "null pointer");
+  if (N < 1 || N > (int64_t(1) << 31) - 1) return fail(PTS_EINVAL, "N must be in [1, 2^31)");
+  if (reinterpret_cast<uintptr_t>(rec) % 256 != 0) return fail(PTS_EINVAL, "record buffer must be 256-byte aligned");
+  const pts_params P = resolve(prm);
+  if (int rc = check_params(P)) return rc;
+  const Layout L(N);
+  if (rec_bytes < L.total) return fail(PTS_EINVAL, "record buffer too small");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (int rc = launch_build(p, n, a, N, P.kfloor_rel, rec, st)) return rc;
+  int32_t status = 0;
+  const Header* h = static_cast<const Header*>(rec);
+  if (int rc = check_hip(hipMemcpyAsync(&status, &h->status, sizeof(status), hipMemcpyDeviceToHost, st),
+                         "read build status"))
+    return rc;
+  if (int rc = check_hip(hipStreamSynchronize(st), "build")) return rc;
+  if (status & kStatusNonFinite) return fail(PTS_EINVAL, "non-finite point, normal or coefficient");
+  if (status & kStatusZeroNormal) return fail(PTS_EINVAL, "zero-length normal");
+  return PTS_OK;
+}
+
+int pts_cloud_info_get(const void* rec, pts_cloud_info* out, void* stream) {
+  if (!rec || !out) return fail(PTS_EINVAL, "null pointer");
+  Header h;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (int rc = check_hip(hipMemcpyAsync(&h, rec, sizeof(h), hipMemcpyDeviceToHost, st), "read header")) return rc;
+  if (int rc = check_hip(hipStreamSynchronize(st), "read header")) return rc;
+  if (h.magic != kMagic) return fail(PTS_EINVAL, "not a built record");
+  std::memset(out, 0, sizeof(*out));
+  out->N = h.N;
+  out->n_direct = h.n_direct;
+  out->n_anchored = h.n_anchored;
+  for (int k = 0; k < 3; ++k) { out->bbox_lo[k] = h.lo[k]; out->bbox_hi[k] = h.hi[k]; }
+  out->diag = h.diag;
+  out->kfloor = h.kfloor;
+  out->version = h.version;
+  return PTS_OK;
+}
+
+int pts_cloud_decode(const void* rec, int64_t N, float* out, void* stream) {
+  if (!rec || !out) return fail(PTS_EINVAL, "null pointer");
+  if (N < 1) return fail(PTS_EINVAL, "N must be >= 1");
+  return launch_decode(rec, N, out, static_cast<hipStream_t>(stream));
+}
+
+int pts_eval_ws_bytes(int64_t N, int64_t Q, const pts_params* prm, size_t* out_bytes) {
+  if (!out_bytes) return fail(PTS_EINVAL, "out_bytes is NULL");
+  if (N < 1 || Q < 0) return fail(PTS_EINVAL, "N must be >= 1 and Q >= 0");
+  const pts_params P = resolve(prm);
+  if (int rc = check_params(P)) return rc;
+  *out_bytes = Q == 0 ? 0 : eval_ws_bytes(make_plan(N, Q, &P), Q);
+  return PTS_OK;
+}
+
+namespace {
+int eval_common(const void* rec, int64_t N, const float* x, int64_t Q, float* sdf, float* grad, float* stats,
+                const pts_params* prm, void* ws, size_t ws_bytes, void* stream, int stages) {
+  if (N < 1 || Q < 0) return fail(PTS_EINVAL, "N must be >= 1 and Q >= 0");
+  if (Q == 0) return PTS_OK;
+  if (!ws) return fail(PTS_EINVAL, "null workspace");
+  if ((stages & (kStageFar | kStageBlend)) && (!rec || !x)) return fail(PTS_EINVAL, "null record or queries");
+  if ((stages & kStageCombine) && !sdf) return fail(PTS_EINVAL, "null output");
+  if (Q > (int64_t(1) << 31) - 1) return fail(PTS_EINVAL, "Q must be < 2^31");
+  const pts_params P = resolve(prm);
+  if (int rc = check_params(P)) return rc;
+  const Plan plan = make_plan(N, Q, &P);
+  if (ws_bytes < eval_ws_bytes(plan, Q)) return fail(PTS_EINVAL, "workspace too small");
+  if (grad) return fail(PTS_EINVAL, "gradient output is not available in this build");
+  return launch_eval(rec, N, x, Q, sdf, grad, stats, P.C, plan, ws, static_cast<hipStream_t>(stream), stages);
+}
+}  // namespace
+
+int pts_eval(const void* rec, int64_t N, const float* x, int64_t Q, float* sdf, float* grad, float* stats,
+             const pts_params* prm, void* ws, size_t ws_bytes, void* stream) {
+  return eval_common(rec, N, x, Q, sdf, grad, stats, prm, ws, ws_bytes, stream, kStageAll);
+}
+
+int pts_eval_far(const void* rec, int64_t N, const float* x, int64_t Q, const pts_params* prm, void* ws,
+                 size_t ws_bytes, void* stream) {
+  return eval_common(rec, N, x, Q, nullptr, nullptr, nullptr, prm, ws, ws_bytes, stream, kStageFar);
+}
+
+int pts_eval_blend(const void* rec, int64_t N, const float* x, int64_t Q, const pts_params* prm, void* ws,
+                   size_t ws_bytes, void* stream) {
+  return eval_common(rec, N, x, Q, nullptr, nullptr, nullptr, prm, ws, ws_bytes, stream, kStageBlend);
+}
+
+int pts_eval_combine(int64_t N, int64_t Q, float* sdf, float* stats, const pts_params* prm, void* ws,
+                     size_t ws_bytes, void* stream) {
+  return eval_common(nullptr, N, nullptr, Q, sdf, nullptr, stats, prm, ws, ws_bytes, stream, kStageCombine);
+}
+
+}  // extern "C"

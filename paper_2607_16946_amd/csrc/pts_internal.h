@@ -1,0 +1,92 @@
+// pts_internal.h -- record layout and launch helpers shared by the HIP sources
+// of libpts (gfx950).  Not part of the public ABI (include/pts.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "pts.h"
+
+namespace pts {
+
+constexpr uint32_t kMagic = 0x31535450u;  // "PTS1"
+constexpr int kRecordVersion = 1;
+constexpr int kBlock = 256;               // threads per workgroup (4 waves of 64)
+constexpr int kTile2 = 128;               // points per LDS tile, blend pass (80 B each)
+constexpr int kTile1 = 512;               // points per LDS tile, farthest-point pass (16 B each)
+constexpr int kRecF4 = 5;                 // float4 per point record
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr double kDirectMaxL = 4.0;       // direct torus form when L <= 4 D
+
+// Cloud header (first 256 bytes of the record buffer).
+struct alignas(256) Header {
+  uint32_t magic;
+  int32_t version;
+  int64_t N;
+  int64_t n_direct;     // points [0, n_direct) use the direct torus form
+  int64_t n_anchored;   // points [n_direct, N) use the anchored form (L > 4 D)
+  float origin[3];      // record coordinates are relative to this point (bbox center)
+  float diag;           // bbox diagonal D
+  float kfloor;         // curvature floor
+  float lmax_direct;    // 4 D
+  float lo[3];
+  float hi[3];
+  uint32_t lo_bits[3];  // order-preserving encodings used by the bbox reduction
+  uint32_t hi_bits[3];
+  int32_t status;       // bit 0: zero normal, bit 1: non-finite input
+  int32_t pad0;
+};
+static_assert(sizeof(Header) == 256, "header is 256 bytes");
+
+constexpr int32_t kStatusZeroNormal = 1;
+constexpr int32_t kStatusNonFinite = 2;
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Byte offsets of the sections of a record buffer for N points.
+//   pos4  [N]     float4 (-2 p, |p|^2), farthest-point pass
+//   rec   [N][5]  float4 torus record, blend passes (layout in pts_build.hip)
+//   perm  [N]     int32 original index of each slot
+//   flag  [N]     int32 build scratch (direct-form flag)
+//   blk   [2*nb]  int32 build scratch (per-block counts and offsets)
+struct Layout {
+  size_t pos, rec, perm, flag, blk, total;
+  int64_t nblk;
+  explicit Layout(int64_t N) {
+    nblk = (N + kBlock - 1) / kBlock;
+    pos = 256;
+    rec = pos + align256(size_t(N) * 16);
+    perm = rec + align256(size_t(N) * 16 * kRecF4);
+    flag = perm + align256(size_t(N) * 4);
+    blk = flag + align256(size_t(N) * 4);
+    total = blk + align256(size_t(nblk) * 8);
+  }
+};
+
+// Split of the point range of one evaluation (a pure function of N, Q and the
+// parameters, so that a request gives the same result alone or batched).
+struct Plan {
+  int qpl;            // queries per lane
+  int S;              // point splits
+  int64_t per_split;  // points per split (multiple of kTile1)
+  int64_t nqb;        // query blocks of kBlock * qpl queries
+};
+Plan make_plan(int64_t N, int64_t Q, const pts_params* prm);
+
+// Error reporting (thread-local message, returned status).
+int fail(int code, const std::string& msg);
+int check_hip(hipError_t e, const char* what);
+
+// Kernel launchers (defined in the .hip files).
+int launch_build(const float* p, const float* n, const float* a, int64_t N, float kfloor_rel,
+                 void* rec, hipStream_t st);
+int launch_decode(const void* rec, int64_t N, float* out, hipStream_t st);
+constexpr int kStageFar = 1, kStageBlend = 2, kStageCombine = 4, kStageAll = 7;
+int launch_eval(const void* rec, int64_t N, const float* x, int64_t Q, float* sdf, float* grad,
+                float* stats, float C, const Plan& plan, void* ws, hipStream_t st, int stages);
+size_t eval_ws_bytes(const Plan& plan, int64_t Q);
+
+}  // namespace pts

@@ -1,0 +1,67 @@
+"""The C-ABI library loads on a CPU-only host and exports every symbol include/pts.h declares.
+
+Only host-side paths are exercised here (argument checks that return before
+any HIP call); compute calls need a GPU and live in the gpu-marked tests.
+"""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2607_16946_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared(header):
+    src = open(os.path.join(ROOT, "include", header)).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pts_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    return binding.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = _declared("pts.h")
+    assert "pts_eval" in names and "pts_cloud_build" in names
+    for name in names:
+        assert hasattr(L, name), name
+    # and the binding describes exactly those entry points
+    assert set(binding.SIGNATURES) == set(names)
+
+
+def test_version_and_sizes(L):
+    assert binding.version() >= 100
+    nb = binding.record_bytes(4096)
+    assert nb % 256 == 0 and nb >= 4096 * (16 + 80 + 4)
+    assert binding.eval_ws_bytes(4096, 0) == 0
+    assert binding.eval_ws_bytes(131072, 128 ** 3) >= 128 ** 3 * 12
+
+
+def test_host_side_errors(L):
+    out = ctypes.c_size_t(0)
+    assert L.pts_record_bytes(0, ctypes.byref(out)) == binding.PTS_EINVAL
+    assert b"N must be" in L.pts_last_error()
+    prm = binding.make_params()
+    # Q = 0 is a no-op, before any device work
+    assert L.pts_eval(None, 10, None, 0, None, None, None, ctypes.byref(prm), None, 0, None) == binding.PTS_OK
+    assert L.pts_eval(None, 0, None, 5, None, None, None, ctypes.byref(prm), None, 0, None) == binding.PTS_EINVAL
+    assert L.pts_eval(None, 10, None, 5, None, None, None, ctypes.byref(prm), None, 0, None) == binding.PTS_EINVAL
+    bad = binding.make_params(C=100.0)
+    assert L.pts_eval_ws_bytes(10, 10, ctypes.byref(bad), ctypes.byref(out)) == binding.PTS_EINVAL
+    bad = binding.make_params(splits=3)
+    assert L.pts_eval_ws_bytes(10, 10, ctypes.byref(bad), ctypes.byref(out)) == binding.PTS_EINVAL
+    assert L.pts_cloud_build(None, None, None, 10, None, None, 0, None) == binding.PTS_EINVAL
+
+
+def test_probe_library_exports():
+    path = os.path.join(ROOT, "paper_2607_16946_amd", "libpts_probe.so")
+    P = ctypes.CDLL(path)
+    P.ptsprobe_instr_per_lane.restype = ctypes.c_longlong
+    assert P.ptsprobe_instr_per_lane(0, 10) == 10 * 4 * 8
+    assert P.ptsprobe_instr_per_lane(5, 10) == 10 * 4 * 8 * 5
