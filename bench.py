@@ -37,18 +37,46 @@ BLEND_PLAIN, BLEND_FMA, BLEND_TRANS = 13, 11, 4
 BLEND_FLOP = BLEND_PLAIN + 2 * BLEND_FMA + BLEND_TRANS      # 39
 FAR_FLOP = 5 + 2 * 2                                         # 9
 
-# MI355X: 256 CUs x 4 SIMD x 16 lanes, 2.4 GHz peak engine clock.
-CUS, LANES_PER_CU, CLOCK_HZ = 256, 64, 2.4e9
-LANE_SLOTS = CUS * LANES_PER_CU * CLOCK_HZ                   # 3.93e13 VALU lane-instr/s
+# MI355X VALU unit counts at the 2.4 GHz peak engine clock (256 CUs):
+#  - FP32 add/mul/FMA: 128 lanes/clk/CU (two VALU issue ports per SIMD fed by
+#    different waves; the published 157.3 TFLOP/s FP32 vector peak);
+#  - transcendentals (sqrt, exp2, rcp): 32 lanes/clk/CU (a quarter of that);
+#  - the two share issue cycles (measured: in mixes their costs add).
+CUS, CLOCK_HZ = 256, 2.4e9
+ARITH_LANES_PER_CLK, TRANS_LANES_PER_CLK = 128, 32
 PUBLISHED_FP32_TFLOPS = 157.3
+# CU-cycles per blend pair at that peak, and the resulting pairs/s and FLOP/s
+BLEND_CYCLES = (BLEND_PLAIN + BLEND_FMA) / ARITH_LANES_PER_CLK + BLEND_TRANS / TRANS_LANES_PER_CLK
+PEAK_PAIRS = CUS * CLOCK_HZ / BLEND_CYCLES                   # 1.97e12 pairs/s
+PEAK_TFLOPS = BLEND_FLOP * PEAK_PAIRS / 1e12                 # 76.7 TFLOP/s
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_blend_mid_traffic.json")
+
+
+def measured_traffic():
+    """HBM bytes per k_blend launch from the committed counter summary, if it
+    was taken on the current kernel source (else None)."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    src = os.path.join(ROOT, "paper_2607_16946_amd", "csrc", "pts_eval.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    return rec.get("bytes_per_launch") if rec.get("pts_eval_sha256") == h else None
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def probe_issue_costs():
-    """Issue cost of v_exp_f32 / v_sqrt_f32 / v_rcp_f32 relative to v_fma_f32, and the shader clock."""
+PROBES = ((0, "fma_vop3_sgpr", 8192), (1, "exp", 2048), (2, "sqrt", 2048), (3, "rcp", 2048), (4, "max3", 8192),
+          (5, "exp_then_4fma", 1024), (6, "fmac_vop2", 8192), (7, "fma_vop3", 8192), (8, "add_vop2", 8192),
+          (9, "mul_vop2", 8192), (10, "exp_par_3fmac", 4096), (11, "sqrt_par_3fmac", 4096),
+          (12, "max_vop2", 8192), (13, "exp_par_7fmac", 4096), (14, "exp_par_14fmac", 2048), (15, "sub_vop2", 8192))
+
+
+def probe_issue_rates():
+    """Sustained lane-instructions/s of the VALU forms the kernels use, and the shader clock."""
     import torch
     path = os.path.join(ROOT, "paper_2607_16946_amd", "libpts_probe.so")
     P = ctypes.CDLL(path)
@@ -60,9 +88,8 @@ def probe_issue_costs():
     blocks = CUS * 8
     out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
     clk = torch.zeros(2, dtype=torch.int64, device="cuda")
-    rates, clock = {}, None
-    for op, name, iters in ((0, "fma", 8192), (1, "exp", 2048), (2, "sqrt", 2048), (3, "rcp", 2048),
-                            (5, "exp+4fma", 1024), (6, "sqrt+4fma", 1024)):
+    rates, clocks = {}, {}
+    for op, name, iters in PROBES:
         best = None
         for _ in range(3):
             ms = ctypes.c_float(0)
@@ -73,16 +100,10 @@ def probe_issue_costs():
             best = ms.value if best is None else min(best, ms.value)
         n = P.ptsprobe_instr_per_lane(op, iters) * blocks * 256
         rates[name] = n / (best * 1e-3)
-        if op == 0:
-            ticks = clk.cpu().tolist()
-            if ticks[1] > 0:
-                clock = ticks[0] / (ticks[1] / 100e6)
-    fma = rates["fma"]
-    tau = {k: fma / rates[k] for k in ("exp", "sqrt", "rcp")}
-    # mixes: slots of (1 trans + 4 fma) relative to 5 fma
-    tau["exp_in_mix"] = 5 * fma / rates["exp+4fma"] - 4
-    tau["sqrt_in_mix"] = 5 * fma / rates["sqrt+4fma"] - 4
-    return {"fma_lane_instr_per_s": fma, "tau": tau, "shader_clock_hz": clock, "rates": rates}
+        ticks = clk.cpu().tolist()
+        if ticks[1] > 0:
+            clocks[name] = ticks[0] / (ticks[1] / 100e6)
+    return {"lane_instr_per_s": rates, "shader_clock_hz": clocks}
 
 
 def cpu_baseline(cl, x, sample: int):
@@ -114,7 +135,18 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run one plain device copy of MIB MiB (calibrates the HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(args.copy_calibration * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 4}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU figures are not produced "
                                    "(queries shard across GPUs with no exchange; see the design notes)"}))
@@ -174,29 +206,26 @@ def main():
     probe = None
     if not args.no_probe:
         try:
-            probe = probe_issue_costs()
-            log(f"bench: probe tau {probe['tau']} clock {probe['shader_clock_hz']}")
-        except Exception as e:  # the roofline falls back to the documented quarter rate
+            probe = probe_issue_rates()
+            for k, v in probe["lane_instr_per_s"].items():
+                log(f"bench: probe {k:16s} {v:.4g} lane-instr/s  clock {probe['shader_clock_hz'].get(k, 0):.4g}")
+        except Exception as e:
             log(f"bench: probe failed: {e}")
-    tau_sqrt = probe["tau"]["sqrt"] if probe else 4.0
-    tau_exp = probe["tau"]["exp"] if probe else 4.0
-    # minimum VALU issue slots per blend pair for the algorithm's op mix
-    slots = BLEND_PLAIN + BLEND_FMA + 3 * tau_sqrt + tau_exp
-    peak_tflops = BLEND_FLOP * LANE_SLOTS / slots / 1e12
     achieved_tflops = BLEND_FLOP * pairs / (stage["blend"] * 1e-3) / 1e12
     roofline = {
         "bound": "alu", "unit": "TFLOP/s", "kernel": "k_blend (blend sweep)",
-        "achieved": achieved_tflops, "peak": peak_tflops, "frac": achieved_tflops / peak_tflops,
-        "traffic": None,
+        "achieved": achieved_tflops, "peak": PEAK_TFLOPS, "frac": achieved_tflops / PEAK_TFLOPS,
+        "traffic": measured_traffic(),
         "flop_per_pair": BLEND_FLOP, "pairs_per_launch": pairs, "launch_ms": stage["blend"],
-        "peak_basis": f"{CUS} CU x {LANES_PER_CU} lanes x {CLOCK_HZ / 1e9} GHz / ({BLEND_PLAIN}+{BLEND_FMA} "
-                      f"plain/FMA + 3x{tau_sqrt:.2f} sqrt + {tau_exp:.2f} exp issue slots per pair), "
-                      "no packed FP32",
+        "peak_basis": f"{CUS} CU x {CLOCK_HZ / 1e9} GHz / ({BLEND_PLAIN + BLEND_FMA} add/mul/FMA at "
+                      f"{ARITH_LANES_PER_CLK} lanes/clk + {BLEND_TRANS} sqrt/exp2 at {TRANS_LANES_PER_CLK} lanes/clk "
+                      f"per pair) = {PEAK_PAIRS:.3e} pairs/s x {BLEND_FLOP} FLOP",
         "frac_of_published_fp32": achieved_tflops / PUBLISHED_FP32_TFLOPS,
+        "far_sweep": {"ms": stage["far"], "flop_per_pair": FAR_FLOP,
+                      "tflops": FAR_FLOP * pairs / (stage["far"] * 1e-3) / 1e12},
     }
     if probe:
-        roofline["probe"] = {"tau": probe["tau"], "shader_clock_hz": probe["shader_clock_hz"],
-                             "fma_lane_instr_per_s": probe["fma_lane_instr_per_s"]}
+        roofline["probe"] = probe
     out = {
         "metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",

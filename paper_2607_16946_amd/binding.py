@@ -57,6 +57,8 @@ SIGNATURES = {
     "pts_cloud_build": (ctypes.c_int, [_P, _P, _P, _I64, ctypes.POINTER(Params), _P, _SZ, _P]),
     "pts_cloud_info_get": (ctypes.c_int, [_P, ctypes.POINTER(CloudInfo), _P]),
     "pts_cloud_decode": (ctypes.c_int, [_P, _I64, _P, _P]),
+    "pts_eval_plan": (ctypes.c_int, [_I64, _I64, ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_int),
+                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_I64)]),
     "pts_eval_ws_bytes": (ctypes.c_int, [_I64, _I64, ctypes.POINTER(Params), ctypes.POINTER(_SZ)]),
     "pts_eval": (ctypes.c_int, [_P, _I64, _P, _I64, _P, _P, _P, ctypes.POINTER(Params), _P, _SZ, _P]),
     "pts_eval_far": (ctypes.c_int, [_P, _I64, _P, _I64, ctypes.POINTER(Params), _P, _SZ, _P]),
@@ -152,6 +154,14 @@ def cloud_decode(rec: torch.Tensor, N: int) -> torch.Tensor:
     out = torch.empty((N, 12), dtype=torch.float32, device=rec.device)
     _check(lib().pts_cloud_decode(_ptr(rec), int(N), _ptr(out), _stream()))
     return out
+
+
+def eval_plan(N: int, Q: int, params: Params | None = None) -> tuple[int, int, int]:
+    """(queries per lane, point splits, points per split) of pts_eval for N points, Q queries."""
+    q, s, ps = ctypes.c_int(0), ctypes.c_int(0), _I64(0)
+    prm = params if params is not None else make_params()
+    _check(lib().pts_eval_plan(int(N), int(Q), ctypes.byref(prm), ctypes.byref(q), ctypes.byref(s), ctypes.byref(ps)))
+    return q.value, s.value, ps.value
 
 
 def eval_ws_bytes(N: int, Q: int, params: Params | None = None) -> int:

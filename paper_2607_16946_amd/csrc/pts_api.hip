@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -50,6 +51,10 @@ Plan make_plan(int64_t N, int64_t Q, const pts_params* prm) {
   Plan p;
   // queries per lane: 4 once there are enough queries to fill the device
   p.qpl = Q >= 4 * 256 * kBlock ? 4 : (Q >= 2 * 64 * kBlock ? 2 : 1);
+  if (const char* e = std::getenv("PTS_QPL")) {  // tuning knob: 1, 2, 4 or 8
+    const int v = std::atoi(e);
+    if (v == 1 || v == 2 || v == 4 || v == 8) p.qpl = v;
+  }
   p.nqb = (Q + int64_t(kBlock) * p.qpl - 1) / (int64_t(kBlock) * p.qpl);
   const int64_t tiles = (N + kTile1 - 1) / kTile1;
   int S;
@@ -62,11 +67,12 @@ Plan make_plan(int64_t N, int64_t Q, const pts_params* prm) {
     while (S < 8 && tiles >= int64_t(2) * S * 2) S *= 2;
     while (S < 64 && p.nqb * S < 2048 && tiles >= int64_t(2) * S * 2) S *= 2;
   }
+  S = int(std::max<int64_t>(1, std::min<int64_t>(S, tiles)));
   const int64_t tiles_per = (tiles + S - 1) / S;
-  p.per_split = std::max<int64_t>(1, tiles_per) * kTile1;
-  // drop empty trailing splits
-  while (S > 1 && int64_t(S - 1) * p.per_split >= N) S /= 2;
-  p.S = S;
+  p.per_split = tiles_per * kTile1;
+  // splits that would start past the last point are dropped; the remaining
+  // S * per_split >= N cover every point
+  p.S = int((N + p.per_split - 1) / p.per_split);
   return p;
 }
 
@@ -131,6 +137,18 @@ int pts_cloud_decode(const void* rec, int64_t N, float* out, void* stream) {
   if (!rec || !out) return fail(PTS_EINVAL, "null pointer");
   if (N < 1) return fail(PTS_EINVAL, "N must be >= 1");
   return launch_decode(rec, N, out, static_cast<hipStream_t>(stream));
+}
+
+int pts_eval_plan(int64_t N, int64_t Q, const pts_params* prm, int* qpl, int* splits, int64_t* per_split) {
+  if (!qpl || !splits || !per_split) return fail(PTS_EINVAL, "null pointer");
+  if (N < 1 || Q < 1) return fail(PTS_EINVAL, "N and Q must be >= 1");
+  const pts_params P = resolve(prm);
+  if (int rc = check_params(P)) return rc;
+  const Plan plan = make_plan(N, Q, &P);
+  *qpl = plan.qpl;
+  *splits = plan.S;
+  *per_split = plan.per_split;
+  return PTS_OK;
 }
 
 int pts_eval_ws_bytes(int64_t N, int64_t Q, const pts_params* prm, size_t* out_bytes) {

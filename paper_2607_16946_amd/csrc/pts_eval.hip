@@ -172,6 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_blend(const Header* __restrict__ h, 
     num[k] = 0.f;
     den[k] = 0.f;
   }
+  const float c2 = C2;
   const int64_t beg = int64_t(split) * per_split;
   const int64_t end = min(N, beg + per_split);
   for (int64_t t0 = beg; t0 < end; t0 += kTile2) {
@@ -190,7 +191,7 @@ __global__ __launch_bounds__(kBlock) void k_blend(const Header* __restrict__ h, 
       for (int k = 0; k < QPL; ++k) {
         const float dx = qx[k] - P.x, dy = qy[k] - P.y, dz = qz[k] - P.z;
         const float d = hw_sqrt(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
-        const float w = hw_exp2(fmaf(d, nl[k], C2));
+        const float w = hw_exp2(fmaf(d, nl[k], c2));
         const float g = g_direct(qx[k], qy[k], qz[k], U, Mv, K, G);
         tn[k] = fmaf(w, g, tn[k]);
         td[k] += w;
@@ -203,7 +204,7 @@ __global__ __launch_bounds__(kBlock) void k_blend(const Header* __restrict__ h, 
       for (int k = 0; k < QPL; ++k) {
         const float dx = qx[k] - P.x, dy = qy[k] - P.y, dz = qz[k] - P.z;
         const float d = hw_sqrt(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
-        const float w = hw_exp2(fmaf(d, nl[k], C2));
+        const float w = hw_exp2(fmaf(d, nl[k], c2));
         const float g = g_anchored(qx[k], qy[k], qz[k], P.w, U, Mv, K, G);
         tn[k] = fmaf(w, g, tn[k]);
         td[k] += w;
@@ -275,6 +276,7 @@ int launch_eval(const void* rec, int64_t N, const float* x, int64_t Q, float* sd
   switch (plan.qpl) {
     case 1: launch_sweeps<1>(h, pos4, recs, x, Q, plan, far2, part, C2, st, stages); break;
     case 2: launch_sweeps<2>(h, pos4, recs, x, Q, plan, far2, part, C2, st, stages); break;
+    case 8: launch_sweeps<8>(h, pos4, recs, x, Q, plan, far2, part, C2, st, stages); break;
     default: launch_sweeps<4>(h, pos4, recs, x, Q, plan, far2, part, C2, st, stages); break;
   }
   if (stages & kStageCombine)

@@ -65,3 +65,19 @@ def test_probe_library_exports():
     P.ptsprobe_instr_per_lane.restype = ctypes.c_longlong
     assert P.ptsprobe_instr_per_lane(0, 10) == 10 * 4 * 8
     assert P.ptsprobe_instr_per_lane(5, 10) == 10 * 4 * 8 * 5
+
+
+def test_plan_covers_every_point():
+    rng = __import__("numpy").random.default_rng(0)
+    Ns = [1, 2, 511, 512, 513, 4096, 5000, 8192, 20000, 131072, 262144, 1 << 20] + list(rng.integers(1, 3_000_000, 40))
+    Qs = [1, 7, 1000, 1728, 4096, 70001, 128 ** 3, 1 << 20]
+    for N in Ns:
+        for Q in Qs:
+            for S in (0, 1, 2, 8, 32, 64):
+                qpl, splits, per = binding.eval_plan(int(N), Q, binding.make_params(splits=S))
+                assert qpl in (1, 2, 4)
+                assert per % 512 == 0 and per > 0
+                assert splits >= 1 and splits * per >= N, (N, Q, S, splits, per)
+                assert (splits - 1) * per < N, (N, Q, S, splits, per)     # no empty split
+                if S:
+                    assert splits <= S
