@@ -137,8 +137,12 @@ int pts_cloud_decode(const void* rec, int64_t N, float* out, void* stream);
 int pts_eval_plan(int64_t N, int64_t Q, const pts_params* prm, int* qpl, int* splits,
                   int64_t* per_split);
 
-/* Scratch bytes pts_eval needs for N points and Q queries (given params). */
+/* Scratch bytes pts_eval needs for N points and Q queries (given params), when
+ * no gradient is requested. */
 int pts_eval_ws_bytes(int64_t N, int64_t Q, const pts_params* prm, size_t* out_bytes);
+
+/* Scratch bytes for pts_eval with a gradient output and for pts_grad_x. */
+int pts_grad_ws_bytes(int64_t N, int64_t Q, const pts_params* prm, size_t* out_bytes);
 
 /* phi at Q queries.
  *   rec         device, built by pts_cloud_build for the same N.
@@ -146,33 +150,67 @@ int pts_eval_ws_bytes(int64_t N, int64_t Q, const pts_params* prm, size_t* out_b
  *   sdf [Q]     device float32 output phi(x).
  *   grad [Q,3]  device float32 output grad phi(x), or NULL.  The gradient is
  *               the exact derivative of phi including the dependence of
- *               lambda_x on x (App. D holds lambda fixed; the extra term is
- *               (2C/M^2) e_* sum_i (w_i/W)(g_i - phi) d_i with M the largest
- *               distance and e_* the unit vector from that point to x).
- *   stats [Q,3] device float32 output (M, W, phi) or NULL: M = max_i |x-p_i|,
- *               W = sum_i 2^(C log2(e) - lambda_x log2(e) |x - p_i|) (the shifted
- *               weight sum of Eq. BasicFormulaShifted).  Used by the backward calls.
+ *               lambda_x on x: App. D holds lambda fixed; the extra term is
+ *               (2C/M^2) e_* (1/W) sum_i w_i (g_i - phi) d_i, with M the largest
+ *               distance and e_* the unit vector from that farthest point to x.
+ *               Where a torus SDF is not differentiable (its axis, its core
+ *               circle) and at a query on a point, the undefined factor is 0.
+ *               Requires ws_bytes >= pts_grad_ws_bytes(N, Q, prm).
+ *   stats [Q,6] device float32 output or NULL: (M, W, phi, e_*) with
+ *               M = max_i |x - p_i|, W = sum_i exp(-lambda_x(|x-p_i| - sigma_x))
+ *               (the shifted weight sum of Eq. BasicFormulaShifted), phi, and
+ *               e_* as above.  The input of pts_grad_x.
  *   ws          device scratch of ws_bytes >= pts_eval_ws_bytes(N, Q, prm).
  * A query with a NaN or infinite coordinate gives NaN.  Q = 0 is a no-op. */
 int pts_eval(const void* rec, int64_t N, const float* x, int64_t Q, float* sdf, float* grad,
              float* stats, const pts_params* prm, void* ws, size_t ws_bytes, void* stream);
 
-/* The three launches of pts_eval as separate calls, with the same arguments
- * and workspace, for callers that time or schedule them individually
- * (pts_eval is exactly these three in order):
+/* The three launches of pts_eval without gradient or statistics as separate
+ * calls, with the same arguments and workspace, for callers that time or
+ * schedule them individually (pts_eval is exactly these three in order):
  *   pts_eval_far      farthest-point sweep: M = max_i |x - p_i| per query and
  *                     point split (Eq. RelationshipBetweenLambdaAndRadius);
  *   pts_eval_blend    weighted sweep: per split, sum_i w_i g_i and sum_i w_i
  *                     (Eq. BasicFormulaShifted); needs pts_eval_far's output;
- *   pts_eval_combine  fixed-order sum over splits, phi = num / den, and the
- *                     optional (M, W, phi) statistics.
+ *   pts_eval_combine  fixed-order sum over splits, phi = num / den.
  * Errors as pts_eval. */
 int pts_eval_far(const void* rec, int64_t N, const float* x, int64_t Q, const pts_params* prm,
                  void* ws, size_t ws_bytes, void* stream);
 int pts_eval_blend(const void* rec, int64_t N, const float* x, int64_t Q, const pts_params* prm,
                    void* ws, size_t ws_bytes, void* stream);
-int pts_eval_combine(int64_t N, int64_t Q, float* sdf, float* stats, const pts_params* prm,
-                     void* ws, size_t ws_bytes, void* stream);
+int pts_eval_combine(int64_t N, int64_t Q, float* sdf, const pts_params* prm, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/* Backward with respect to the queries (App. D and the lambda_x term):
+ * gx[q] = gout[q] * grad phi(x_q), from the statistics a pts_eval call wrote
+ * for the same queries.  gout [Q] may be NULL (then 1).  Re-sweeps all points
+ * once.  ws_bytes >= pts_grad_ws_bytes(N, Q, prm). */
+int pts_grad_x(const void* rec, int64_t N, const float* x, int64_t Q, const float* gout,
+               const float* stats, float* gx, const pts_params* prm, void* ws, size_t ws_bytes,
+               void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Backward with respect to the per-point coefficients (the representation is
+ * differentiable, Sec. 6): ga[i] = dL/da_i for L = sum_q gout[q] phi(x_q).
+ * ------------------------------------------------------------------------- */
+
+/* Scratch bytes for pts_backward_params. */
+int pts_backward_ws_bytes(int64_t N, int64_t Q, const pts_params* prm, size_t* out_bytes);
+
+/* dL/da [N,6] (device float32, the caller's point order and coefficient order
+ * (a00, a01, a10, a11, a02, a20)).
+ *   rec, p, n, a  the record and the inputs it was built from (device);
+ *   x [Q,3]       queries; stats [Q,6] from pts_eval at the same queries;
+ *   gout [Q]      upstream gradient dL/dphi (NULL = 1).
+ * The weights of Eq. (BasicFormulaShifted) do not depend on a, so
+ * dL/da_i = sum_q gout_q (w_qi/W_q) dg_i(x_q)/da_i: a point-major sweep
+ * accumulates dL/d(c, u, R, r) per point and an FP64 chain rule through the
+ * torus fit of Sec. 4.1 maps it to a.  Derivatives through a floored
+ * curvature are 0, and at umbilics d sqrt(H^2 - K) is taken as 0.  A NaN query
+ * makes every point's gradient NaN.  Deterministic (fixed-order reductions). */
+int pts_backward_params(const void* rec, int64_t N, const float* p, const float* n, const float* a,
+                        const float* x, int64_t Q, const float* gout, const float* stats, float* ga,
+                        const pts_params* prm, void* ws, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

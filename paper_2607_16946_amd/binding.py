@@ -63,7 +63,12 @@ SIGNATURES = {
     "pts_eval": (ctypes.c_int, [_P, _I64, _P, _I64, _P, _P, _P, ctypes.POINTER(Params), _P, _SZ, _P]),
     "pts_eval_far": (ctypes.c_int, [_P, _I64, _P, _I64, ctypes.POINTER(Params), _P, _SZ, _P]),
     "pts_eval_blend": (ctypes.c_int, [_P, _I64, _P, _I64, ctypes.POINTER(Params), _P, _SZ, _P]),
-    "pts_eval_combine": (ctypes.c_int, [_I64, _I64, _P, _P, ctypes.POINTER(Params), _P, _SZ, _P]),
+    "pts_eval_combine": (ctypes.c_int, [_I64, _I64, _P, ctypes.POINTER(Params), _P, _SZ, _P]),
+    "pts_grad_ws_bytes": (ctypes.c_int, [_I64, _I64, ctypes.POINTER(Params), ctypes.POINTER(_SZ)]),
+    "pts_grad_x": (ctypes.c_int, [_P, _I64, _P, _I64, _P, _P, _P, ctypes.POINTER(Params), _P, _SZ, _P]),
+    "pts_backward_ws_bytes": (ctypes.c_int, [_I64, _I64, ctypes.POINTER(Params), ctypes.POINTER(_SZ)]),
+    "pts_backward_params": (ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _I64, _P, _P, _P, ctypes.POINTER(Params), _P,
+                                           _SZ, _P]),
 }
 
 
@@ -171,16 +176,23 @@ def eval_ws_bytes(N: int, Q: int, params: Params | None = None) -> int:
     return int(out.value)
 
 
+def grad_ws_bytes(N: int, Q: int, params: Params | None = None) -> int:
+    out = _SZ(0)
+    prm = params if params is not None else make_params()
+    _check(lib().pts_grad_ws_bytes(int(N), int(Q), ctypes.byref(prm), ctypes.byref(out)))
+    return int(out.value)
+
+
 def eval(rec: torch.Tensor, N: int, x: torch.Tensor, params: Params | None = None, grad: bool = False,
          stats: bool = False, ws: torch.Tensor | None = None, out: torch.Tensor | None = None):
-    """phi(x) at queries x [Q,3] (Sec. 4.2); optionally grad phi [Q,3] and (M, W, phi) [Q,3]."""
+    """phi(x) at queries x [Q,3] (Sec. 4.2); optionally grad phi [Q,3] and (M, W, phi, e_*) [Q,6]."""
     _dev(x, "x", 3)
     Q = x.shape[0]
     prm = params if params is not None else make_params()
     sdf = out if out is not None else torch.empty(Q, dtype=torch.float32, device=x.device)
     g = torch.empty((Q, 3), dtype=torch.float32, device=x.device) if grad else None
-    st = torch.empty((Q, 3), dtype=torch.float32, device=x.device) if stats else None
-    need = eval_ws_bytes(N, Q, prm)
+    st = torch.empty((Q, 6), dtype=torch.float32, device=x.device) if stats else None
+    need = grad_ws_bytes(N, Q, prm) if grad else eval_ws_bytes(N, Q, prm)
     if ws is None or ws.numel() < need:
         ws = torch.empty(max(need, 256), dtype=torch.uint8, device=x.device)
     _check(lib().pts_eval(_ptr(rec), int(N), _ptr(x), Q, _ptr(sdf), _ptr(g), _ptr(st), ctypes.byref(prm), _ptr(ws),
@@ -193,6 +205,26 @@ def eval(rec: torch.Tensor, N: int, x: torch.Tensor, params: Params | None = Non
     return res[0] if len(res) == 1 else tuple(res)
 
 
+def grad_x(rec: torch.Tensor, N: int, x: torch.Tensor, stats: torch.Tensor, gout: torch.Tensor | None = None,
+           params: Params | None = None, ws: torch.Tensor | None = None) -> torch.Tensor:
+    """gout * grad phi(x) [Q,3] from the statistics of a previous eval at the same queries."""
+    _dev(x, "x", 3)
+    _dev(stats, "stats", 6)
+    Q = x.shape[0]
+    if gout is not None:
+        _dev(gout, "gout")
+        if gout.numel() != Q:
+            raise ValueError("gout must have one value per query")
+    prm = params if params is not None else make_params()
+    gx = torch.empty((Q, 3), dtype=torch.float32, device=x.device)
+    need = grad_ws_bytes(N, Q, prm)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device=x.device)
+    _check(lib().pts_grad_x(_ptr(rec), int(N), _ptr(x), Q, _ptr(gout), _ptr(stats), _ptr(gx), ctypes.byref(prm),
+                            _ptr(ws), ws.numel(), _stream()))
+    return gx
+
+
 def eval_far(rec, N: int, x: torch.Tensor, params: Params, ws: torch.Tensor) -> None:
     _check(lib().pts_eval_far(_ptr(rec), int(N), _ptr(x), x.shape[0], ctypes.byref(params), _ptr(ws), ws.numel(),
                               _stream()))
@@ -203,10 +235,39 @@ def eval_blend(rec, N: int, x: torch.Tensor, params: Params, ws: torch.Tensor) -
                                 ws.numel(), _stream()))
 
 
-def eval_combine(N: int, Q: int, sdf: torch.Tensor, params: Params, ws: torch.Tensor,
-                 stats: torch.Tensor | None = None) -> None:
-    _check(lib().pts_eval_combine(int(N), int(Q), _ptr(sdf), _ptr(stats), ctypes.byref(params), _ptr(ws),
-                                  ws.numel(), _stream()))
+def eval_combine(N: int, Q: int, sdf: torch.Tensor, params: Params, ws: torch.Tensor) -> None:
+    _check(lib().pts_eval_combine(int(N), int(Q), _ptr(sdf), ctypes.byref(params), _ptr(ws), ws.numel(), _stream()))
+
+
+def backward_ws_bytes(N: int, Q: int, params: Params | None = None) -> int:
+    out = _SZ(0)
+    prm = params if params is not None else make_params()
+    _check(lib().pts_backward_ws_bytes(int(N), int(Q), ctypes.byref(prm), ctypes.byref(out)))
+    return int(out.value)
+
+
+def backward_params(rec: torch.Tensor, p: torch.Tensor, n: torch.Tensor, a: torch.Tensor, x: torch.Tensor,
+                    stats: torch.Tensor, gout: torch.Tensor | None = None, params: Params | None = None,
+                    ws: torch.Tensor | None = None) -> torch.Tensor:
+    """dL/da [N,6] for L = sum_q gout_q phi(x_q), from the statistics of an eval at x."""
+    _dev(p, "p", 3)
+    _dev(n, "n", 3)
+    _dev(a, "a", 6)
+    _dev(x, "x", 3)
+    _dev(stats, "stats", 6)
+    N, Q = p.shape[0], x.shape[0]
+    if gout is not None:
+        _dev(gout, "gout")
+        if gout.numel() != Q:
+            raise ValueError("gout must have one value per query")
+    prm = params if params is not None else make_params()
+    ga = torch.empty((N, 6), dtype=torch.float32, device=p.device)
+    need = backward_ws_bytes(N, Q, prm)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device=p.device)
+    _check(lib().pts_backward_params(_ptr(rec), N, _ptr(p), _ptr(n), _ptr(a), _ptr(x), Q, _ptr(gout), _ptr(stats),
+                                     _ptr(ga), ctypes.byref(prm), _ptr(ws), ws.numel(), _stream()))
+    return ga
 
 
 class Cloud:
@@ -216,6 +277,7 @@ class Cloud:
                  kfloor_rel: float = 1e-6, splits: int = 0):
         self.params = make_params(C, kfloor_rel, splits)
         self.N = int(p.shape[0])
+        self.p, self.n, self.a = p, n, a
         self.rec = cloud_build(p, n, a, self.params)
         self._ws = None
 
@@ -226,7 +288,7 @@ class Cloud:
         return cloud_decode(self.rec, self.N)
 
     def __call__(self, x: torch.Tensor, grad: bool = False, stats: bool = False):
-        need = eval_ws_bytes(self.N, x.shape[0], self.params)
+        need = (grad_ws_bytes if grad else eval_ws_bytes)(self.N, x.shape[0], self.params)
         if self._ws is None or self._ws.numel() < need:
             self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device=x.device)
         return eval(self.rec, self.N, x, self.params, grad=grad, stats=stats, ws=self._ws)

@@ -160,42 +160,116 @@ int pts_eval_ws_bytes(int64_t N, int64_t Q, const pts_params* prm, size_t* out_b
   return PTS_OK;
 }
 
-namespace {
-int eval_common(const void* rec, int64_t N, const float* x, int64_t Q, float* sdf, float* grad, float* stats,
-                const pts_params* prm, void* ws, size_t ws_bytes, void* stream, int stages) {
+int pts_grad_ws_bytes(int64_t N, int64_t Q, const pts_params* prm, size_t* out_bytes) {
+  if (!out_bytes) return fail(PTS_EINVAL, "out_bytes is NULL");
   if (N < 1 || Q < 0) return fail(PTS_EINVAL, "N must be >= 1 and Q >= 0");
-  if (Q == 0) return PTS_OK;
-  if (!ws) return fail(PTS_EINVAL, "null workspace");
-  if ((stages & (kStageFar | kStageBlend)) && (!rec || !x)) return fail(PTS_EINVAL, "null record or queries");
-  if ((stages & kStageCombine) && !sdf) return fail(PTS_EINVAL, "null output");
-  if (Q > (int64_t(1) << 31) - 1) return fail(PTS_EINVAL, "Q must be < 2^31");
   const pts_params P = resolve(prm);
   if (int rc = check_params(P)) return rc;
-  const Plan plan = make_plan(N, Q, &P);
-  if (ws_bytes < eval_ws_bytes(plan, Q)) return fail(PTS_EINVAL, "workspace too small");
-  if (grad) return fail(PTS_EINVAL, "gradient output is not available in this build");
-  return launch_eval(rec, N, x, Q, sdf, grad, stats, P.C, plan, ws, static_cast<hipStream_t>(stream), stages);
+  *out_bytes = Q == 0 ? 0 : grad_ws_bytes(make_plan(N, Q, &P), Q);
+  return PTS_OK;
+}
+
+namespace {
+// Common checks; on success *plan and *P are set.  need_grad_ws selects the
+// workspace size that the call requires.
+int eval_checks(int64_t N, int64_t Q, const pts_params* prm, size_t ws_bytes, bool need_grad_ws, Plan* plan,
+                pts_params* P) {
+  if (N < 1 || Q < 0) return fail(PTS_EINVAL, "N must be >= 1 and Q >= 0");
+  if (Q > (int64_t(1) << 31) - 1) return fail(PTS_EINVAL, "Q must be < 2^31");
+  *P = resolve(prm);
+  if (int rc = check_params(*P)) return rc;
+  if (Q == 0) return PTS_OK;
+  *plan = make_plan(N, Q, P);
+  const size_t need = need_grad_ws ? grad_ws_bytes(*plan, Q) : eval_ws_bytes(*plan, Q);
+  if (ws_bytes < need) return fail(PTS_EINVAL, "workspace too small");
+  return PTS_OK;
 }
 }  // namespace
 
 int pts_eval(const void* rec, int64_t N, const float* x, int64_t Q, float* sdf, float* grad, float* stats,
              const pts_params* prm, void* ws, size_t ws_bytes, void* stream) {
-  return eval_common(rec, N, x, Q, sdf, grad, stats, prm, ws, ws_bytes, stream, kStageAll);
+  Plan plan;
+  pts_params P;
+  if (int rc = eval_checks(N, Q, prm, ws_bytes, grad != nullptr, &plan, &P)) return rc;
+  if (Q == 0) return PTS_OK;
+  if (!rec || !x || !sdf || !ws) return fail(PTS_EINVAL, "null pointer");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const WsView v = ws_view(plan, Q, ws);
+  if (!grad && !stats) {
+    if (int rc = launch_far(rec, N, x, Q, plan, v, st)) return rc;
+    if (int rc = launch_blend(rec, N, x, Q, P.C, plan, v, st)) return rc;
+    return launch_combine(Q, plan, v, sdf, st);
+  }
+  float* st6 = stats ? stats : v.stats;
+  if (int rc = launch_far_arg(rec, N, x, Q, plan, v, st)) return rc;
+  if (int rc = launch_blend(rec, N, x, Q, P.C, plan, v, st)) return rc;
+  if (int rc = launch_combine_stats(rec, N, x, Q, plan, v, sdf, st6, st)) return rc;
+  if (grad) return launch_grad(rec, N, x, Q, st6, nullptr, grad, P.C, plan, v, st);
+  return PTS_OK;
 }
 
 int pts_eval_far(const void* rec, int64_t N, const float* x, int64_t Q, const pts_params* prm, void* ws,
                  size_t ws_bytes, void* stream) {
-  return eval_common(rec, N, x, Q, nullptr, nullptr, nullptr, prm, ws, ws_bytes, stream, kStageFar);
+  Plan plan;
+  pts_params P;
+  if (int rc = eval_checks(N, Q, prm, ws_bytes, false, &plan, &P)) return rc;
+  if (Q == 0) return PTS_OK;
+  if (!rec || !x || !ws) return fail(PTS_EINVAL, "null pointer");
+  return launch_far(rec, N, x, Q, plan, ws_view(plan, Q, ws), static_cast<hipStream_t>(stream));
 }
 
 int pts_eval_blend(const void* rec, int64_t N, const float* x, int64_t Q, const pts_params* prm, void* ws,
                    size_t ws_bytes, void* stream) {
-  return eval_common(rec, N, x, Q, nullptr, nullptr, nullptr, prm, ws, ws_bytes, stream, kStageBlend);
+  Plan plan;
+  pts_params P;
+  if (int rc = eval_checks(N, Q, prm, ws_bytes, false, &plan, &P)) return rc;
+  if (Q == 0) return PTS_OK;
+  if (!rec || !x || !ws) return fail(PTS_EINVAL, "null pointer");
+  return launch_blend(rec, N, x, Q, P.C, plan, ws_view(plan, Q, ws), static_cast<hipStream_t>(stream));
 }
 
-int pts_eval_combine(int64_t N, int64_t Q, float* sdf, float* stats, const pts_params* prm, void* ws,
-                     size_t ws_bytes, void* stream) {
-  return eval_common(nullptr, N, nullptr, Q, sdf, nullptr, stats, prm, ws, ws_bytes, stream, kStageCombine);
+int pts_eval_combine(int64_t N, int64_t Q, float* sdf, const pts_params* prm, void* ws, size_t ws_bytes,
+                     void* stream) {
+  Plan plan;
+  pts_params P;
+  if (int rc = eval_checks(N, Q, prm, ws_bytes, false, &plan, &P)) return rc;
+  if (Q == 0) return PTS_OK;
+  if (!sdf || !ws) return fail(PTS_EINVAL, "null pointer");
+  return launch_combine(Q, plan, ws_view(plan, Q, ws), sdf, static_cast<hipStream_t>(stream));
+}
+
+int pts_grad_x(const void* rec, int64_t N, const float* x, int64_t Q, const float* gout, const float* stats,
+               float* gx, const pts_params* prm, void* ws, size_t ws_bytes, void* stream) {
+  Plan plan;
+  pts_params P;
+  if (int rc = eval_checks(N, Q, prm, ws_bytes, true, &plan, &P)) return rc;
+  if (Q == 0) return PTS_OK;
+  if (!rec || !x || !stats || !gx || !ws) return fail(PTS_EINVAL, "null pointer");
+  return launch_grad(rec, N, x, Q, stats, gout, gx, P.C, plan, ws_view(plan, Q, ws),
+                     static_cast<hipStream_t>(stream));
+}
+
+int pts_backward_ws_bytes(int64_t N, int64_t Q, const pts_params* prm, size_t* out_bytes) {
+  if (!out_bytes) return fail(PTS_EINVAL, "out_bytes is NULL");
+  if (N < 1 || Q < 0) return fail(PTS_EINVAL, "N must be >= 1 and Q >= 0");
+  const pts_params P = resolve(prm);
+  if (int rc = check_params(P)) return rc;
+  *out_bytes = back_ws_bytes(N, Q == 0 ? 1 : Q);
+  return PTS_OK;
+}
+
+int pts_backward_params(const void* rec, int64_t N, const float* p, const float* n, const float* a,
+                        const float* x, int64_t Q, const float* gout, const float* stats, float* ga,
+                        const pts_params* prm, void* ws, size_t ws_bytes, void* stream) {
+  if (N < 1 || Q < 0) return fail(PTS_EINVAL, "N must be >= 1 and Q >= 0");
+  if (Q > (int64_t(1) << 31) - 1) return fail(PTS_EINVAL, "Q must be < 2^31");
+  if (!rec || !p || !n || !a || !ga || !ws) return fail(PTS_EINVAL, "null pointer");
+  if (Q > 0 && (!x || !stats)) return fail(PTS_EINVAL, "null queries or statistics");
+  const pts_params P = resolve(prm);
+  if (int rc = check_params(P)) return rc;
+  if (ws_bytes < back_ws_bytes(N, Q == 0 ? 1 : Q)) return fail(PTS_EINVAL, "workspace too small");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  return launch_backward(rec, N, p, n, a, x, Q, gout, stats, ga, P.C, ws, st);
 }
 
 }  // extern "C"

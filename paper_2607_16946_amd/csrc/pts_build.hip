@@ -24,6 +24,7 @@
 // <x-c,m> = <x,m> - <c,m> = (<x,m> - <o,m>) + L.
 
 #include "pts_internal.h"
+#include "pts_fit.h"
 
 #include <cmath>
 
@@ -57,6 +58,7 @@ __global__ void k_init(Header* h, int64_t N) {
   h->lmax_direct = 0.f;
   h->status = 0;
   h->pad0 = 0;
+  h->kfloor64 = 0.0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_bbox(const float* __restrict__ p, const float* __restrict__ n,
@@ -114,90 +116,9 @@ __device__ inline BoxInfo box_info(const Header* h, float kfloor_rel) {
   return b;
 }
 
-// Torus of one point, FP64 (Sec. 4.1; App. C for the fundamental forms).
-struct Fit {
-  double c[3], u[3], m[3], k[3], o[3];
-  double L, R, r, zeta, sgn;
-};
+__device__ inline double clampmag(double k, double floor_) { return floor_mag<double>(k, floor_); }
 
-__device__ inline double clampmag(double k, double floor_) {
-  // |kappa| <- max(|kappa|, floor), sign kept, sign(0) = -1
-  if (fabs(k) >= floor_) return k;
-  return k > 0.0 ? floor_ : -floor_;
-}
-
-__device__ Fit fit_one(const float* pp, const float* nn, const float* aa, double kfloor) {
-  Fit F;
-  const double a00 = aa[0], a01 = aa[1], a10 = aa[2], a11 = aa[3], a02 = aa[4], a20 = aa[5];
-  // unit normal and the fixed frame (s, t, n)
-  double n0 = nn[0], n1 = nn[1], n2 = nn[2];
-  double nl = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
-  n0 /= nl; n1 /= nl; n2 /= nl;
-  double ex = fabs(n0) < 0.9 ? 1.0 : 0.0;
-  double ey = 1.0 - ex;
-  double en = ex * n0 + ey * n1;
-  double s0 = ex - en * n0, s1 = ey - en * n1, s2 = -en * n2;
-  double sl = sqrt(s0 * s0 + s1 * s1 + s2 * s2);
-  s0 /= sl; s1 /= sl; s2 /= sl;
-  double t0 = n1 * s2 - n2 * s1, t1 = n2 * s0 - n0 * s2, t2 = n0 * s1 - n1 * s0;
-
-  // mean and Gaussian curvature of the height polynomial at (0,0)
-  const double E = 1.0 + a10 * a10, G = 1.0 + a01 * a01, Fm = a10 * a01;
-  const double A = sqrt(1.0 + a01 * a01 + a10 * a10);
-  const double H = (a02 * E + a20 * G - a11 * Fm) / (A * A * A);
-  const double K = (4.0 * a02 * a20 - a11 * a11) / (A * A * A * A);
-  const double root = sqrt(fmax(H * H - K, 0.0));
-  const double kp = H + root, km = H - root;
-  const bool plus_is_min = fabs(kp) < fabs(km);
-  const double kmin = plus_is_min ? kp : km;
-  const double kmax = plus_is_min ? km : kp;
-
-  // principal direction of kappa_min: rows of (II - kappa I) w = 0, longer one
-  double r1x = kmin * Fm * A - a11, r1y = 2.0 * a20 - kmin * E * A;
-  double r2x = 2.0 * a02 - kmin * G * A, r2y = kmin * Fm * A - a11;
-  double q1 = r1x * r1x + r1y * r1y, q2 = r2x * r2x + r2y * r2y;
-  double wx = r1x, wy = r1y, qw = q1;
-  if (q2 > q1) { wx = r2x; wy = r2y; qw = q2; }
-  double scale = fabs(a11) + 2.0 * fabs(a20) + 2.0 * fabs(a02) + fabs(kmin) * A * (1.0 + a10 * a10 + a01 * a01);
-  double v0, v1, v2;
-  if (sqrt(qw) > 1e-12 * scale) {
-    v0 = wx * (s0 + a10 * n0) + wy * (t0 + a01 * n0);
-    v1 = wx * (s1 + a10 * n1) + wy * (t1 + a01 * n1);
-    v2 = wx * (s2 + a10 * n2) + wy * (t2 + a01 * n2);
-    double vl = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
-    v0 /= vl; v1 /= vl; v2 /= vl;
-  } else {  // umbilic: any tangent direction
-    v0 = s0; v1 = s1; v2 = s2;
-  }
-
-  // polynomial normal n*(0,0)
-  double ns0 = (n0 - a10 * s0 - a01 * t0) / A;
-  double ns1 = (n1 - a10 * s1 - a01 * t1) / A;
-  double ns2 = (n2 - a10 * s2 - a01 * t2) / A;
-
-  const double kminf = clampmag(kmin, kfloor), kmaxf = clampmag(kmax, kfloor);
-  F.L = 1.0 / fabs(kminf);
-  F.r = 1.0 / fabs(kmaxf);
-  F.zeta = (kminf * kmaxf > 0.0) ? 1.0 : -1.0;
-  F.R = F.L - F.zeta * F.r;
-  F.sgn = (kmaxf < 0.0) ? 1.0 : -1.0;
-
-  F.o[0] = pp[0] + a00 * n0; F.o[1] = pp[1] + a00 * n1; F.o[2] = pp[2] + a00 * n2;
-  F.c[0] = F.o[0] + ns0 / kminf; F.c[1] = F.o[1] + ns1 / kminf; F.c[2] = F.o[2] + ns2 / kminf;
-  // axis u = n* x v_min
-  double u0 = ns1 * v2 - ns2 * v1, u1 = ns2 * v0 - ns0 * v2, u2 = ns0 * v1 - ns1 * v0;
-  double ul = sqrt(u0 * u0 + u1 * u1 + u2 * u2);
-  F.u[0] = u0 / ul; F.u[1] = u1 / ul; F.u[2] = u2 / ul;
-  // m = (o - c)/L = -sign(kappa_min) n*
-  double sm = kminf > 0.0 ? -1.0 : 1.0;
-  F.m[0] = sm * ns0; F.m[1] = sm * ns1; F.m[2] = sm * ns2;
-  F.k[0] = F.u[1] * F.m[2] - F.u[2] * F.m[1];
-  F.k[1] = F.u[2] * F.m[0] - F.u[0] * F.m[2];
-  F.k[2] = F.u[0] * F.m[1] - F.u[1] * F.m[0];
-  return F;
-}
-
-// L = 1/|kappa_min| only (for the form flag); same arithmetic as fit_one.
+// L = 1/|kappa_min| only (for the form flag); same arithmetic as fit_point.
 __device__ inline double radius_L(const float* aa, double kfloor) {
   const double a01 = aa[1], a10 = aa[2], a11 = aa[3], a02 = aa[4], a20 = aa[5];
   const double E = 1.0 + a10 * a10, G = 1.0 + a01 * a01, Fm = a10 * a01;
@@ -256,6 +177,7 @@ __global__ __launch_bounds__(1024) void k_scan(int32_t* blk, int64_t nb, int64_t
     }
     h->diag = float(b.diag);
     h->kfloor = float(b.kfloor);
+    h->kfloor64 = b.kfloor;
     h->lmax_direct = float(b.lmax);
   }
 }
@@ -283,7 +205,10 @@ __global__ __launch_bounds__(kBlock) void k_fit(const float* __restrict__ p, con
   const int64_t n_direct = h->n_direct;
   const int64_t slot = direct ? direct_before : n_direct + (i - direct_before);
 
-  const Fit F = fit_one(p + 3 * i, n + 3 * i, a + 6 * i, b.kfloor);
+  double pd[3], nd[3], ad[6];
+  for (int k = 0; k < 3; ++k) { pd[k] = p[3 * i + k]; nd[k] = n[3 * i + k]; }
+  for (int k = 0; k < 6; ++k) ad[k] = a[6 * i + k];
+  const FitT<double> F = fit_point<double>(pd, nd, ad, b.kfloor);
   const double* O = b.origin;
   double pr[3], orel[3], crel[3];
   for (int k = 0; k < 3; ++k) {

@@ -1,0 +1,120 @@
+// pts_device.h -- device helpers shared by the evaluation and gradient sweeps.
+#pragma once
+
+#include "pts_internal.h"
+
+namespace pts {
+
+__device__ __forceinline__ float hw_sqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
+__device__ __forceinline__ float hw_exp2(float v) { return __builtin_amdgcn_exp2f(v); }
+__device__ __forceinline__ float hw_rcp(float v) { return __builtin_amdgcn_rcpf(v); }
+
+struct QueryIn {
+  float x, y, z;
+  bool valid;
+};
+
+// Query q relative to the cloud origin (record coordinates).
+__device__ __forceinline__ QueryIn load_query(const float* __restrict__ x, int64_t q, int64_t Q, const Header* h) {
+  QueryIn r{0.f, 0.f, 0.f, false};
+  if (q < Q) {
+    r.x = x[3 * q] - h->origin[0];
+    r.y = x[3 * q + 1] - h->origin[1];
+    r.z = x[3 * q + 2] - h->origin[2];
+    r.valid = true;
+  }
+  return r;
+}
+
+// M and -lambda' = -lambda log2(e) of a query from the per-split maxima of
+// |x - p|^2 (Eq. RelationshipBetweenLambdaAndRadius: lambda_x = 2C/M).
+__device__ __forceinline__ void far_of(const float* __restrict__ far2, int S, int64_t Q, int64_t q, float C2,
+                                       float& M, float& nlam) {
+  float m2 = -3.0e38f;
+  for (int s = 0; s < S; ++s) m2 = fmaxf(m2, far2[int64_t(s) * Q + q]);
+  M = sqrtf(fmaxf(m2, 0.f));
+  // with M = 0 every point sits at the query and the weights are uniform
+  nlam = M > 0.f ? -2.f * C2 / M : 0.f;
+}
+
+// One pair, direct torus form: <x-c,.> from stored dot products, then
+// rho = |((x-c).m, (x-c).k)|, |q| = |(rho - R, (x-c).u)|, g = sign (|q| - r)
+// (Eq. SingleTorusSDF and the sign of Eq. TorusSigns).
+__device__ __forceinline__ float g_direct(float x, float y, float z, const float4& U, const float4& Mv,
+                                          const float4& K, const float4& G) {
+  const float vu = fmaf(z, U.z, fmaf(y, U.y, fmaf(x, U.x, U.w)));
+  const float vm = fmaf(z, Mv.z, fmaf(y, Mv.y, fmaf(x, Mv.x, Mv.w)));
+  const float vk = fmaf(z, K.z, fmaf(y, K.y, fmaf(x, K.x, K.w)));
+  const float rho = hw_sqrt(fmaf(vm, vm, vk * vk));
+  const float b = rho - G.x;
+  const float qn = hw_sqrt(fmaf(b, b, vu * vu));
+  return fmaf(G.z, qn, G.w);
+}
+
+// One pair, anchored form for large radii L (nearly flat directions): with
+// y = x - o and t = y.m + L (= (x-c).m),
+//   rho - L = alpha / (rho + L),  alpha = y.m (t + L) + (y.k)^2,
+//   rho - R = (rho - L) + zeta r,
+//   |q| - r = ((rho-L)(rho-L + 2 zeta r) + (y.u)^2) / (|q| + r),
+// which avoids subtracting quantities of size L (and r).
+__device__ __forceinline__ float g_anchored(float x, float y, float z, float L, const float4& U,
+                                            const float4& Mv, const float4& K, const float4& G) {
+  const float yu = fmaf(z, U.z, fmaf(y, U.y, fmaf(x, U.x, U.w)));
+  const float ym = fmaf(z, Mv.z, fmaf(y, Mv.y, fmaf(x, Mv.x, Mv.w)));
+  const float yk = fmaf(z, K.z, fmaf(y, K.y, fmaf(x, K.x, K.w)));
+  const float t = ym + L;
+  const float yk2 = yk * yk;
+  const float rho = hw_sqrt(fmaf(t, t, yk2));
+  const float alpha = fmaf(ym, t + L, yk2);
+  const float beta = alpha * hw_rcp(rho + L);
+  const float b = beta + G.y;
+  const float yu2 = yu * yu;
+  const float qn = hw_sqrt(fmaf(b, b, yu2));
+  const float num = fmaf(beta, b + G.y, yu2);
+  const float den = fmaf(G.z, qn, -G.w);   // sign (|q| + r)
+  return num * hw_rcp(den);
+}
+
+// Torus quantities of one pair needed by the derivatives: g, the components
+// (vu, vm, vk) of x - c in the frame (u, m, k), rho, b = rho - R and |q|.
+struct Geo {
+  float g, vu, vm, vk, rho, b, qn;
+};
+
+__device__ __forceinline__ Geo geo_direct(float x, float y, float z, const float4& U, const float4& Mv,
+                                          const float4& K, const float4& G) {
+  Geo r;
+  r.vu = fmaf(z, U.z, fmaf(y, U.y, fmaf(x, U.x, U.w)));
+  r.vm = fmaf(z, Mv.z, fmaf(y, Mv.y, fmaf(x, Mv.x, Mv.w)));
+  r.vk = fmaf(z, K.z, fmaf(y, K.y, fmaf(x, K.x, K.w)));
+  r.rho = hw_sqrt(fmaf(r.vm, r.vm, r.vk * r.vk));
+  r.b = r.rho - G.x;
+  r.qn = hw_sqrt(fmaf(r.b, r.b, r.vu * r.vu));
+  r.g = fmaf(G.z, r.qn, G.w);
+  return r;
+}
+
+__device__ __forceinline__ Geo geo_anchored(float x, float y, float z, float L, const float4& U, const float4& Mv,
+                                            const float4& K, const float4& G) {
+  Geo r;
+  r.vu = fmaf(z, U.z, fmaf(y, U.y, fmaf(x, U.x, U.w)));
+  const float ym = fmaf(z, Mv.z, fmaf(y, Mv.y, fmaf(x, Mv.x, Mv.w)));
+  r.vk = fmaf(z, K.z, fmaf(y, K.y, fmaf(x, K.x, K.w)));
+  r.vm = ym + L;
+  const float yk2 = r.vk * r.vk;
+  r.rho = hw_sqrt(fmaf(r.vm, r.vm, yk2));
+  const float alpha = fmaf(ym, r.vm + L, yk2);
+  const float beta = alpha * hw_rcp(r.rho + L);
+  r.b = beta + G.y;
+  const float yu2 = r.vu * r.vu;
+  r.qn = hw_sqrt(fmaf(r.b, r.b, yu2));
+  const float num = fmaf(beta, r.b + G.y, yu2);
+  r.g = num * hw_rcp(fmaf(G.z, r.qn, -G.w));
+  return r;
+}
+
+// 1/v, or 0 where v is 0 (the derivative factors it scales vanish there; a
+// subgradient on the torus axis, its core circle, and at the points).
+__device__ __forceinline__ float safe_rcp(float v) { return v > 0.f ? hw_rcp(v) : 0.f; }
+
+}  // namespace pts

@@ -23,30 +23,10 @@
 // and the sums are accumulated per tile and then per split (two-level), which
 // bounds FP32 accumulation error by ~(tile + N/(S tile)) ulp.
 
-#include "pts_internal.h"
+#include "pts_device.h"
 
 namespace pts {
 namespace {
-
-__device__ __forceinline__ float hw_sqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
-__device__ __forceinline__ float hw_exp2(float v) { return __builtin_amdgcn_exp2f(v); }
-__device__ __forceinline__ float hw_rcp(float v) { return __builtin_amdgcn_rcpf(v); }
-
-struct QueryIn {
-  float x, y, z;
-  bool valid;
-};
-
-__device__ __forceinline__ QueryIn load_query(const float* __restrict__ x, int64_t q, int64_t Q, const Header* h) {
-  QueryIn r{0.f, 0.f, 0.f, false};
-  if (q < Q) {
-    r.x = x[3 * q] - h->origin[0];
-    r.y = x[3 * q + 1] - h->origin[1];
-    r.z = x[3 * q + 2] - h->origin[2];
-    r.valid = true;
-  }
-  return r;
-}
 
 // ---------------------------------------------------------------------------
 // Sweep 1: squared distance to the farthest point, per split.
@@ -97,54 +77,6 @@ __global__ __launch_bounds__(kBlock) void k_far(const Header* __restrict__ h, co
     const int64_t q = qb * (kBlock * QPL) + k * kBlock + threadIdx.x;
     if (q < Q) far2[int64_t(split) * Q + q] = acc[k] + fmaf(qz[k], qz[k], fmaf(qy[k], qy[k], qx[k] * qx[k]));
   }
-}
-
-// M and lambda' = lambda log2(e) of a query from the per-split maxima.
-__device__ __forceinline__ void far_of(const float* __restrict__ far2, int S, int64_t Q, int64_t q, float C2,
-                                       float& M, float& nlam) {
-  float m2 = -3.0e38f;
-  for (int s = 0; s < S; ++s) m2 = fmaxf(m2, far2[int64_t(s) * Q + q]);
-  M = sqrtf(fmaxf(m2, 0.f));
-  // lambda_x = 2C/M; with M = 0 every point sits at the query and the
-  // weights are uniform (lambda does not matter).
-  nlam = M > 0.f ? -2.f * C2 / M : 0.f;
-}
-
-// One pair, direct torus form: <x-c,.> from stored dot products, then
-// rho = |((x-c).m, (x-c).k)|, |q| = |(rho - R, (x-c).u)|, g = sign (|q| - r).
-__device__ __forceinline__ float g_direct(float x, float y, float z, const float4& U, const float4& Mv,
-                                          const float4& K, const float4& G) {
-  const float vu = fmaf(z, U.z, fmaf(y, U.y, fmaf(x, U.x, U.w)));
-  const float vm = fmaf(z, Mv.z, fmaf(y, Mv.y, fmaf(x, Mv.x, Mv.w)));
-  const float vk = fmaf(z, K.z, fmaf(y, K.y, fmaf(x, K.x, K.w)));
-  const float rho = hw_sqrt(fmaf(vm, vm, vk * vk));
-  const float b = rho - G.x;
-  const float qn = hw_sqrt(fmaf(b, b, vu * vu));
-  return fmaf(G.z, qn, G.w);
-}
-
-// One pair, anchored form for large radii L (nearly flat directions): with
-// y = x - o and t = y.m + L (= (x-c).m),
-//   rho - L = alpha / (rho + L),  alpha = y.m (t + L) + (y.k)^2,
-//   rho - R = (rho - L) + zeta r,
-//   |q| - r = ((rho-L)(rho-L + 2 zeta r) + (y.u)^2) / (|q| + r),
-// which avoids subtracting quantities of size L (and r).
-__device__ __forceinline__ float g_anchored(float x, float y, float z, float L, const float4& U,
-                                            const float4& Mv, const float4& K, const float4& G) {
-  const float yu = fmaf(z, U.z, fmaf(y, U.y, fmaf(x, U.x, U.w)));
-  const float ym = fmaf(z, Mv.z, fmaf(y, Mv.y, fmaf(x, Mv.x, Mv.w)));
-  const float yk = fmaf(z, K.z, fmaf(y, K.y, fmaf(x, K.x, K.w)));
-  const float t = ym + L;
-  const float yk2 = yk * yk;
-  const float rho = hw_sqrt(fmaf(t, t, yk2));
-  const float alpha = fmaf(ym, t + L, yk2);
-  const float beta = alpha * hw_rcp(rho + L);
-  const float b = beta + G.y;
-  const float yu2 = yu * yu;
-  const float qn = hw_sqrt(fmaf(b, b, yu2));
-  const float num = fmaf(beta, b + G.y, yu2);
-  const float den = fmaf(G.z, qn, -G.w);   // sign (|q| + r)
-  return num * hw_rcp(den);
 }
 
 // ---------------------------------------------------------------------------
@@ -220,10 +152,9 @@ __global__ __launch_bounds__(kBlock) void k_blend(const Header* __restrict__ h, 
   }
 }
 
-// Fixed-order combine of the split partials; optional (M, W, phi) statistics.
-__global__ __launch_bounds__(kBlock) void k_combine(const float2* __restrict__ part, const float* __restrict__ far2,
-                                                    int S, int64_t Q, float C2, float* __restrict__ sdf,
-                                                    float* __restrict__ stats) {
+// Fixed-order combine of the split partials.
+__global__ __launch_bounds__(kBlock) void k_combine(const float2* __restrict__ part, int S, int64_t Q,
+                                                    float* __restrict__ sdf) {
   const int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (q >= Q) return;
   float num = 0.f, den = 0.f;
@@ -232,57 +163,86 @@ __global__ __launch_bounds__(kBlock) void k_combine(const float2* __restrict__ p
     num += v.x;
     den += v.y;
   }
-  const float phi = num / den;
-  sdf[q] = phi;
-  if (stats) {
-    float M, nlam;
-    far_of(far2, S, Q, q, C2, M, nlam);
-    stats[3 * q] = M;
-    stats[3 * q + 1] = den;
-    stats[3 * q + 2] = phi;
-  }
+  sdf[q] = num / den;
 }
 
 template <int QPL>
-void launch_sweeps(const Header* h, const float4* pos4, const float4* rec, const float* x, int64_t Q,
-                   const Plan& plan, float* far2, float2* part, float C2, hipStream_t st, int stages) {
-  const dim3 grid(unsigned(plan.nqb * plan.S));
-  if (stages & kStageFar)
-    hipLaunchKernelGGL(k_far<QPL>, grid, dim3(kBlock), 0, st, h, pos4, x, Q, plan.S, plan.per_split, far2);
-  if (stages & kStageBlend)
-    hipLaunchKernelGGL(k_blend<QPL>, grid, dim3(kBlock), 0, st, h, rec, x, Q, plan.S, plan.per_split, far2, C2,
-                       part);
+void launch_far_q(const Header* h, const float4* pos4, const float* x, int64_t Q, const Plan& plan, float* far2,
+                  hipStream_t st) {
+  hipLaunchKernelGGL(k_far<QPL>, dim3(unsigned(plan.nqb * plan.S)), dim3(kBlock), 0, st, h, pos4, x, Q, plan.S,
+                     plan.per_split, far2);
+}
+
+template <int QPL>
+void launch_blend_q(const Header* h, const float4* rec, const float* x, int64_t Q, const Plan& plan,
+                    const float* far2, float2* part, float C2, hipStream_t st) {
+  hipLaunchKernelGGL(k_blend<QPL>, dim3(unsigned(plan.nqb * plan.S)), dim3(kBlock), 0, st, h, rec, x, Q, plan.S,
+                     plan.per_split, far2, C2, part);
 }
 
 }  // namespace
 
 size_t eval_ws_bytes(const Plan& plan, int64_t Q) {
-  return align256(size_t(plan.S) * size_t(Q) * sizeof(float)) +
-         align256(size_t(plan.S) * size_t(Q) * sizeof(float2));
+  const size_t sq = size_t(plan.S) * size_t(Q);
+  return align256(sq * sizeof(float)) + align256(sq * sizeof(float2)) + align256(sq * sizeof(int32_t));
 }
 
-int launch_eval(const void* rec, int64_t N, const float* x, int64_t Q, float* sdf, float* grad, float* stats,
-                float C, const Plan& plan, void* ws, hipStream_t st, int stages) {
-  (void)grad;
+size_t grad_ws_bytes(const Plan& plan, int64_t Q) {
+  const size_t sq = size_t(plan.S) * size_t(Q);
+  return eval_ws_bytes(plan, Q) + align256(size_t(Q) * 6 * sizeof(float)) + align256(sq * 2 * sizeof(float4));
+}
+
+WsView ws_view(const Plan& plan, int64_t Q, void* ws) {
+  const size_t sq = size_t(plan.S) * size_t(Q);
+  char* w = static_cast<char*>(ws);
+  WsView v;
+  v.far2 = reinterpret_cast<float*>(w);
+  w += align256(sq * sizeof(float));
+  v.part = reinterpret_cast<float2*>(w);
+  w += align256(sq * sizeof(float2));
+  v.farix = reinterpret_cast<int32_t*>(w);
+  w += align256(sq * sizeof(int32_t));
+  v.stats = reinterpret_cast<float*>(w);
+  w += align256(size_t(Q) * 6 * sizeof(float));
+  v.gpart = reinterpret_cast<float4*>(w);
+  return v;
+}
+
+int launch_far(const void* rec, int64_t N, const float* x, int64_t Q, const Plan& plan, const WsView& ws,
+               hipStream_t st) {
   const Layout L(N);
   const char* base = static_cast<const char*>(rec);
   const Header* h = reinterpret_cast<const Header*>(base);
   const float4* pos4 = reinterpret_cast<const float4*>(base + L.pos);
+  switch (plan.qpl) {
+    case 1: launch_far_q<1>(h, pos4, x, Q, plan, ws.far2, st); break;
+    case 2: launch_far_q<2>(h, pos4, x, Q, plan, ws.far2, st); break;
+    case 8: launch_far_q<8>(h, pos4, x, Q, plan, ws.far2, st); break;
+    default: launch_far_q<4>(h, pos4, x, Q, plan, ws.far2, st); break;
+  }
+  return check_hip(hipGetLastError(), "farthest-point kernel");
+}
+
+int launch_blend(const void* rec, int64_t N, const float* x, int64_t Q, float C, const Plan& plan,
+                 const WsView& ws, hipStream_t st) {
+  const Layout L(N);
+  const char* base = static_cast<const char*>(rec);
+  const Header* h = reinterpret_cast<const Header*>(base);
   const float4* recs = reinterpret_cast<const float4*>(base + L.rec);
-  char* w = static_cast<char*>(ws);
-  float* far2 = reinterpret_cast<float*>(w);
-  float2* part = reinterpret_cast<float2*>(w + align256(size_t(plan.S) * size_t(Q) * sizeof(float)));
   const float C2 = C * kLog2e;
   switch (plan.qpl) {
-    case 1: launch_sweeps<1>(h, pos4, recs, x, Q, plan, far2, part, C2, st, stages); break;
-    case 2: launch_sweeps<2>(h, pos4, recs, x, Q, plan, far2, part, C2, st, stages); break;
-    case 8: launch_sweeps<8>(h, pos4, recs, x, Q, plan, far2, part, C2, st, stages); break;
-    default: launch_sweeps<4>(h, pos4, recs, x, Q, plan, far2, part, C2, st, stages); break;
+    case 1: launch_blend_q<1>(h, recs, x, Q, plan, ws.far2, ws.part, C2, st); break;
+    case 2: launch_blend_q<2>(h, recs, x, Q, plan, ws.far2, ws.part, C2, st); break;
+    case 8: launch_blend_q<8>(h, recs, x, Q, plan, ws.far2, ws.part, C2, st); break;
+    default: launch_blend_q<4>(h, recs, x, Q, plan, ws.far2, ws.part, C2, st); break;
   }
-  if (stages & kStageCombine)
-    hipLaunchKernelGGL(k_combine, dim3(unsigned((Q + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, part, far2,
-                       plan.S, Q, C2, sdf, stats);
-  return check_hip(hipGetLastError(), "eval kernels");
+  return check_hip(hipGetLastError(), "blend kernel");
+}
+
+int launch_combine(int64_t Q, const Plan& plan, const WsView& ws, float* sdf, hipStream_t st) {
+  hipLaunchKernelGGL(k_combine, dim3(unsigned((Q + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, ws.part, plan.S,
+                     Q, sdf);
+  return check_hip(hipGetLastError(), "combine kernel");
 }
 
 }  // namespace pts

@@ -38,6 +38,7 @@ struct alignas(256) Header {
   uint32_t hi_bits[3];
   int32_t status;       // bit 0: zero normal, bit 1: non-finite input
   int32_t pad0;
+  double kfloor64;      // curvature floor used by the fit (FP64)
 };
 static_assert(sizeof(Header) == 256, "header is 256 bytes");
 
@@ -75,6 +76,26 @@ struct Plan {
   int64_t nqb;        // query blocks of kBlock * qpl queries
 };
 Plan make_plan(int64_t N, int64_t Q, const pts_params* prm);
+// The same split with a different number of queries per lane.
+inline Plan with_qpl(Plan p, int qpl, int64_t Q) {
+  p.qpl = qpl;
+  p.nqb = (Q + int64_t(kBlock) * qpl - 1) / (int64_t(kBlock) * qpl);
+  return p;
+}
+
+// Workspace of one evaluation: per-split maxima and blend partials, the slot
+// of each split's farthest point, and (gradients only) the statistics of the
+// queries and the per-split gradient partials.
+struct WsView {
+  float* far2;     // [S][Q]
+  float2* part;    // [S][Q]
+  int32_t* farix;  // [S][Q]
+  float* stats;    // [Q][6]    (gradient workspace only)
+  float4* gpart;   // [S][Q][2] (gradient workspace only)
+};
+size_t eval_ws_bytes(const Plan& plan, int64_t Q);
+size_t grad_ws_bytes(const Plan& plan, int64_t Q);
+WsView ws_view(const Plan& plan, int64_t Q, void* ws);
 
 // Error reporting (thread-local message, returned status).
 int fail(int code, const std::string& msg);
@@ -84,9 +105,27 @@ int check_hip(hipError_t e, const char* what);
 int launch_build(const float* p, const float* n, const float* a, int64_t N, float kfloor_rel,
                  void* rec, hipStream_t st);
 int launch_decode(const void* rec, int64_t N, float* out, hipStream_t st);
-constexpr int kStageFar = 1, kStageBlend = 2, kStageCombine = 4, kStageAll = 7;
-int launch_eval(const void* rec, int64_t N, const float* x, int64_t Q, float* sdf, float* grad,
-                float* stats, float C, const Plan& plan, void* ws, hipStream_t st, int stages);
-size_t eval_ws_bytes(const Plan& plan, int64_t Q);
+int launch_far(const void* rec, int64_t N, const float* x, int64_t Q, const Plan& plan, const WsView& ws,
+               hipStream_t st);
+int launch_blend(const void* rec, int64_t N, const float* x, int64_t Q, float C, const Plan& plan,
+                 const WsView& ws, hipStream_t st);
+int launch_combine(int64_t Q, const Plan& plan, const WsView& ws, float* sdf, hipStream_t st);
+int launch_far_arg(const void* rec, int64_t N, const float* x, int64_t Q, const Plan& plan, const WsView& ws,
+                   hipStream_t st);
+int launch_combine_stats(const void* rec, int64_t N, const float* x, int64_t Q, const Plan& plan,
+                         const WsView& ws, float* sdf, float* stats, hipStream_t st);
+int launch_grad(const void* rec, int64_t N, const float* x, int64_t Q, const float* stats, const float* gout,
+                float* gx, float C, const Plan& plan, const WsView& ws, hipStream_t st);
+
+// Parameter backward: point blocks x query ranges.
+struct BackPlan {
+  int Sq;          // query ranges
+  int64_t per_qs;  // queries per range (multiple of the query tile)
+  int64_t pbs;     // point blocks of kBlock points
+};
+BackPlan make_back_plan(int64_t N, int64_t Q);
+size_t back_ws_bytes(int64_t N, int64_t Q);
+int launch_backward(const void* rec, int64_t N, const float* p, const float* n, const float* a, const float* x,
+                    int64_t Q, const float* gout, const float* stats, float* ga, float C, void* ws, hipStream_t st);
 
 }  // namespace pts
