@@ -212,6 +212,28 @@ int pts_backward_params(const void* rec, int64_t N, const float* p, const float*
                         const float* x, int64_t Q, const float* gout, const float* stats, float* ga,
                         const pts_params* prm, void* ws, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Sphere tracing (Sec. 5.3, "Direct visualization of point cloud surfaces").
+ * ------------------------------------------------------------------------- */
+
+/* Scratch bytes for pts_trace with R rays. */
+int pts_trace_ws_bytes(int64_t N, int64_t R, const pts_params* prm, size_t* out_bytes);
+
+/* March R rays x(t) = origin + t dir (dir unit length; device [R,3] float32)
+ * through phi: t = 0; up to `steps` evaluations; a ray stops with a hit when
+ * |phi(x)| < eps, else t += phi(x) and it stops with a miss once t > tmax.
+ * Outputs (device): t_out [R] float32 (final t), hit_out [R] int32 (1 = hit),
+ * steps_out [R] int32 or NULL (steps taken before stopping; `steps` if the
+ * budget ran out), normal_out [R,3] float32 or NULL (grad phi / |grad phi| at
+ * hits, 0 elsewhere).  Each step evaluates the active rays with the pts_eval
+ * kernels; the point split depends on N only, so a ray's result does not
+ * depend on the other rays.  Blocks: it reads back the active-ray count after
+ * every step.  phi overestimates |distance| away from the surface for finite
+ * C (Sec. 6), so rays can overshoot thin features. */
+int pts_trace(const void* rec, int64_t N, const float* origin, const float* dir, int64_t R, int steps,
+              float eps, float tmax, float* t_out, float* normal_out, int32_t* hit_out,
+              int32_t* steps_out, const pts_params* prm, void* ws, size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -69,6 +69,9 @@ SIGNATURES = {
     "pts_backward_ws_bytes": (ctypes.c_int, [_I64, _I64, ctypes.POINTER(Params), ctypes.POINTER(_SZ)]),
     "pts_backward_params": (ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _I64, _P, _P, _P, ctypes.POINTER(Params), _P,
                                            _SZ, _P]),
+    "pts_trace_ws_bytes": (ctypes.c_int, [_I64, _I64, ctypes.POINTER(Params), ctypes.POINTER(_SZ)]),
+    "pts_trace": (ctypes.c_int, [_P, _I64, _P, _P, _I64, ctypes.c_int, ctypes.c_float, ctypes.c_float, _P, _P, _P, _P,
+                                 ctypes.POINTER(Params), _P, _SZ, _P]),
 }
 
 
@@ -268,6 +271,29 @@ def backward_params(rec: torch.Tensor, p: torch.Tensor, n: torch.Tensor, a: torc
     _check(lib().pts_backward_params(_ptr(rec), N, _ptr(p), _ptr(n), _ptr(a), _ptr(x), Q, _ptr(gout), _ptr(stats),
                                      _ptr(ga), ctypes.byref(prm), _ptr(ws), ws.numel(), _stream()))
     return ga
+
+
+def trace(rec: torch.Tensor, N: int, origin: torch.Tensor, direction: torch.Tensor, steps: int, eps: float,
+          tmax: float, params: Params | None = None, normals: bool = True, ws: torch.Tensor | None = None):
+    """Sphere tracing (Sec. 5.3): returns (t [R], hit [R] bool, steps [R] int32, normals [R,3] or None)."""
+    _dev(origin, "origin", 3)
+    _dev(direction, "direction", 3)
+    R = origin.shape[0]
+    if direction.shape[0] != R:
+        raise ValueError("origin and direction must have the same number of rows")
+    prm = params if params is not None else make_params()
+    t = torch.empty(R, dtype=torch.float32, device=origin.device)
+    hit = torch.empty(R, dtype=torch.int32, device=origin.device)
+    ns = torch.empty(R, dtype=torch.int32, device=origin.device)
+    nrm = torch.empty((R, 3), dtype=torch.float32, device=origin.device) if normals else None
+    out = _SZ(0)
+    _check(lib().pts_trace_ws_bytes(int(N), R, ctypes.byref(prm), ctypes.byref(out)))
+    if ws is None or ws.numel() < out.value:
+        ws = torch.empty(max(out.value, 256), dtype=torch.uint8, device=origin.device)
+    _check(lib().pts_trace(_ptr(rec), int(N), _ptr(origin), _ptr(direction), R, int(steps), float(eps), float(tmax),
+                           _ptr(t), _ptr(nrm), _ptr(hit), _ptr(ns), ctypes.byref(prm), _ptr(ws), ws.numel(),
+                           _stream()))
+    return t, hit.bool(), ns, nrm
 
 
 class Cloud:
