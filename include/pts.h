@@ -53,9 +53,9 @@ extern "C" {
 #define PTS_OK 0
 #define PTS_EINVAL 1      /* invalid argument (null pointer, size, layout)   */
 #define PTS_EBUDGET 2     /* request does not fit the server's memory budget */
-#define PTS_ENOMEM 3      /* device allocation failed (server only)         */
+#define PTS_ENOMEM 3      /* device or pinned allocation failed (server only) */
 #define PTS_EHIP 4        /* a HIP runtime call failed                       */
-#define PTS_EBUSY 5       /* server queue full                               */
+#define PTS_EBUSY 5       /* server busy: queue full, cloud or ticket in use  */
 #define PTS_ECANCELLED 6  /* request cancelled                               */
 #define PTS_ENOTFOUND 7   /* unknown cloud id or ticket                      */
 #define PTS_ETIMEOUT 8    /* wait timed out                                  */
@@ -233,6 +233,142 @@ int pts_trace_ws_bytes(int64_t N, int64_t R, const pts_params* prm, size_t* out_
 int pts_trace(const void* rec, int64_t N, const float* origin, const float* dir, int64_t R, int steps,
               float eps, float tmax, float* t_out, float* normal_out, int32_t* hit_out,
               int32_t* steps_out, const pts_params* prm, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Serving: a resident-cloud server with continuous batching.
+ *
+ * The server keeps many clouds' records resident on the device and answers
+ * requests (phi at queries, or a sphere trace) from client threads.  A
+ * scheduler thread admits queued requests in arrival order while fewer than
+ * max_inflight are running and their device buffers fit the memory budget,
+ * packs every runnable piece of work (whole query requests and the next step
+ * of every trace request) into one launch of the evaluation kernels, and keeps
+ * up to two such launches in flight on two streams, so requests that arrive
+ * while the device is busy are admitted and start as soon as memory and a
+ * launch slot free up.  Trace requests advance one step per launch and are
+ * repacked until every ray has stopped; then normals are computed.
+ *
+ * A request on a cloud of N points is evaluated with the point split
+ * pts_server_cloud_plan reports, a function of N only: its results are bitwise
+ * the same alone or in any mix, and equal pts_eval / pts_trace called with
+ * pts_params.splits set to that split (and the server's C, kfloor_rel).
+ *
+ * All device memory (records, request buffers, launch descriptors) comes from
+ * one allocation of hbm_budget_bytes made at creation; that is the budget
+ * requests are admitted against.  Host buffers named in a request are plain
+ * host memory: inputs are copied before pts_server_submit returns, outputs are
+ * written before the request is reported finished and must stay valid until
+ * then.  All entry points are thread-safe.
+ * ------------------------------------------------------------------------- */
+
+typedef struct pts_server pts_server;
+
+typedef struct pts_server_cfg {
+  size_t hbm_budget_bytes;  /* device memory of the server; 0 = 4 GiB */
+  int max_inflight;         /* requests admitted at once; 0 = 64 */
+  int max_queue;            /* queued (not yet admitted) requests; 0 = 2^20 */
+  int64_t max_batch_work;   /* workgroups per packed launch (512 queries x one
+                               point split each); 0 = 131072.  A request needing
+                               more than this is rejected with PTS_EINVAL. */
+  float C;                  /* as pts_params; 0 = 64 */
+  float kfloor_rel;         /* as pts_params; 0 = 1e-6 */
+  int mock;                 /* 1 = no device: a cost model stands in for the
+                               kernels (pairs / mock_pairs_per_s seconds per
+                               launch) and outputs are filled with a pattern
+                               (query requests: cloud + 1e-3 (j mod 1000); trace
+                               requests: t = cloud, hit = j mod 2, normals 0, and
+                               every ray stops after min(steps, 3) steps).  For
+                               testing the scheduler on hosts without a GPU. */
+  int mock_fail_count;      /* mock only: query requests of exactly this count
+                               fail with PTS_EHIP (0 = never) */
+  double mock_pairs_per_s;  /* mock only; 0 = 1e12 */
+} pts_server_cfg;
+
+#define PTS_REQ_EVAL 0
+#define PTS_REQ_TRACE 1
+
+typedef struct pts_request {
+  int kind;           /* PTS_REQ_EVAL or PTS_REQ_TRACE */
+  int cloud;          /* id from pts_server_add_cloud */
+  int64_t count;      /* queries (EVAL) or rays (TRACE); 0 finishes at once */
+  const float* in0;   /* host [count,3]: queries (EVAL) or ray origins (TRACE) */
+  const float* in1;   /* host [count,3]: unit ray directions (TRACE) */
+  float* out_sdf;     /* host [count]: phi (EVAL) or final t (TRACE) */
+  float* out_normal;  /* host [count,3] or NULL (TRACE): normals at hits, 0 elsewhere */
+  int32_t* out_hit;   /* host [count] (TRACE): 1 = hit */
+  int32_t* out_steps; /* host [count] or NULL (TRACE): as pts_trace's steps_out */
+  int steps;          /* TRACE: evaluation budget per ray (>= 0) */
+  float eps, tmax;    /* TRACE: hit threshold and exit distance, as pts_trace */
+  int reserved;
+} pts_request;
+
+/* Request states reported by pts_server_poll. */
+#define PTS_STATE_QUEUED 0
+#define PTS_STATE_RUNNING 1
+#define PTS_STATE_DONE 2
+#define PTS_STATE_FAILED 3
+#define PTS_STATE_CANCELLED 4
+
+typedef struct pts_server_stats {
+  uint64_t submitted, completed, failed, cancelled, rejected;
+  uint64_t launches;            /* packed launches issued */
+  uint64_t overlapped_launches; /* launches issued while another was in flight */
+  int64_t max_batch_requests;   /* most requests packed into one launch */
+  double pairs;                 /* query x point pairs evaluated (all sweeps count once) */
+  double busy_s;                /* sum of launch durations (device time) */
+  double p50_ms, p99_ms, max_ms;/* latency, submit -> result written, all requests */
+  double p50_eval_ms, p99_eval_ms, p50_trace_ms, p99_trace_ms;
+  size_t bytes_resident;        /* cloud records */
+  size_t bytes_inflight;        /* buffers of admitted requests */
+  size_t bytes_reserved;        /* launch descriptors */
+  int inflight, queued;
+} pts_server_stats;
+
+/* Create a server (cfg NULL = defaults); allocates its budget on the current
+ * device and starts the scheduler thread.  PTS_ENOMEM if the budget cannot be
+ * allocated or does not hold the launch descriptors. */
+int pts_server_create(const pts_server_cfg* cfg, pts_server** out);
+
+/* Upload and build a cloud (host p [N,3], n [N,3], a [N,6], as
+ * pts_cloud_build) into the server's memory; blocks until built.
+ * PTS_EBUDGET if its record (plus the inputs while building) does not fit. */
+int pts_server_add_cloud(pts_server* srv, const float* p, const float* n, const float* a, int64_t N,
+                         int* id);
+
+/* Split and point count a cloud's requests are evaluated with. */
+int pts_server_cloud_plan(pts_server* srv, int id, int64_t* N, int* splits);
+
+/* Remove a cloud; PTS_EBUSY while requests on it are queued or running. */
+int pts_server_remove_cloud(pts_server* srv, int id);
+
+/* Queue a request.  PTS_EINVAL for a malformed request, PTS_ENOTFOUND for an
+ * unknown cloud, PTS_EBUDGET if its buffers can never fit next to the
+ * resident clouds, PTS_EBUSY if the queue is full. */
+int pts_server_submit(pts_server* srv, const pts_request* req, uint64_t* ticket);
+
+/* Current state (PTS_STATE_*) of a request. */
+int pts_server_poll(pts_server* srv, uint64_t ticket, int* state);
+
+/* Wait until a request has finished (timeout_ms < 0: no limit).  Returns the
+ * request's status: PTS_OK, PTS_ECANCELLED, or the error it failed with;
+ * PTS_ETIMEOUT if it is still queued or running at the limit. */
+int pts_server_wait(pts_server* srv, uint64_t ticket, int timeout_ms);
+
+/* Cancel a request.  A queued one finishes at once; a running one finishes,
+ * with its outputs unwritten, once its current launch has completed. */
+int pts_server_cancel(pts_server* srv, uint64_t ticket);
+
+/* Forget a finished request (its ticket becomes unknown). PTS_EBUSY if it
+ * has not finished. */
+int pts_server_release(pts_server* srv, uint64_t ticket);
+
+/* Counters and latency percentiles since creation or the last reset. */
+int pts_server_stats_get(pts_server* srv, pts_server_stats* out);
+int pts_server_stats_reset(pts_server* srv);
+
+/* Stop the server: queued and running requests finish as PTS_ECANCELLED, the
+ * scheduler drains the device, and all memory is freed.  NULL is a no-op. */
+int pts_server_destroy(pts_server* srv);
 
 #ifdef __cplusplus
 }

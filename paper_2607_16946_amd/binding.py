@@ -44,6 +44,33 @@ class CloudInfo(ctypes.Structure):
                 ("kfloor", ctypes.c_float), ("version", ctypes.c_int), ("reserved", ctypes.c_int)]
 
 
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_inflight", ctypes.c_int), ("max_queue", ctypes.c_int),
+                ("max_batch_work", ctypes.c_int64), ("C", ctypes.c_float), ("kfloor_rel", ctypes.c_float),
+                ("mock", ctypes.c_int), ("mock_fail_count", ctypes.c_int), ("mock_pairs_per_s", ctypes.c_double)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("cloud", ctypes.c_int), ("count", ctypes.c_int64),
+                ("in0", ctypes.c_void_p), ("in1", ctypes.c_void_p), ("out_sdf", ctypes.c_void_p),
+                ("out_normal", ctypes.c_void_p), ("out_hit", ctypes.c_void_p), ("out_steps", ctypes.c_void_p),
+                ("steps", ctypes.c_int), ("eps", ctypes.c_float), ("tmax", ctypes.c_float), ("reserved", ctypes.c_int)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in ("submitted", "completed", "failed", "cancelled", "rejected",
+                                              "launches", "overlapped_launches")] + \
+               [("max_batch_requests", ctypes.c_int64)] + \
+               [(k, ctypes.c_double) for k in ("pairs", "busy_s", "p50_ms", "p99_ms", "max_ms", "p50_eval_ms",
+                                              "p99_eval_ms", "p50_trace_ms", "p99_trace_ms")] + \
+               [(k, ctypes.c_size_t) for k in ("bytes_resident", "bytes_inflight", "bytes_reserved")] + \
+               [("inflight", ctypes.c_int), ("queued", ctypes.c_int)]
+
+
+PTS_REQ_EVAL = 0
+PTS_REQ_TRACE = 1
+STATE_NAMES = {0: "queued", 1: "running", 2: "done", 3: "failed", 4: "cancelled"}
+
 _lib = None
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -72,6 +99,18 @@ SIGNATURES = {
     "pts_trace_ws_bytes": (ctypes.c_int, [_I64, _I64, ctypes.POINTER(Params), ctypes.POINTER(_SZ)]),
     "pts_trace": (ctypes.c_int, [_P, _I64, _P, _P, _I64, ctypes.c_int, ctypes.c_float, ctypes.c_float, _P, _P, _P, _P,
                                  ctypes.POINTER(Params), _P, _SZ, _P]),
+    "pts_server_create": (ctypes.c_int, [ctypes.POINTER(ServerCfg), ctypes.POINTER(_P)]),
+    "pts_server_add_cloud": (ctypes.c_int, [_P, _P, _P, _P, _I64, ctypes.POINTER(ctypes.c_int)]),
+    "pts_server_cloud_plan": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_int)]),
+    "pts_server_remove_cloud": (ctypes.c_int, [_P, ctypes.c_int]),
+    "pts_server_submit": (ctypes.c_int, [_P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
+    "pts_server_poll": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]),
+    "pts_server_wait": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_int]),
+    "pts_server_cancel": (ctypes.c_int, [_P, ctypes.c_uint64]),
+    "pts_server_release": (ctypes.c_int, [_P, ctypes.c_uint64]),
+    "pts_server_stats_get": (ctypes.c_int, [_P, ctypes.POINTER(ServerStats)]),
+    "pts_server_stats_reset": (ctypes.c_int, [_P]),
+    "pts_server_destroy": (ctypes.c_int, [_P]),
 }
 
 

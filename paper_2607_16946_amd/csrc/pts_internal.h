@@ -134,5 +134,16 @@ size_t trace_ws_bytes(int64_t N, int64_t R, const pts_params& P);
 int launch_trace(const void* rec, int64_t N, const float* org, const float* dir, int64_t R, int steps, float eps,
                  float tmax, float* t, float* nrm, int32_t* hit, int32_t* nsteps, const pts_params& P, void* ws,
                  size_t ws_bytes, hipStream_t st);
+// Single steps of the march with the active-ray count left on the device.
+int trace_init(int64_t R, int steps, float* t, int32_t* hit, int32_t* nsteps, int32_t* act, float* nrm,
+               hipStream_t st);
+int trace_step_pre(const int32_t* act, int64_t na, const float* org, const float* dir, const float* t, float* xq,
+                   hipStream_t st);
+int trace_step_post(const int32_t* act, int64_t na, const float* phi, float eps, float tmax, int step, float* t,
+                    int32_t* hit, int32_t* nsteps, int32_t* keep, int32_t* act_out, int32_t* blk, int32_t* off,
+                    int32_t* count, hipStream_t st);
+int trace_normals_all(const void* rec, int64_t N, const float* org, const float* dir, const float* t,
+                      const int32_t* hit, int64_t R, int32_t* iota, float* xq, float* phi, float* g, float* nrm,
+                      const Plan& plan, float C, void* ws, hipStream_t st);
 
 }  // namespace pts

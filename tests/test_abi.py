@@ -81,3 +81,27 @@ def test_plan_covers_every_point():
                 assert (splits - 1) * per < N, (N, Q, S, splits, per)     # no empty split
                 if S:
                     assert splits <= S
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """ctypes structures have the sizes and field offsets gcc gives the C structs."""
+    structs = {"pts_params": binding.Params, "pts_cloud_info": binding.CloudInfo,
+               "pts_server_cfg": binding.ServerCfg, "pts_request": binding.Request,
+               "pts_server_stats": binding.ServerStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pts.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
