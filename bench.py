@@ -20,6 +20,7 @@ from __future__ import annotations
 import argparse
 import ctypes
 import json
+import math
 import os
 import sys
 import time
@@ -125,6 +126,108 @@ def cpu_baseline(cl, x, sample: int):
             "seconds": t2 - t1}
 
 
+def serving_bench(n_requests: int, n_warmup: int, loads, n_clouds: int = 64, budget_gib: int = 64,
+                  mock: bool = False):
+    """Serving workload: resident clouds, Poisson arrivals of query / trace requests.
+
+    64 clouds, cloud j from the sphere generator with N log-uniform in
+    [1024, 262144]; 90% query requests (Q log-uniform in [1, 65536], x uniform in
+    [-1.5, 1.5]^3) and 10% trace requests (256^2 rays, 48 steps, camera on a
+    radius-3 sphere aimed at the origin, 45 degree field of view, normals).
+    Capacity is measured closed-loop (a burst of requests, all submitted at
+    once); then Poisson arrivals at each fraction of it.  Latency is the
+    server's own (submit -> result written to host memory)."""
+    import numpy as np
+    from paper_2607_16946_amd import synth
+    from paper_2607_16946_amd.server import Server
+
+    t_setup = time.perf_counter()
+    clouds = [synth.serving_cloud(j) for j in range(n_clouds)]
+    S = Server(budget_bytes=budget_gib << 30, max_inflight=64, mock=mock, mock_pairs_per_s=1e12)
+    ids = [S.add_cloud(c.p, c.n, c.a) for c in clouds]
+    Ns = np.array([c.N for c in clouds], dtype=np.float64)
+    diag = [float(np.linalg.norm(c.p.max(0) - c.p.min(0))) for c in clouds]
+    cams = []
+    for k in range(8):
+        o, d = synth.camera_rays(256, radius=3.0, fov_deg=45.0, seed=100 + k)
+        d = d.astype(np.float64)
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        cams.append((np.ascontiguousarray(o, np.float32), np.ascontiguousarray(d, np.float32)))
+    log(f"serving: {n_clouds} clouds resident (N {int(Ns.min())}..{int(Ns.max())}, sum {int(Ns.sum())}); "
+        f"setup {time.perf_counter() - t_setup:.1f} s")
+    rng = np.random.Generator(np.random.PCG64(synth.SERVE_SEED_BASE + 777))
+
+    def draw():
+        j = int(rng.integers(n_clouds))
+        if rng.random() < 0.1:
+            return ("trace", j, int(rng.integers(len(cams))))
+        q = int(round(math.exp(rng.uniform(0.0, math.log(65536)))))
+        return ("eval", j, rng.uniform(-1.5, 1.5, size=(q, 3)).astype(np.float32))
+
+    def submit(r):
+        kind, j, arg = r
+        if kind == "eval":
+            return S.submit_eval(ids[j], arg)
+        o, d = cams[arg]
+        return S.submit_trace(ids[j], o, d, steps=48, eps=1e-4 * diag[j], tmax=6.0, normals=True)
+
+    def run_open(reqs, rate):
+        """Submit reqs at Poisson times of the given rate; wait for all."""
+        gaps = rng.exponential(1.0 / rate, size=len(reqs))
+        t0 = time.perf_counter()
+        due = t0
+        tickets, lag = [], 0.0
+        for r, g in zip(reqs, gaps):
+            due += g
+            now = time.perf_counter()
+            if due > now:
+                time.sleep(due - now)
+            lag = max(lag, time.perf_counter() - due)
+            tickets.append(submit(r))
+        for t in tickets:
+            S.wait(t)
+        return time.perf_counter() - t0, lag
+
+    # closed-loop capacity
+    burst = [draw() for _ in range(min(400, max(n_requests, 100)))]
+    S.reset_stats()
+    t0 = time.perf_counter()
+    ts = [submit(r) for r in burst]
+    for t in ts:
+        S.wait(t)
+    wall = time.perf_counter() - t0
+    st = S.stats()
+    cap = len(burst) / wall
+    out = {"workload": f"{n_clouds} resident clouds (sphere generator, N log-uniform 1024..262144); 90% query "
+                       f"requests Q log-uniform 1..65536, 10% 256x256 sphere traces of 48 steps with normals",
+           "budget_gib": budget_gib, "clouds": n_clouds, "points_resident": int(Ns.sum()),
+           "capacity_req_s": cap, "capacity_pairs_s": st["pairs"] / wall, "capacity_requests": len(burst),
+           "capacity_launches": st["launches"], "capacity_busy_frac": st["busy_s"] / wall, "loads": []}
+    log(f"serving: capacity {cap:.1f} req/s, {st['pairs'] / wall:.3g} pairs/s over {len(burst)} requests "
+        f"({st['launches']} launches, device busy {st['busy_s'] / wall:.2f} of wall)")
+    for load in loads:
+        rate = load * cap
+        run_open([draw() for _ in range(n_warmup)], rate)
+        S.reset_stats()
+        reqs = [draw() for _ in range(n_requests)]
+        wall, lag = run_open(reqs, rate)
+        st = S.stats()
+        row = {"load": load, "offered_req_s": rate, "achieved_req_s": len(reqs) / wall, "requests": len(reqs),
+               "n_trace": sum(r[0] == "trace" for r in reqs), "wall_s": wall, "pairs_s": st["pairs"] / wall,
+               "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "max_ms": st["max_ms"],
+               "p50_query_ms": st["p50_eval_ms"], "p99_query_ms": st["p99_eval_ms"],
+               "p50_trace_ms": st["p50_trace_ms"], "p99_trace_ms": st["p99_trace_ms"],
+               "launches": st["launches"], "overlapped_launches": st["overlapped_launches"],
+               "max_batch_requests": st["max_batch_requests"], "device_busy_frac": st["busy_s"] / wall,
+               "max_submit_lag_ms": lag * 1e3}
+        out["loads"].append(row)
+        log(f"serving: load {load:.2f}: {row['achieved_req_s']:.1f} req/s, p50 {row['p50_ms']:.2f} ms, "
+            f"p99 {row['p99_ms']:.2f} ms (query p50/p99 {row['p50_query_ms']:.2f}/{row['p99_query_ms']:.2f}, "
+            f"trace {row['p50_trace_ms']:.1f}/{row['p99_trace_ms']:.1f})")
+    S.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +238,11 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-mode measurement")
+    ap.add_argument("--serving-only", action="store_true", help="only the serving-mode measurement")
+    ap.add_argument("--serve-requests", type=int, default=600, help="measured requests per load level")
+    ap.add_argument("--serve-warmup", type=int, default=50)
+    ap.add_argument("--serve-loads", default="0.5,0.9", help="arrival rates as fractions of capacity")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run one plain device copy of MIB MiB (calibrates the HBM byte counters) and exit")
     args = ap.parse_args()
@@ -158,6 +266,10 @@ def main():
 
     torch.cuda.set_device(0)
     log(f"bench: device {torch.cuda.get_device_name(0)}")
+    loads = [float(v) for v in args.serve_loads.split(",") if v]
+    if args.serving_only:
+        print(json.dumps({"serving": serving_bench(args.serve_requests, args.serve_warmup, loads)}))
+        return
     cl, x = synth.mid(N=args.points, grid=args.grid)
     N, Q = cl.N, x.shape[0]
     log(f"bench: workload N={N} Q={Q} pairs/step={N * Q:.4g}")
@@ -236,6 +348,8 @@ def main():
         "stages_ms": stage,
         "roofline": roofline,
     }
+    if not args.no_serving:
+        out["serving"] = serving_bench(args.serve_requests, args.serve_warmup, loads)
     if not args.no_cpu_baseline:
         log("bench: timing the FP64 oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(cl, x, args.cpu_sample)
