@@ -108,10 +108,11 @@ def probe_issue_rates():
 
 
 def cpu_baseline(cl, x, sample: int):
+    """The FP64 oracle as it stands, on a seeded sample of the workload's queries:
+    all host threads (up to 16), then one thread on a sixteenth of the sample."""
     import numpy as np
     import oracle
     threads = min(16, os.cpu_count() or 1)
-    oracle.threads(threads)
     idx = np.random.default_rng(12345).choice(x.shape[0], size=min(sample, x.shape[0]), replace=False)
     xs = x[np.sort(idx)]
     t0 = time.perf_counter()
@@ -120,10 +121,112 @@ def cpu_baseline(cl, x, sample: int):
     oracle.eval_sdf(cl.p, tor, xs, nthreads=threads)
     t2 = time.perf_counter()
     pairs = xs.shape[0] * cl.N
+    x1 = xs[:max(1, xs.shape[0] // 16)]
+    t3 = time.perf_counter()
+    oracle.eval_sdf(cl.p, tor, x1, nthreads=1)
+    t4 = time.perf_counter()
     return {"value": pairs / (t2 - t1), "unit": "pairs/s", "cores": threads, "kind": "oracle",
             "sample": f"{xs.shape[0]} seeded queries of the {x.shape[0]}-query lattice x all {cl.N} points "
                       f"({pairs:.3g} pairs), FP64, after a {t1 - t0:.2f} s torus fit",
-            "seconds": t2 - t1}
+            "seconds": t2 - t1,
+            "one_core": {"value": x1.shape[0] * cl.N / (t4 - t3), "queries": x1.shape[0], "seconds": t4 - t3}}
+
+
+def _timed(fn, reps: int, warm: int = 1) -> float:
+    """Median milliseconds of fn() over reps runs, bracketed by events on the current stream."""
+    import numpy as np
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in evs:
+        e0.record(s)
+        fn()
+        e1.record(s)
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in evs]))
+
+
+def diff_bench(reps: int):
+    """Differentiation workload: one ellipsoid, N = 32768, Q = 2^20 (half within
+    0.05 of the surface, half uniform in the padded bbox), loss = sum phi^2 over
+    the near-surface half.  Times the plain forward, the forward with the
+    statistics backward needs, the fused forward+gradient, d/dquery and
+    d/dcoefficients, each as pairs/s beside the plain forward."""
+    import torch
+    from paper_2607_16946_amd import binding, synth
+    cl, x, mask = synth.diff_workload()
+    N, Q = cl.N, x.shape[0]
+    p, n, a, xd = (torch.from_numpy(v).cuda() for v in (cl.p, cl.n, cl.a, x))
+    md = torch.from_numpy(mask).cuda()
+    prm = binding.make_params()
+    rec = binding.cloud_build(p, n, a, prm)
+    ws_e = torch.empty(binding.eval_ws_bytes(N, Q, prm), dtype=torch.uint8, device="cuda")
+    ws_g = torch.empty(binding.grad_ws_bytes(N, Q, prm), dtype=torch.uint8, device="cuda")
+    ws_b = torch.empty(binding.backward_ws_bytes(N, Q, prm), dtype=torch.uint8, device="cuda")
+    sdf = torch.empty(Q, dtype=torch.float32, device="cuda")
+    ms = {"forward": _timed(lambda: binding.eval(rec, N, xd, prm, ws=ws_e, out=sdf), reps)}
+    ms["forward_stats"] = _timed(lambda: binding.eval(rec, N, xd, prm, stats=True, ws=ws_g), reps)
+    ms["forward_grad"] = _timed(lambda: binding.eval(rec, N, xd, prm, grad=True, ws=ws_g), reps)
+    phi, st = binding.eval(rec, N, xd, prm, stats=True, ws=ws_g)
+    gout = torch.where(md, 2.0 * phi, torch.zeros_like(phi))
+    ms["grad_x"] = _timed(lambda: binding.grad_x(rec, N, xd, st, gout, prm, ws_g), reps)
+    ms["grad_a"] = _timed(lambda: binding.backward_params(rec, p, n, a, xd, st, gout, prm, ws_b), reps)
+    ms["build"] = _timed(lambda: binding.cloud_build(p, n, a, prm, rec), reps)
+    pairs = float(N) * Q
+    out = {"workload": f"ellipsoid, N={N}, Q={Q} (half near-surface), loss = sum phi^2 over the near half",
+           "N": N, "Q": Q, "ms": ms, "pairs_per_s": {k: pairs / (v * 1e-3) for k, v in ms.items() if k != "build"},
+           "vs_forward": {k: ms["forward"] / v for k, v in ms.items() if k != "build"},
+           "train_step_ms": ms["forward_stats"] + ms["grad_x"] + ms["grad_a"]}
+    log(f"diff: forward {ms['forward']:.2f} ms, +stats {ms['forward_stats']:.2f}, fused grad "
+        f"{ms['forward_grad']:.2f}, grad_x {ms['grad_x']:.2f}, grad_a {ms['grad_a']:.2f} ms")
+    return out
+
+
+def large_bench(reps: int, trace: bool):
+    """Large photogrammetry-like cloud: N = 2^20 points on 32 primitives (density
+    varying 10x, sigma 0.005 noise, 3% outliers), 2^20 uniform queries; and,
+    if asked, a 1024^2 sphere trace of 64 steps with normals."""
+    import torch
+    from paper_2607_16946_amd import binding, synth
+    t0 = time.perf_counter()
+    cl, x = synth.large()
+    log(f"large: generated N={cl.N} Q={x.shape[0]} in {time.perf_counter() - t0:.1f} s")
+    N, Q = cl.N, x.shape[0]
+    p, n, a, xd = (torch.from_numpy(v).cuda() for v in (cl.p, cl.n, cl.a, x))
+    prm = binding.make_params()
+    rec = binding.cloud_build(p, n, a, prm)
+    ws = torch.empty(binding.eval_ws_bytes(N, Q, prm), dtype=torch.uint8, device="cuda")
+    sdf = torch.empty(Q, dtype=torch.float32, device="cuda")
+    ms_eval = _timed(lambda: binding.eval(rec, N, xd, prm, ws=ws, out=sdf), reps)
+    ms_build = _timed(lambda: binding.cloud_build(p, n, a, prm, rec), reps)
+    out = {"workload": f"large: {N} points on 32 primitives, density varying 10x, sigma 0.005 noise, "
+                       f"3% outliers; {Q} uniform queries", "N": N, "Q": Q,
+           "eval_ms": ms_eval, "build_ms": ms_build, "pairs_per_s": float(N) * Q / (ms_eval * 1e-3)}
+    log(f"large: eval {ms_eval:.1f} ms ({out['pairs_per_s']:.4g} pairs/s), build {ms_build:.2f} ms")
+    if trace:
+        import numpy as np
+        lo, hi = cl.p.min(0), cl.p.max(0)
+        D = float(np.linalg.norm(hi - lo))
+        ctr = 0.5 * (lo + hi)
+        o, d = synth.camera_rays(1024, radius=1.5 * D, fov_deg=45.0, seed=5, target=tuple(ctr))
+        d = d.astype(np.float64)
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        od, dd = torch.from_numpy(o.astype(np.float32)).cuda(), torch.from_numpy(d.astype(np.float32)).cuda()
+        R = od.shape[0]
+        binding.trace(rec, N, od[:4096], dd[:4096], steps=4, eps=1e-4 * D, tmax=3.0 * D, params=prm)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        t, hit, ns, nrm = binding.trace(rec, N, od, dd, steps=64, eps=1e-4 * D, tmax=3.0 * D, params=prm)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t1
+        steps_sum = float(torch.clamp(ns, max=64).sum())
+        out["trace"] = {"rays": R, "steps": 64, "seconds": sec, "hits": int(hit.sum()),
+                        "ray_steps": steps_sum, "pairs_per_s": steps_sum * N / sec}
+        log(f"large: trace {R} rays in {sec:.2f} s, {int(hit.sum())} hits, {steps_sum:.4g} ray-steps")
+    return out
 
 
 def serving_bench(n_requests: int, n_warmup: int, loads, n_clouds: int = 64, budget_gib: int = 64,
@@ -235,7 +338,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--grid", type=int, default=128, help="query lattice resolution (default 128)")
     ap.add_argument("--points", type=int, default=131072)
-    ap.add_argument("--cpu-sample", type=int, default=8192)
+    ap.add_argument("--cpu-sample", type=int, default=98304,
+                    help="oracle sample (queries); about 10 s on 16 host threads at the default size")
+    ap.add_argument("--no-diff", action="store_true", help="skip the differentiation workload")
+    ap.add_argument("--no-large", action="store_true", help="skip the large (2^20 x 2^20) workload")
+    ap.add_argument("--large-trace", action="store_true", help="also run the 1024^2 x 64-step trace of it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-mode measurement")
@@ -348,6 +455,10 @@ def main():
         "stages_ms": stage,
         "roofline": roofline,
     }
+    if not args.no_diff:
+        out["diff"] = diff_bench(5)
+    if not args.no_large:
+        out["large"] = large_bench(3, args.large_trace)
     if not args.no_serving:
         out["serving"] = serving_bench(args.serve_requests, args.serve_warmup, loads)
     if not args.no_cpu_baseline:
