@@ -110,6 +110,41 @@ def test_mid_full_size_sampled():
     _say("anchored points:", info.n_anchored)
 
 
+def _mixed_coefficients_cloud(N=6000, seed=21):
+    """mid-shaped cloud with general coefficients interleaved in input order:
+    shift a00, tilt a10/a01, both, and nearly flat points (large L, anchored
+    form), next to the analytic ones."""
+    cl, _ = synth.mid(N=N, grid=4)
+    rng = np.random.default_rng(seed)
+    a = cl.a.astype(np.float64).copy()
+    kind = rng.integers(0, 5, size=N)
+    a[kind == 1, 0] = rng.normal(0, 0.01, size=(kind == 1).sum())                 # shift
+    a[kind == 2, 1:3] = rng.normal(0, 0.2, size=((kind == 2).sum(), 2))          # tilt
+    both = kind == 3
+    a[both, 0] = rng.normal(0, 0.01, size=both.sum())
+    a[both, 1:3] = rng.normal(0, 0.2, size=(both.sum(), 2))
+    a[kind == 4, 4:6] *= 1e-4                                                     # nearly flat: large L
+    return synth.Cloud(cl.p, cl.n, a.astype(np.float32), {})
+
+
+def test_mixed_coefficients_and_forms():
+    cl = _mixed_coefficients_cloud()
+    c = _build(cl)
+    info = c.info()
+    tor = oracle.fit(cl.p, cl.n, cl.a)
+    D = oracle.bbox_diag(cl.p)
+    L = 1.0 / np.abs(tor.kminf)
+    _say(f"mixed coefficients: direct {info.n_direct}, anchored {info.n_anchored}")
+    assert info.n_direct == int(np.sum(L <= 4.0 * D)) and 0 < info.n_anchored < cl.N
+    dec = c.decode().cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(dec[:, 0:3] - tor.c).max(axis=1) <= 2e-6 * (np.abs(tor.c).max(axis=1) + 1.0))
+    assert np.all(np.abs(dec[:, 9] - L) <= 1e-6 * L)
+    x = np.random.default_rng(5).uniform(-1.2, 1.2, size=(2500, 3)).astype(np.float32)
+    got = c(_dev(x)).cpu().numpy()
+    ref = oracle.eval_sdf(cl.p, tor, x)
+    _check_close(got, ref, D, "mixed coefficients")
+
+
 @pytest.mark.parametrize("Q", [1, 7, 255, 1000, 1025, 70001])
 def test_ragged_query_counts(Q):
     cl, _ = synth.mid(N=3000, grid=4)
