@@ -128,8 +128,11 @@ size_t back_ws_bytes(int64_t N, int64_t Q);
 int launch_backward(const void* rec, int64_t N, const float* p, const float* n, const float* a, const float* x,
                     int64_t Q, const float* gout, const float* stats, float* ga, float C, void* ws, hipStream_t st);
 
-// Sphere tracing (point split fixed by N so that rays do not affect each other).
-Plan trace_plan(int64_t N, int64_t Q, const pts_params& P);
+// Sphere tracing (point splits fixed by N so that rays do not affect each other).
+int march_splits(int64_t N);
+Plan march_plan(int64_t N, int64_t Q, const pts_params& P);
+Plan normal_plan(int64_t N, int64_t Q, const pts_params& P);
+size_t trace_eval_ws_bytes(int64_t N, int64_t R, const pts_params& P);  // evaluation part of the workspace
 size_t trace_ws_bytes(int64_t N, int64_t R, const pts_params& P);
 int launch_trace(const void* rec, int64_t N, const float* org, const float* dir, int64_t R, int steps, float eps,
                  float tmax, float* t, float* nrm, int32_t* hit, int32_t* nsteps, const pts_params& P, void* ws,

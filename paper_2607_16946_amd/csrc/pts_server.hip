@@ -26,9 +26,10 @@
 // A request's region returns to the arena only after the device work that
 // uses it has completed (observed through an event), so reuse never races.
 //
-// Determinism.  A request's point split depends only on its cloud's N, and a
-// query's sums only on that split and the tile boundaries, so results are
-// bitwise the same alone or packed with any other requests.
+// Determinism.  A request's point splits (march_splits / normal_plan of the
+// tracer) depend only on its cloud's N, and a query's sums only on the split
+// and the tile boundaries, so results are bitwise the same alone or packed
+// with any other requests, and equal to pts_trace's for trace requests.
 //
 // Mock mode.  With cfg.mock the scheduler runs unchanged without a device: a
 // launch "takes" pairs / mock_pairs_per_s seconds and outputs are a pattern,
@@ -57,20 +58,6 @@ using Clock = std::chrono::steady_clock;
 double now_s() { return std::chrono::duration<double>(Clock::now().time_since_epoch()).count(); }
 
 constexpr int kSlots = 2;  // launches in flight at once
-
-// Point split of every request on a cloud of N points: the largest power of
-// two <= 64 that leaves each split at least two farthest-point tiles.
-int serve_splits(int64_t N) {
-  const int64_t tiles = (N + kTile1 - 1) / kTile1;
-  int S = 1;
-  while (S < 64 && tiles >= int64_t(4) * S) S *= 2;
-  return S;
-}
-Plan serve_plan(int64_t N, int64_t Q) {
-  pts_params F{};
-  F.splits = serve_splits(N);
-  return make_plan(N, Q, &F);
-}
 
 // First-fit allocator over byte offsets [0, size) with coalescing.
 class Arena {
@@ -136,7 +123,7 @@ struct ReqLayout {
   size_t total = 0;
 };
 
-ReqLayout req_layout(int kind, int64_t n, const Plan& plan) {
+ReqLayout req_layout(int kind, int64_t n, const Plan& plan, const pts_params& P, int64_t N) {
   ReqLayout L;
   size_t w = 0;
   auto take = [&](size_t b) {
@@ -167,7 +154,7 @@ ReqLayout req_layout(int kind, int64_t n, const Plan& plan) {
     L.xq = take(size_t(n) * 12);
     L.phi = take(size_t(n) * 4);
     L.g = take(size_t(n) * 12);
-    L.nws = take(grad_ws_bytes(plan, n));
+    L.nws = take(trace_eval_ws_bytes(N, n, P));
   }
   L.total = w;
   return L;
@@ -200,7 +187,8 @@ struct Req {
   // cloud and plan (copied at submit; a cloud cannot be removed under a request)
   size_t cloud_off = 0;
   int64_t N = 0;
-  Plan plan{};
+  Plan plan{};   // split of query requests and of trace steps
+  Plan nplan{};  // split of a trace request's normals
   ReqLayout lay;
   size_t dev_off = 0;
   bool admitted = false;
@@ -344,7 +332,7 @@ class Server {
     auto it = clouds_.find(id);
     if (it == clouds_.end()) return fail(PTS_ENOTFOUND, "unknown cloud");
     if (N) *N = it->second.N;
-    if (splits) *splits = serve_splits(it->second.N);
+    if (splits) *splits = march_splits(it->second.N);
     return PTS_OK;
   }
 
@@ -384,13 +372,14 @@ class Server {
     q->N = c.N;
     const int64_t n = r->count;
     if (n > 0) {
-      q->plan = serve_plan(c.N, n);
+      q->plan = march_plan(c.N, n, P_);
+      q->nplan = normal_plan(c.N, n, P_);
       if (work_descs(n, q->plan.S) > max_work_ || comb_descs(n) > max_comb_) {
         std::lock_guard<std::mutex> lk(mu_);
         ++rejected_;
         return fail(PTS_EINVAL, "request needs more workgroups than one launch holds; split it");
       }
-      q->lay = req_layout(r->kind, n, q->plan);
+      q->lay = req_layout(r->kind, n, q->plan, P_, c.N);
     }
     {
       std::lock_guard<std::mutex> lk(mu_);
@@ -798,7 +787,7 @@ class Server {
       rc = trace_normals_all(base_ + q->cloud_off, q->N, dev<float>(q, q->lay.org), dev<float>(q, q->lay.dir),
                              dev<float>(q, q->lay.t), dev<int32_t>(q, q->lay.hit), n, dev<int32_t>(q, q->lay.keep),
                              dev<float>(q, q->lay.xq), dev<float>(q, q->lay.phi), dev<float>(q, q->lay.g),
-                             dev<float>(q, q->lay.nrm), q->plan, P_.C, dev<void>(q, q->lay.nws), st);
+                             dev<float>(q, q->lay.nrm), q->nplan, P_.C, dev<void>(q, q->lay.nws), st);
     char* s = q->stage + size_t(n) * 24;
     if (!rc)
       rc = check_hip(hipMemcpyAsync(s, dev<float>(q, q->lay.t), size_t(n) * 4, hipMemcpyDeviceToHost, st), "copy t");

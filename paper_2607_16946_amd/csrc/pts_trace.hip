@@ -7,9 +7,12 @@
 // returned.  Each step evaluates all still-active rays with the evaluation
 // kernels (farthest-point and blend sweeps, split combine), then a small
 // kernel advances the rays and a deterministic stream compaction keeps the
-// active ones.  The point split is a function of N only, so every ray's phi is
-// computed in the same order whatever the other rays do.
+// active ones.  The point splits (of the march, and of the normals' gradient
+// sweep) are functions of N only, so every ray's phi and normal are computed in
+// the same order whatever the other rays do.
 #include "pts_device.h"
+
+#include <algorithm>
 
 namespace pts {
 namespace {
@@ -199,19 +202,36 @@ int compact(const int32_t* keep, const int32_t* act_in, int64_t n, int32_t* act_
 
 }  // namespace
 
-Plan trace_plan(int64_t N, int64_t Q, const pts_params& P) {
+// Point split of the march: the largest power of two <= 64 that leaves every
+// split at least two farthest-point tiles.  A function of N only, so a ray's
+// phi does not depend on which other rays are still active.
+int march_splits(int64_t N) {
+  const int64_t tiles = (N + kTile1 - 1) / kTile1;
+  int S = 1;
+  while (S < 64 && tiles >= int64_t(4) * S) S *= 2;
+  return S;
+}
+
+Plan march_plan(int64_t N, int64_t Q, const pts_params& P) {
   pts_params F = P;
-  if (F.splits == 0) {
-    const int64_t tiles = (N + kTile1 - 1) / kTile1;
-    int S = 1;
-    while (S < 8 && tiles >= int64_t(2) * S * 2) S *= 2;
-    F.splits = S;
-  }
+  if (F.splits == 0) F.splits = march_splits(N);
   return make_plan(N, Q, &F);
 }
 
+// The normals' gradient sweep keeps at most 8 splits (its workspace grows by
+// 32 bytes per ray and split); also a function of N only.
+Plan normal_plan(int64_t N, int64_t Q, const pts_params& P) {
+  pts_params F = P;
+  if (F.splits == 0) F.splits = std::min(march_splits(N), 8);
+  return make_plan(N, Q, &F);
+}
+
+size_t trace_eval_ws_bytes(int64_t N, int64_t R, const pts_params& P) {
+  return std::max(eval_ws_bytes(march_plan(N, R, P), R), grad_ws_bytes(normal_plan(N, R, P), R));
+}
+
 size_t trace_ws_bytes(int64_t N, int64_t R, const pts_params& P) {
-  return trace_fixed_bytes(R) + grad_ws_bytes(trace_plan(N, R, P), R);
+  return trace_fixed_bytes(R) + trace_eval_ws_bytes(N, R, P);
 }
 
 int launch_trace(const void* rec, int64_t N, const float* org, const float* dir, int64_t R, int steps, float eps,
@@ -224,7 +244,7 @@ int launch_trace(const void* rec, int64_t N, const float* org, const float* dir,
   int32_t* nxt = v.act1;
   int64_t na = R;
   for (int k = 0; k < steps && na > 0; ++k) {
-    const Plan plan = trace_plan(N, na, P);
+    const Plan plan = march_plan(N, na, P);
     const WsView wv = ws_view(plan, na, v.eval);
     hipLaunchKernelGGL(k_positions, dim3(nblk(na)), dim3(kBlock), 0, st, act, na, org, dir, t, v.xq);
     if (int rc = launch_far(rec, N, v.xq, na, plan, wv, st)) return rc;
@@ -245,7 +265,7 @@ int launch_trace(const void* rec, int64_t N, const float* org, const float* dir,
   int64_t nh = 0;
   if (int rc = compact(hit, nxt, R, act, v, &nh, st)) return rc;
   if (nh == 0) return PTS_OK;
-  const Plan plan = trace_plan(N, nh, P);
+  const Plan plan = normal_plan(N, nh, P);
   const WsView wv = ws_view(plan, nh, v.eval);
   hipLaunchKernelGGL(k_positions, dim3(nblk(nh)), dim3(kBlock), 0, st, act, nh, org, dir, t, v.xq);
   if (int rc = launch_far_arg(rec, N, v.xq, nh, plan, wv, st)) return rc;

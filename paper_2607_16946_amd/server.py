@@ -80,7 +80,8 @@ class Server:
         return int(cid.value)
 
     def cloud_plan(self, cid: int) -> tuple[int, int]:
-        """(N, splits): pts_eval / pts_trace with params.splits = splits give the server's bits."""
+        """(N, splits): pts_eval with params.splits = splits gives the server's query results bit for bit
+        (trace requests match pts_trace with default splits)."""
         N, S = ctypes.c_int64(0), ctypes.c_int(0)
         self._rc(self._L.pts_server_cloud_plan(self._handle(), int(cid), ctypes.byref(N), ctypes.byref(S)))
         return int(N.value), int(S.value)
