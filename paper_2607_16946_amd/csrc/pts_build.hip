@@ -4,14 +4,20 @@
 // Pipeline (all on `stream`, deterministic):
 //   k_init     header defaults
 //   k_bbox     bounding box + input validation (order-preserving atomics)
-//   k_flags    per point: which torus form the blend kernels use; per-block counts
+//   k_flags    per point: which torus form the blend kernels use, per-block
+//              counts, and the sort key (form bit, then the 24-bit Morton code
+//              of the point in a 256^3 grid over the bbox)
 //   k_scan     exclusive scan of the per-block counts (one workgroup)
-//   k_fit      per point: FP64 torus fit, FP32 record written to its slot
+//   k_rhist / k_exscan / k_rscatter
+//              stable LSD radix sort of (key, input index), 4 bits per pass
+//   k_fit      per slot: FP64 torus fit of its point, FP32 record
+//   k_units    bounding sphere and extreme point of every kUnit slots
 //
 // Slots: points whose torus radius L = 1/|kappa_min| is at most 4 D (D = bbox
-// diagonal) come first, in input order ("direct" form); the rest follow, in
-// input order ("anchored" form, which stays accurate in FP32 for very large
-// radii).  perm[slot] is the input index.
+// diagonal) come first ("direct" form), the rest ("anchored" form, which stays
+// accurate in FP32 for very large radii) after; within each group points are
+// in Morton order (ties in input order), so consecutive slots are close in
+// space and a unit's bounding sphere is small.  perm[slot] is the input index.
 //
 // Record of one point, 5 x float4, coordinates relative to the bbox center:
 //   f0 = (p, L)                      L = 1/|kappa_min| (floored)
@@ -131,17 +137,99 @@ __device__ inline double radius_L(const float* aa, double kfloor) {
   return 1.0 / fabs(clampmag(kmin, kfloor));
 }
 
-__global__ __launch_bounds__(kBlock) void k_flags(const float* __restrict__ a, int64_t N, float kfloor_rel,
-                                                  Header* h, int32_t* flag, int32_t* blk) {
+// Spread the low 8 bits of v to every third bit.
+__device__ inline uint32_t spread3(uint32_t v) {
+  uint32_t r = 0;
+  for (int k = 0; k < 8; ++k) r |= ((v >> k) & 1u) << (3 * k);
+  return r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_flags(const float* __restrict__ p, const float* __restrict__ a,
+                                                  int64_t N, float kfloor_rel, Header* h, int32_t* flag,
+                                                  int32_t* blk, uint32_t* key, int32_t* idx) {
   const BoxInfo b = box_info(h, kfloor_rel);
   const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   int direct = 0;
   if (i < N) {
     direct = radius_L(a + 6 * i, b.kfloor) <= b.lmax ? 1 : 0;
     flag[i] = direct;
+    uint32_t m = 0;
+    for (int k = 0; k < 3; ++k) {
+      const double ext = b.hi[k] - b.lo[k];
+      int c = ext > 0.0 ? int((double(p[3 * i + k]) - b.lo[k]) / ext * 256.0) : 0;
+      c = c < 0 ? 0 : (c > 255 ? 255 : c);
+      m |= spread3(uint32_t(c)) << k;
+    }
+    key[i] = (direct ? 0u : (1u << 24)) | m;
+    idx[i] = int32_t(i);
   }
   int cnt = __syncthreads_count(direct);
   if (threadIdx.x == 0) blk[blockIdx.x] = cnt;
+}
+
+// Radix sort, pass histogram: counts of the 4-bit digit at `shift` in each
+// block of kBlock keys, digit-major: hist[d * nb + block].
+__global__ __launch_bounds__(kBlock) void k_rhist(const uint32_t* __restrict__ key, int64_t N, int shift,
+                                                  int32_t* __restrict__ hist, int64_t nb) {
+  __shared__ int32_t cnt[1 << kSortBits];
+  if (threadIdx.x < (1 << kSortBits)) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < N) atomicAdd(&cnt[(key[i] >> shift) & ((1u << kSortBits) - 1)], 1);
+  __syncthreads();
+  if (threadIdx.x < (1 << kSortBits)) hist[int64_t(threadIdx.x) * nb + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Exclusive scan of n int32 in place (one workgroup of 1024 threads).
+__global__ __launch_bounds__(1024) void k_exscan(int32_t* __restrict__ v, int64_t n) {
+  __shared__ int32_t s[1024];
+  __shared__ int32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < n; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    const int32_t x = i < n ? v[i] : 0;
+    s[threadIdx.x] = x;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const int32_t t = threadIdx.x >= unsigned(o) ? s[threadIdx.x - o] : 0;
+      __syncthreads();
+      s[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < n) v[i] = carry + s[threadIdx.x] - x;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry += s[1023];
+    __syncthreads();
+  }
+}
+
+// Radix sort, pass scatter: each key goes to its digit's offset for its block
+// plus its rank among the block's keys with the same digit (stable).
+__global__ __launch_bounds__(kBlock) void k_rscatter(const uint32_t* __restrict__ kin, const int32_t* __restrict__ iin,
+                                                     uint32_t* __restrict__ kout, int32_t* __restrict__ iout,
+                                                     int64_t N, int shift, const int32_t* __restrict__ hist,
+                                                     int64_t nb) {
+  constexpr int kD = 1 << kSortBits;
+  __shared__ int32_t wc[kBlock / 64][kD];
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  const bool valid = i < N;
+  const uint32_t k = valid ? kin[i] : 0u;
+  const int d = valid ? int((k >> shift) & (kD - 1)) : kD;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  int rank = 0;
+  for (int v = 0; v < kD; ++v) {
+    const uint64_t m = __ballot(d == v);
+    if (lane == 0) wc[wave][v] = __popcll(m);
+    if (d == v) rank = __popcll(m & lt);
+  }
+  __syncthreads();
+  if (!valid) return;
+  for (int w = 0; w < wave; ++w) rank += wc[w][d];
+  const int64_t dst = int64_t(hist[int64_t(d) * nb + blockIdx.x]) + rank;
+  kout[dst] = k;
+  iout[dst] = iin[i];
 }
 
 // Exclusive scan of nb block counts in place into blk[nb + b]; header totals.
@@ -184,26 +272,14 @@ __global__ __launch_bounds__(1024) void k_scan(int32_t* blk, int64_t nb, int64_t
 
 __global__ __launch_bounds__(kBlock) void k_fit(const float* __restrict__ p, const float* __restrict__ n,
                                                 const float* __restrict__ a, int64_t N, float kfloor_rel,
-                                                const Header* __restrict__ h, const int32_t* __restrict__ flag,
-                                                const int32_t* __restrict__ blk, int64_t nb,
+                                                const Header* __restrict__ h, const int32_t* __restrict__ order,
                                                 float4* __restrict__ pos4, float4* __restrict__ rec,
                                                 int32_t* __restrict__ perm) {
-  __shared__ int32_t s_wave[kBlock / 64];
   const BoxInfo b = box_info(h, kfloor_rel);
-  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  const int direct = i < N ? flag[i] : 0;
-  // rank of this point among the direct points of its workgroup
-  const uint64_t ball = __ballot(direct);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int below = __popcll(ball & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
-  if (lane == 0) s_wave[wave] = __popcll(ball);
-  __syncthreads();
-  int before = 0;
-  for (int w = 0; w < wave; ++w) before += s_wave[w];
-  if (i >= N) return;
-  const int64_t direct_before = int64_t(blk[nb + blockIdx.x]) + before + below;
-  const int64_t n_direct = h->n_direct;
-  const int64_t slot = direct ? direct_before : n_direct + (i - direct_before);
+  const int64_t slot = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (slot >= N) return;
+  const int64_t i = order[slot];
+  const bool direct = slot < h->n_direct;
 
   double pd[3], nd[3], ad[6];
   for (int k = 0; k < 3; ++k) { pd[k] = p[3 * i + k]; nd[k] = n[3 * i + k]; }
@@ -229,6 +305,45 @@ __global__ __launch_bounds__(kBlock) void k_fit(const float* __restrict__ p, con
   R[3] = make_float4(float(F.k[0]), float(F.k[1]), float(F.k[2]), float(-dot(orel, F.k)));
   R[4] = make_float4(float(F.R), float(F.zeta * F.r), float(F.sgn), float(-F.sgn * F.r));
   perm[slot] = int32_t(i);
+}
+
+// Bounds of each unit of kUnit consecutive slots (one wave per unit): center
+// c = midpoint of the unit's box, radius r >= max |p - c| (FP64, rounded up),
+// and the unit's point e farthest from c (lowest slot among ties).
+__global__ __launch_bounds__(kBlock) void k_units(const float4* __restrict__ pos4, int64_t N,
+                                                  float4* __restrict__ ub) {
+  const int64_t u = int64_t(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t nunit = (N + kUnit - 1) / kUnit;
+  if (u >= nunit) return;                       // whole wave leaves together
+  const int64_t s = u * kUnit + lane;
+  const bool valid = s < N;
+  float px = 0.f, py = 0.f, pz = 0.f;
+  if (valid) {
+    const float4 P = pos4[s];
+    px = -0.5f * P.x; py = -0.5f * P.y; pz = -0.5f * P.z;   // exact: pos4 holds -2p
+  }
+  float lo[3] = {valid ? px : 3.0e38f, valid ? py : 3.0e38f, valid ? pz : 3.0e38f};
+  float hi[3] = {valid ? px : -3.0e38f, valid ? py : -3.0e38f, valid ? pz : -3.0e38f};
+  for (int o = 32; o > 0; o >>= 1)
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = fminf(lo[k], __shfl_xor(lo[k], o));
+      hi[k] = fmaxf(hi[k], __shfl_xor(hi[k], o));
+    }
+  const float cx = 0.5f * (lo[0] + hi[0]), cy = 0.5f * (lo[1] + hi[1]), cz = 0.5f * (lo[2] + hi[2]);
+  const double dx = double(px) - cx, dy = double(py) - cy, dz = double(pz) - cz;
+  double d = valid ? sqrt(dx * dx + dy * dy + dz * dz) : -1.0;
+  int who = valid ? lane : 64;
+  for (int o = 32; o > 0; o >>= 1) {
+    const double od = __shfl_xor(d, o);
+    const int ow = __shfl_xor(who, o);
+    if (od > d || (od == d && ow < who)) { d = od; who = ow; }
+  }
+  const float ex = __shfl(px, who), ey = __shfl(py, who), ez = __shfl(pz, who);
+  if (lane == 0) {
+    ub[2 * u] = make_float4(cx, cy, cz, float(d * (1.0 + 1e-6)) + 1e-30f);
+    ub[2 * u + 1] = make_float4(ex, ey, ez, 0.f);
+  }
 }
 
 // Original-order view of the fitted tori (inspection and tests).
@@ -271,11 +386,27 @@ int launch_build(const float* p, const float* n, const float* a, int64_t N, floa
   hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, h, N);
   const unsigned gb = unsigned(std::min<int64_t>(L.nblk, 2048));
   hipLaunchKernelGGL(k_bbox, dim3(gb), dim3(kBlock), 0, st, p, n, a, N, h);
-  hipLaunchKernelGGL(k_flags, dim3(nb), dim3(kBlock), 0, st, a, N, kfloor_rel, h, flag, blk);
+  uint32_t* key[2] = {reinterpret_cast<uint32_t*>(base + L.key),
+                      reinterpret_cast<uint32_t*>(base + L.key + align256(size_t(N) * 4))};
+  int32_t* idx[2] = {reinterpret_cast<int32_t*>(base + L.idx),
+                     reinterpret_cast<int32_t*>(base + L.idx + align256(size_t(N) * 4))};
+  int32_t* rhist = reinterpret_cast<int32_t*>(base + L.rhist);
+  hipLaunchKernelGGL(k_flags, dim3(nb), dim3(kBlock), 0, st, p, a, N, kfloor_rel, h, flag, blk, key[0], idx[0]);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, blk, int64_t(nb), N, kfloor_rel, h);
-  hipLaunchKernelGGL(k_fit, dim3(nb), dim3(kBlock), 0, st, p, n, a, N, kfloor_rel, h, flag, blk,
-                     int64_t(nb), reinterpret_cast<float4*>(base + L.pos), reinterpret_cast<float4*>(base + L.rec),
-                     reinterpret_cast<int32_t*>(base + L.perm));
+  int cur = 0;
+  for (int pass = 0; pass < kSortPasses; ++pass) {
+    const int shift = pass * kSortBits;
+    hipLaunchKernelGGL(k_rhist, dim3(nb), dim3(kBlock), 0, st, key[cur], N, shift, rhist, int64_t(nb));
+    hipLaunchKernelGGL(k_exscan, dim3(1), dim3(1024), 0, st, rhist, int64_t(nb) << kSortBits);
+    hipLaunchKernelGGL(k_rscatter, dim3(nb), dim3(kBlock), 0, st, key[cur], idx[cur], key[1 - cur], idx[1 - cur], N,
+                       shift, rhist, int64_t(nb));
+    cur = 1 - cur;
+  }
+  float4* pos4 = reinterpret_cast<float4*>(base + L.pos);
+  hipLaunchKernelGGL(k_fit, dim3(nb), dim3(kBlock), 0, st, p, n, a, N, kfloor_rel, h, idx[cur], pos4,
+                     reinterpret_cast<float4*>(base + L.rec), reinterpret_cast<int32_t*>(base + L.perm));
+  hipLaunchKernelGGL(k_units, dim3(unsigned((L.nunit + 3) / 4)), dim3(kBlock), 0, st, pos4, N,
+                     reinterpret_cast<float4*>(base + L.ub));
   return check_hip(hipGetLastError(), "build kernels");
 }
 

@@ -29,53 +29,143 @@ namespace pts {
 namespace {
 
 // ---------------------------------------------------------------------------
-// Sweep 1: squared distance to the farthest point, per split.
+// Sweep 1: squared distance to the farthest point, M^2 = max_i |x - p_i|^2.
 //   |x-p|^2 = |x|^2 + |p|^2 - 2<x,p>; the max is taken over (|p|^2 - 2<x,p>)
 //   (three FMAs and a max per pair) and |x|^2 is added once at the end.
+// Exact culling by units of kUnit consecutive slots (spatially sorted at
+// build time, with bounding spheres (c, r) and extreme points e):
+//   1. LB = max_u |x - e_u| <= M for each query of the workgroup;
+//   2. unit u can hold a point farther than LB (1 - 1e-5) only if
+//      |x - c_u| + r_u >= LB (1 - 1e-5) for some query of the workgroup;
+//   3. only the points of such units are swept, in ascending slot order.
+// A culled unit's points are at least 1e-5 M closer than the farthest point,
+// far beyond FP32 rounding of the swept values, so M^2 (and, with kArg, the
+// first slot attaining it) is exactly what a sweep over every point gives.
 // ---------------------------------------------------------------------------
-template <int QPL>
-__global__ __launch_bounds__(kBlock) void k_far(const Header* __restrict__ h, const float4* __restrict__ pos4,
-                                                const float* __restrict__ x, int64_t Q, int S, int64_t per_split,
-                                                float* __restrict__ far2) {
+constexpr int kChunkU = 256;            // units whose bounds are staged in LDS at once
+constexpr int kBatchU = kTile1 / kUnit;  // units per LDS tile of points
+
+template <int QPL, bool kArg>
+__global__ __launch_bounds__(kBlock) void k_far_cull(const Header* __restrict__ h, const float4* __restrict__ pos4,
+                                                     const float4* __restrict__ ub, const float* __restrict__ x,
+                                                     int64_t Q, float* __restrict__ far2,
+                                                     int32_t* __restrict__ farix) {
+  __shared__ float4 sb[kChunkU];
+  __shared__ uint32_t smask[kChunkU / 32];
+  __shared__ int32_t slist[kChunkU];
+  __shared__ int32_t scount;
   __shared__ float4 tile[kTile1];
-  const int split = int(blockIdx.x % unsigned(S));
-  const int64_t qb = blockIdx.x / unsigned(S);
   const int64_t N = h->N;
-  float qx[QPL], qy[QPL], qz[QPL], acc[QPL];
+  const int64_t U = (N + kUnit - 1) / kUnit;
+  const int64_t qb = blockIdx.x;
+  float qx[QPL], qy[QPL], qz[QPL], acc[QPL], lb[QPL];
+  int32_t ix[QPL];
+  bool ok[QPL];
 #pragma unroll
   for (int k = 0; k < QPL; ++k) {
-    QueryIn qi = load_query(x, qb * (kBlock * QPL) + k * kBlock + threadIdx.x, Q, h);
+    const QueryIn qi = load_query(x, qb * (kBlock * QPL) + k * kBlock + threadIdx.x, Q, h);
     qx[k] = qi.x; qy[k] = qi.y; qz[k] = qi.z;
+    ok[k] = qi.valid;
     acc[k] = -3.0e38f;
+    ix[k] = -1;
+    lb[k] = -1.f;
   }
-  const int64_t beg = int64_t(split) * per_split;
-  const int64_t end = min(N, beg + per_split);
-  for (int64_t t0 = beg; t0 < end; t0 += kTile1) {
-    const int cnt = int(min<int64_t>(kTile1, end - t0));
+  // 1. lower bound from the units' extreme points
+  for (int64_t c0 = 0; c0 < U; c0 += kChunkU) {
+    const int cnt = int(min<int64_t>(kChunkU, U - c0));
     __syncthreads();
-    for (int j = threadIdx.x; j < cnt; j += kBlock) tile[j] = pos4[t0 + j];
+    for (int j = threadIdx.x; j < cnt; j += kBlock) sb[j] = ub[2 * (c0 + j) + 1];
     __syncthreads();
-    int j = 0;
-    for (; j + 1 < cnt; j += 2) {
-      const float4 P0 = tile[j], P1 = tile[j + 1];
+    for (int j = 0; j < cnt; ++j) {
+      const float4 E = sb[j];
 #pragma unroll
       for (int k = 0; k < QPL; ++k) {
-        const float a0 = fmaf(qz[k], P0.z, fmaf(qy[k], P0.y, fmaf(qx[k], P0.x, P0.w)));
-        const float a1 = fmaf(qz[k], P1.z, fmaf(qy[k], P1.y, fmaf(qx[k], P1.x, P1.w)));
-        acc[k] = fmaxf(acc[k], fmaxf(a0, a1));
+        const float dx = qx[k] - E.x, dy = qy[k] - E.y, dz = qz[k] - E.z;
+        lb[k] = fmaxf(lb[k], fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
       }
     }
-    if (j < cnt) {
-      const float4 P0 = tile[j];
+  }
 #pragma unroll
-      for (int k = 0; k < QPL; ++k)
-        acc[k] = fmaxf(acc[k], fmaf(qz[k], P0.z, fmaf(qy[k], P0.y, fmaf(qx[k], P0.x, P0.w))));
+  for (int k = 0; k < QPL; ++k) {
+    ok[k] = ok[k] && lb[k] >= 0.f;              // a query with a NaN coordinate needs no unit: M is NaN
+    lb[k] = sqrtf(fmaxf(lb[k], 0.f)) * (1.f - 1e-5f);
+  }
+  // 2./3. per chunk of units: mark the needed ones, list them, sweep their points
+  for (int64_t c0 = 0; c0 < U; c0 += kChunkU) {
+    const int cnt = int(min<int64_t>(kChunkU, U - c0));
+    __syncthreads();
+    for (int j = threadIdx.x; j < cnt; j += kBlock) sb[j] = ub[2 * (c0 + j)];
+    for (int j = threadIdx.x; j < kChunkU / 32; j += kBlock) smask[j] = 0u;
+    __syncthreads();
+    for (int j = 0; j < cnt; ++j) {
+      const float4 C = sb[j];
+      bool need = false;
+#pragma unroll
+      for (int k = 0; k < QPL; ++k) {
+        const float t = lb[k] - C.w;
+        const float dx = qx[k] - C.x, dy = qy[k] - C.y, dz = qz[k] - C.z;
+        const float dc2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        need = need || (ok[k] && (t <= 0.f || !(dc2 < t * t)));
+      }
+      if (__ballot(need) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&smask[j >> 5], 1u << (j & 31));
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {  // ascending list of the needed units (first wave)
+      const int w = int(threadIdx.x);
+      const uint32_t bits = w < kChunkU / 32 ? smask[w] : 0u;
+      const int pc = __popc(bits);
+      int incl = pc;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o);
+        if (w >= o) incl += t;
+      }
+      int pos = incl - pc;
+      for (uint32_t b = bits; b != 0u; b &= b - 1u) slist[pos++] = int32_t(c0) + w * 32 + (__ffs(b) - 1);
+      if (w == 63) scount = incl;
+    }
+    __syncthreads();
+    const int nlist = scount;
+    for (int b0 = 0; b0 < nlist; b0 += kBatchU) {
+      const int nbu = min(kBatchU, nlist - b0);
+      const int cntp = nbu * kUnit;
+      __syncthreads();
+      for (int t = threadIdx.x; t < cntp; t += kBlock) {
+        const int64_t sl = int64_t(slist[b0 + t / kUnit]) * kUnit + (t % kUnit);
+        tile[t] = sl < N ? pos4[sl] : make_float4(0.f, 0.f, 0.f, -3.0e38f);
+      }
+      __syncthreads();
+      if (kArg) {
+        for (int u = 0; u < nbu; ++u) {
+          const int32_t base = slist[b0 + u] * kUnit;
+          for (int j = 0; j < kUnit; ++j) {
+            const float4 P = tile[u * kUnit + j];
+#pragma unroll
+            for (int k = 0; k < QPL; ++k) {
+              const float a = fmaf(qz[k], P.z, fmaf(qy[k], P.y, fmaf(qx[k], P.x, P.w)));
+              if (a > acc[k]) { acc[k] = a; ix[k] = base + j; }
+            }
+          }
+        }
+      } else {
+        for (int j = 0; j < cntp; j += 2) {
+          const float4 P0 = tile[j], P1 = tile[j + 1];
+#pragma unroll
+          for (int k = 0; k < QPL; ++k) {
+            const float a0 = fmaf(qz[k], P0.z, fmaf(qy[k], P0.y, fmaf(qx[k], P0.x, P0.w)));
+            const float a1 = fmaf(qz[k], P1.z, fmaf(qy[k], P1.y, fmaf(qx[k], P1.x, P1.w)));
+            acc[k] = fmaxf(acc[k], fmaxf(a0, a1));
+          }
+        }
+      }
     }
   }
 #pragma unroll
   for (int k = 0; k < QPL; ++k) {
     const int64_t q = qb * (kBlock * QPL) + k * kBlock + threadIdx.x;
-    if (q < Q) far2[int64_t(split) * Q + q] = acc[k] + fmaf(qz[k], qz[k], fmaf(qy[k], qy[k], qx[k] * qx[k]));
+    if (q < Q) {
+      far2[q] = acc[k] + fmaf(qz[k], qz[k], fmaf(qy[k], qy[k], qx[k] * qx[k]));
+      if (kArg) farix[q] = ix[k];
+    }
   }
 }
 
@@ -100,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_blend(const Header* __restrict__ h, 
     qx[k] = qi.x; qy[k] = qi.y; qz[k] = qi.z;
     float M = 0.f;
     nl[k] = 0.f;
-    if (qi.valid) far_of(far2, S, Q, q, C2, M, nl[k]);
+    if (qi.valid) far_of(far2, 1, Q, q, C2, M, nl[k]);
     num[k] = 0.f;
     den[k] = 0.f;
   }
@@ -166,11 +256,11 @@ __global__ __launch_bounds__(kBlock) void k_combine(const float2* __restrict__ p
   sdf[q] = num / den;
 }
 
-template <int QPL>
-void launch_far_q(const Header* h, const float4* pos4, const float* x, int64_t Q, const Plan& plan, float* far2,
-                  hipStream_t st) {
-  hipLaunchKernelGGL(k_far<QPL>, dim3(unsigned(plan.nqb * plan.S)), dim3(kBlock), 0, st, h, pos4, x, Q, plan.S,
-                     plan.per_split, far2);
+template <int QPL, bool kArg>
+void launch_far_q(const Header* h, const float4* pos4, const float4* ub, const float* x, int64_t Q, int64_t nqb,
+                  float* far2, int32_t* farix, hipStream_t st) {
+  hipLaunchKernelGGL((k_far_cull<QPL, kArg>), dim3(unsigned(nqb)), dim3(kBlock), 0, st, h, pos4, ub, x, Q, far2,
+                     farix);
 }
 
 template <int QPL>
@@ -208,19 +298,37 @@ WsView ws_view(const Plan& plan, int64_t Q, void* ws) {
   return v;
 }
 
-int launch_far(const void* rec, int64_t N, const float* x, int64_t Q, const Plan& plan, const WsView& ws,
-               hipStream_t st) {
+int launch_far_cull(const void* rec, int64_t N, const float* x, int64_t Q, int qpl, float* far2, int32_t* farix,
+                    hipStream_t st) {
   const Layout L(N);
   const char* base = static_cast<const char*>(rec);
   const Header* h = reinterpret_cast<const Header*>(base);
   const float4* pos4 = reinterpret_cast<const float4*>(base + L.pos);
-  switch (plan.qpl) {
-    case 1: launch_far_q<1>(h, pos4, x, Q, plan, ws.far2, st); break;
-    case 2: launch_far_q<2>(h, pos4, x, Q, plan, ws.far2, st); break;
-    case 8: launch_far_q<8>(h, pos4, x, Q, plan, ws.far2, st); break;
-    default: launch_far_q<4>(h, pos4, x, Q, plan, ws.far2, st); break;
+  const float4* ub = reinterpret_cast<const float4*>(base + L.ub);
+  // one workgroup per query block: keep at least 2048 of them (8 per CU) when
+  // there are queries enough, by lowering the queries per lane
+  int q = qpl >= 4 ? 4 : (qpl == 2 ? 2 : 1);
+  while (q > 1 && (Q + int64_t(kBlock) * q - 1) / (int64_t(kBlock) * q) < 2048) q /= 2;
+  const int64_t nqb = (Q + int64_t(kBlock) * q - 1) / (int64_t(kBlock) * q);
+  if (farix) {
+    switch (q) {
+      case 1: launch_far_q<1, true>(h, pos4, ub, x, Q, nqb, far2, farix, st); break;
+      case 2: launch_far_q<2, true>(h, pos4, ub, x, Q, nqb, far2, farix, st); break;
+      default: launch_far_q<4, true>(h, pos4, ub, x, Q, nqb, far2, farix, st); break;
+    }
+  } else {
+    switch (q) {
+      case 1: launch_far_q<1, false>(h, pos4, ub, x, Q, nqb, far2, nullptr, st); break;
+      case 2: launch_far_q<2, false>(h, pos4, ub, x, Q, nqb, far2, nullptr, st); break;
+      default: launch_far_q<4, false>(h, pos4, ub, x, Q, nqb, far2, nullptr, st); break;
+    }
   }
   return check_hip(hipGetLastError(), "farthest-point kernel");
+}
+
+int launch_far(const void* rec, int64_t N, const float* x, int64_t Q, const Plan& plan, const WsView& ws,
+               hipStream_t st) {
+  return launch_far_cull(rec, N, x, Q, plan.qpl, ws.far2, nullptr, st);
 }
 
 int launch_blend(const void* rec, int64_t N, const float* x, int64_t Q, float C, const Plan& plan,

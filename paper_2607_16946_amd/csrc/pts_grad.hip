@@ -13,7 +13,8 @@
 // core circle, query on a point): a subgradient of the nonsmooth sets.
 //
 // Kernels:
-//   k_far_arg        farthest-point sweep that also records the farthest slot
+//   (farthest-point sweep that also records the farthest slot: the culled
+//    sweep of pts_eval.hip with argmax tracking)
 //   k_combine_stats  phi and the statistics (M, W, phi, e_*) of each query
 //   k_grad           third sweep: per split, sum w grad g, sum w (g-phi) e,
 //                    sum w (g-phi) d (seven accumulators per query)
@@ -24,50 +25,8 @@
 namespace pts {
 namespace {
 
-template <int QPL>
-__global__ __launch_bounds__(kBlock) void k_far_arg(const Header* __restrict__ h, const float4* __restrict__ pos4,
-                                                    const float* __restrict__ x, int64_t Q, int S, int64_t per_split,
-                                                    float* __restrict__ far2, int32_t* __restrict__ farix) {
-  __shared__ float4 tile[kTile1];
-  const int split = int(blockIdx.x % unsigned(S));
-  const int64_t qb = blockIdx.x / unsigned(S);
-  const int64_t N = h->N;
-  float qx[QPL], qy[QPL], qz[QPL], acc[QPL];
-  int32_t ix[QPL];
-#pragma unroll
-  for (int k = 0; k < QPL; ++k) {
-    QueryIn qi = load_query(x, qb * (kBlock * QPL) + k * kBlock + threadIdx.x, Q, h);
-    qx[k] = qi.x; qy[k] = qi.y; qz[k] = qi.z;
-    acc[k] = -3.0e38f;
-    ix[k] = -1;
-  }
-  const int64_t beg = int64_t(split) * per_split;
-  const int64_t end = min(N, beg + per_split);
-  for (int64_t t0 = beg; t0 < end; t0 += kTile1) {
-    const int cnt = int(min<int64_t>(kTile1, end - t0));
-    __syncthreads();
-    for (int j = threadIdx.x; j < cnt; j += kBlock) tile[j] = pos4[t0 + j];
-    __syncthreads();
-    for (int j = 0; j < cnt; ++j) {
-      const float4 P = tile[j];
-#pragma unroll
-      for (int k = 0; k < QPL; ++k) {
-        const float a = fmaf(qz[k], P.z, fmaf(qy[k], P.y, fmaf(qx[k], P.x, P.w)));
-        if (a > acc[k]) { acc[k] = a; ix[k] = int32_t(t0 + j); }
-      }
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < QPL; ++k) {
-    const int64_t q = qb * (kBlock * QPL) + k * kBlock + threadIdx.x;
-    if (q < Q) {
-      far2[int64_t(split) * Q + q] = acc[k] + fmaf(qz[k], qz[k], fmaf(qy[k], qy[k], qx[k] * qx[k]));
-      farix[int64_t(split) * Q + q] = ix[k];
-    }
-  }
-}
-
-// phi = sum num / sum den over splits (fixed order) and stats (M, W, phi, e_*).
+// phi = sum num / sum den over splits (fixed order) and stats (M, W, phi, e_*)
+// from the farthest-point sweep's M^2 and farthest slot of each query.
 __global__ __launch_bounds__(kBlock) void k_combine_stats(const Header* __restrict__ h, const float4* __restrict__ pos4,
                                                           const float* __restrict__ x, const float2* __restrict__ part,
                                                           const float* __restrict__ far2,
@@ -75,15 +34,14 @@ __global__ __launch_bounds__(kBlock) void k_combine_stats(const Header* __restri
                                                           float* __restrict__ sdf, float* __restrict__ stats) {
   const int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (q >= Q) return;
-  float num = 0.f, den = 0.f, m2 = -3.0e38f;
-  int32_t slot = -1;
+  float num = 0.f, den = 0.f;
   for (int s = 0; s < S; ++s) {
     const float2 v = part[int64_t(s) * Q + q];
     num += v.x;
     den += v.y;
-    const float f = far2[int64_t(s) * Q + q];
-    if (f > m2) { m2 = f; slot = farix[int64_t(s) * Q + q]; }
   }
+  const float m2 = far2[q];
+  const int32_t slot = farix[q];
   const float phi = num / den;
   if (sdf) sdf[q] = phi;
   const float M = sqrtf(fmaxf(m2, 0.f));
@@ -229,29 +187,11 @@ void launch_grad_sweep(const Header* h, const float4* rec, const float* x, int64
                      plan.per_split, stats, C2, gpart);
 }
 
-template <int QPL>
-void launch_far_arg_q(const Header* h, const float4* pos4, const float* x, int64_t Q, const Plan& plan, float* far2,
-                      int32_t* farix, hipStream_t st) {
-  hipLaunchKernelGGL(k_far_arg<QPL>, dim3(unsigned(plan.nqb * plan.S)), dim3(kBlock), 0, st, h, pos4, x, Q, plan.S,
-                     plan.per_split, far2, farix);
-}
-
 }  // namespace
 
 int launch_far_arg(const void* rec, int64_t N, const float* x, int64_t Q, const Plan& plan, const WsView& ws,
                    hipStream_t st) {
-  const Layout L(N);
-  const char* base = static_cast<const char*>(rec);
-  const Header* h = reinterpret_cast<const Header*>(base);
-  const float4* pos4 = reinterpret_cast<const float4*>(base + L.pos);
-  const int qpl = plan.qpl > 4 ? 4 : plan.qpl;
-  const Plan p = with_qpl(plan, qpl, Q);
-  switch (qpl) {
-    case 1: launch_far_arg_q<1>(h, pos4, x, Q, p, ws.far2, ws.farix, st); break;
-    case 2: launch_far_arg_q<2>(h, pos4, x, Q, p, ws.far2, ws.farix, st); break;
-    default: launch_far_arg_q<4>(h, pos4, x, Q, p, ws.far2, ws.farix, st); break;
-  }
-  return check_hip(hipGetLastError(), "farthest-point (argmax) kernel");
+  return launch_far_cull(rec, N, x, Q, plan.qpl, ws.far2, ws.farix, st);
 }
 
 int launch_combine_stats(const void* rec, int64_t N, const float* x, int64_t Q, const Plan& plan, const WsView& ws,

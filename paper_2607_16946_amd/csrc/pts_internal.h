@@ -13,13 +13,16 @@
 namespace pts {
 
 constexpr uint32_t kMagic = 0x31535450u;  // "PTS1"
-constexpr int kRecordVersion = 1;
+constexpr int kRecordVersion = 2;
 constexpr int kBlock = 256;               // threads per workgroup (4 waves of 64)
 constexpr int kTile2 = 128;               // points per LDS tile, blend pass (80 B each)
 constexpr int kTile1 = 512;               // points per LDS tile, farthest-point pass (16 B each)
 constexpr int kRecF4 = 5;                 // float4 per point record
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr double kDirectMaxL = 4.0;       // direct torus form when L <= 4 D
+constexpr int kUnit = 64;                 // points per culling unit of the farthest-point pass
+constexpr int kSortBits = 4;              // radix of the build's spatial sort (16 buckets per pass)
+constexpr int kSortPasses = 7;            // 25-bit keys: form bit + 3 x 8 Morton bits
 
 // Cloud header (first 256 bytes of the record buffer).
 struct alignas(256) Header {
@@ -51,19 +54,28 @@ inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 //   pos4  [N]     float4 (-2 p, |p|^2), farthest-point pass
 //   rec   [N][5]  float4 torus record, blend passes (layout in pts_build.hip)
 //   perm  [N]     int32 original index of each slot
+//   ub    [U][2]  float4 bounds of each kUnit-point unit of slots, U = ceil(N / kUnit):
+//                 (center c, radius r) and (the unit's point farthest from c, 0)
 //   flag  [N]     int32 build scratch (direct-form flag)
 //   blk   [2*nb]  int32 build scratch (per-block counts and offsets)
+//   key, idx [2][N] uint32 / int32 build scratch (sort keys and indices, ping-pong)
+//   rhist [16*nb] int32 build scratch (radix histograms)
 struct Layout {
-  size_t pos, rec, perm, flag, blk, total;
-  int64_t nblk;
+  size_t pos, rec, perm, ub, flag, blk, key, idx, rhist, total;
+  int64_t nblk, nunit;
   explicit Layout(int64_t N) {
     nblk = (N + kBlock - 1) / kBlock;
+    nunit = (N + kUnit - 1) / kUnit;
     pos = 256;
     rec = pos + align256(size_t(N) * 16);
     perm = rec + align256(size_t(N) * 16 * kRecF4);
-    flag = perm + align256(size_t(N) * 4);
+    ub = perm + align256(size_t(N) * 4);
+    flag = ub + align256(size_t(nunit) * 32);
     blk = flag + align256(size_t(N) * 4);
-    total = blk + align256(size_t(nblk) * 8);
+    key = blk + align256(size_t(nblk) * 8);
+    idx = key + 2 * align256(size_t(N) * 4);
+    rhist = idx + 2 * align256(size_t(N) * 4);
+    total = rhist + align256(size_t(nblk) * 16 * 4);
   }
 };
 
@@ -87,9 +99,9 @@ inline Plan with_qpl(Plan p, int qpl, int64_t Q) {
 // of each split's farthest point, and (gradients only) the statistics of the
 // queries and the per-split gradient partials.
 struct WsView {
-  float* far2;     // [S][Q]
+  float* far2;     // [S][Q] (the farthest-point sweep fills row 0; packed launches use all rows)
   float2* part;    // [S][Q]
-  int32_t* farix;  // [S][Q]
+  int32_t* farix;  // [S][Q] (row 0 used)
   float* stats;    // [Q][6]    (gradient workspace only)
   float4* gpart;   // [S][Q][2] (gradient workspace only)
 };
@@ -105,6 +117,10 @@ int check_hip(hipError_t e, const char* what);
 int launch_build(const float* p, const float* n, const float* a, int64_t N, float kfloor_rel,
                  void* rec, hipStream_t st);
 int launch_decode(const void* rec, int64_t N, float* out, hipStream_t st);
+// Farthest-point sweep (culled by units): M^2 per query into far2[Q] and, if
+// farix is non-null, the first slot attaining it into farix[Q].
+int launch_far_cull(const void* rec, int64_t N, const float* x, int64_t Q, int qpl, float* far2, int32_t* farix,
+                    hipStream_t st);
 int launch_far(const void* rec, int64_t N, const float* x, int64_t Q, const Plan& plan, const WsView& ws,
                hipStream_t st);
 int launch_blend(const void* rec, int64_t N, const float* x, int64_t Q, float C, const Plan& plan,
