@@ -72,6 +72,11 @@ def lib():
         L.orc_trace.argtypes = [i64, P, P, i64, P, P, ctypes.c_int, ctypes.c_double,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_int, P, P, P, P]
         L.orc_trace.restype = ctypes.c_int
+        L.orc_knn_mean.argtypes = [i64, P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+        L.orc_knn_mean.restype = ctypes.c_int
+        L.orc_eval_radius.argtypes = [i64, P, P, i64, P, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                      ctypes.c_int, P, P]
+        L.orc_eval_radius.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -223,3 +228,37 @@ def trace(p, tori: Tori, org, dirs, steps: int, eps: float, tmax: float, C: floa
     if rc != 0:
         raise ValueError("oracle trace: empty cloud")
     return t, hit.astype(bool), ns, nrm
+
+
+def knn_mean(p, k: int = 64, nthreads: int = 0) -> float:
+    """Mean over points of the mean distance to their k nearest other points
+    (Sec. 4.2, "Acceleration and adaptive lambda"); 1.0 for a single point."""
+    p = _f64(p, 3)
+    out = ctypes.c_double(0.0)
+    if lib().orc_knn_mean(p.shape[0], _ptr(p), int(k), int(nthreads), ctypes.byref(out)) != 0:
+        raise ValueError("oracle knn_mean: empty cloud")
+    return float(out.value)
+
+
+def radius_params(p, C: float = C_DEFAULT, k: int = 64, nthreads: int = 0):
+    """(D, lambda, R_eval) of the radius-limited evaluation: lambda = 1e3 / D,
+    R_eval = 2 C / lambda (Sec. 4.2)."""
+    D = knn_mean(p, k, nthreads)
+    lam = 1e3 / D
+    return D, lam, 2.0 * C / lam
+
+
+def eval_radius(p, tori: Tori, x, lam: float, reval: float, kfb: int = 32, nthreads: int = 0):
+    """Radius-limited phi (Sec. 4.2): blend over the points within reval of x
+    with the constant lambda, else over the kfb nearest.  Returns (phi, count),
+    count = points blended, negative for the nearest-point fallback."""
+    p = _f64(p, 3)
+    x = _f64(x, 3)
+    Q = x.shape[0]
+    phi = np.zeros(Q)
+    cnt = np.zeros(Q, dtype=np.int32)
+    rc = lib().orc_eval_radius(p.shape[0], _ptr(p), _ptr(tori.raw), Q, _ptr(x), float(lam), float(reval),
+                               int(kfb), int(nthreads), _ptr(phi), _ptr(cnt))
+    if rc != 0:
+        raise ValueError("oracle eval_radius: empty cloud")
+    return phi, cnt

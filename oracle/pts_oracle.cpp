@@ -37,6 +37,16 @@
 //             if max distance is 0 the weights are uniform.
 //   R-argmax  lambda_x depends on x through the farthest point; ties go to
 //             the lowest index (first maximum).
+//
+// Radius-limited evaluation (Sec. 4.2, "Acceleration and adaptive lambda"):
+//   R-rl-knn  D is the mean over points of the mean distance to their 64
+//             nearest *other* points (fewer if N <= 64; D = 1 if N = 1).
+//   R-rl-in   "within R_eval" includes distance = R_eval; sigma = R_eval/2,
+//             so lambda = C/sigma as in Eq. (RelationshipBetweenLambdaAndRadius).
+//   R-rl-fb   the fallback blends the 32 nearest points (the 32 smallest
+//             distances, ties to the lower index) with the same lambda and the
+//             shift sigma = their smallest distance (phi does not depend on
+//             sigma; this keeps the largest weight at 1).
 
 #include <cmath>
 #include <cstdint>
@@ -283,6 +293,62 @@ X blend_at(int64_t N, const double* P, const std::vector<Torus<double>>& tori, c
   return num / den;
 }
 
+// Mean distance from point i to its k nearest other points.
+double knn_mean_of(int64_t N, const double* P, int64_t i, int k, std::vector<double>& d) {
+  d.clear();
+  for (int64_t j = 0; j < N; ++j) {
+    if (j == i) continue;
+    double dv[3];
+    for (int c = 0; c < 3; ++c) dv[c] = P[3 * i + c] - P[3 * j + c];
+    d.push_back(std::sqrt(dot3(dv, dv)));
+  }
+  const int64_t kk = std::min<int64_t>(k, (int64_t)d.size());
+  std::nth_element(d.begin(), d.begin() + (kk - 1), d.end());
+  std::sort(d.begin(), d.begin() + kk);
+  double s = 0.0;
+  for (int64_t j = 0; j < kk; ++j) s += d[j];
+  return s / double(kk);
+}
+
+// Radius-limited phi at one query: the points within reval of x, or the kfb
+// nearest if there are none.  *count = number blended (negative: fallback).
+double blend_radius_at(int64_t N, const double* P, const std::vector<Torus<double>>& tori, const double* x,
+                       double lambda, double reval, int kfb, int32_t* count) {
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(x[k])) { *count = 0; return NAN; }
+  std::vector<double> d(N);
+  for (int64_t i = 0; i < N; ++i) {
+    double dv[3];
+    for (int k = 0; k < 3; ++k) dv[k] = x[k] - P[3 * i + k];
+    d[i] = std::sqrt(dot3(dv, dv));
+  }
+  double num = 0.0, den = 0.0;
+  int64_t nin = 0;
+  const double sigma = 0.5 * reval;
+  for (int64_t i = 0; i < N; ++i) {
+    if (!(d[i] <= reval)) continue;
+    const double w = std::exp(-lambda * (d[i] - sigma));
+    num += w * torus_g(tori[i], x);
+    den += w;
+    ++nin;
+  }
+  if (nin > 0) { *count = int32_t(nin); return num / den; }
+  std::vector<int64_t> idx(N);
+  for (int64_t i = 0; i < N; ++i) idx[i] = i;
+  const int64_t kk = std::min<int64_t>(kfb, N);
+  std::partial_sort(idx.begin(), idx.begin() + kk, idx.end(),
+                    [&](int64_t a, int64_t b) { return d[a] < d[b] || (d[a] == d[b] && a < b); });
+  const double s0 = d[idx[0]];
+  for (int64_t j = 0; j < kk; ++j) {
+    const int64_t i = idx[j];
+    const double w = std::exp(-lambda * (d[i] - s0));
+    num += w * torus_g(tori[i], x);
+    den += w;
+  }
+  *count = -int32_t(kk);
+  return num / den;
+}
+
 int set_threads(int nthreads) {
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -444,6 +510,38 @@ int orc_trace(int64_t N, const double* p, const double* tor, int64_t Rn, const d
       if (gl > 0.0) for (int j = 0; j < 3; ++j) normal_out[3 * r + j] = f.d[j] / gl;
     }
   }
+  return 0;
+}
+
+// D = mean over points of the mean distance to their k nearest other points
+// (Sec. 4.2, "Acceleration and adaptive lambda"); 1 if N = 1.
+int orc_knn_mean(int64_t N, const double* p, int k, int nthreads, double* out) {
+  if (N <= 0 || k <= 0) return 1;
+  if (N == 1) { *out = 1.0; return 0; }
+  set_threads(nthreads);
+  std::vector<double> m(N);
+#pragma omp parallel
+  {
+    std::vector<double> d;
+#pragma omp for schedule(dynamic, 64)
+    for (int64_t i = 0; i < N; ++i) m[i] = knn_mean_of(N, p, i, k, d);
+  }
+  double s = 0.0;
+  for (int64_t i = 0; i < N; ++i) s += m[i];
+  *out = s / double(N);
+  return 0;
+}
+
+// Radius-limited phi at Q queries with the constant lambda and radius reval;
+// count[q] = points blended (negative: the kfb-nearest fallback; 0: NaN query).
+int orc_eval_radius(int64_t N, const double* p, const double* tor, int64_t Q, const double* x, double lambda,
+                    double reval, int kfb, int nthreads, double* phi, int32_t* count) {
+  if (N <= 0 || kfb <= 0) return 1;
+  set_threads(nthreads);
+  std::vector<Torus<double>> tt(N);
+  for (int64_t i = 0; i < N; ++i) tt[i] = load_torus(tor + (size_t)TSTRIDE * i);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t q = 0; q < Q; ++q) phi[q] = blend_radius_at(N, p, tt, x + 3 * q, lambda, reval, kfb, count + q);
   return 0;
 }
 

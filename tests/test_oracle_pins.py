@@ -467,3 +467,78 @@ def test_trace_sphere_closed_form():
     assert np.max(np.abs(t[hit] - tstar[hit])) < 1e-8
     xh = o + t[:, None] * d
     assert np.max(np.abs(nrm[hit] - xh[hit] / np.linalg.norm(xh[hit], axis=1, keepdims=True))) < 1e-7
+
+
+# ---------------------------------------------------------------------------
+# Radius-limited evaluation (Sec. 4.2, "Acceleration and adaptive lambda")
+# ---------------------------------------------------------------------------
+
+def test_knn_mean_matches_brute_force():
+    rng = np.random.default_rng(3)
+    for N in (2, 5, 80, 300):
+        p = rng.normal(size=(N, 3))
+        dm = np.linalg.norm(p[:, None, :] - p[None, :, :], axis=2)
+        np.fill_diagonal(dm, np.inf)
+        k = min(64, N - 1)
+        want = np.sort(dm, axis=1)[:, :k].mean(axis=1).mean()
+        assert abs(oracle.knn_mean(p) - want) <= 1e-12 * want
+    assert oracle.knn_mean(np.zeros((1, 3))) == 1.0
+    # two points: each one's only neighbour is the other
+    assert abs(oracle.knn_mean(np.array([[0.0, 0.0, 0.0], [0.0, 3.0, 4.0]])) - 5.0) < 1e-15
+    D, lam, reval = oracle.radius_params(np.array([[0.0, 0.0, 0.0], [0.0, 3.0, 4.0]]))
+    assert abs(lam - 200.0) < 1e-12 and abs(reval - 2 * 64.0 / 200.0) < 1e-15
+
+
+@pytest.mark.parametrize("shift", [0.0, 0.2])
+def test_radius_eval_sphere_closed_form(shift):
+    # every torus of a sphere cloud is the sphere itself, so any blend of them --
+    # within R_eval or over the 32 nearest -- is |x| - (1 + shift)
+    p, n, a = _sphere(3000, seed=4, shift=shift)
+    tor = oracle.fit(p, n, a)
+    D, lam, reval = oracle.radius_params(p)
+    rng = np.random.default_rng(9)
+    near = p[:40] * (1.0 + 0.3 * reval * rng.uniform(-1, 1, size=(40, 1)))
+    u = rng.normal(size=(60, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    far = u * rng.choice([0.3, 1.6, 2.5], size=(60, 1))
+    x = np.vstack([near, far])
+    phi, cnt = oracle.eval_radius(p, tor, x, lam, reval)
+    assert np.all(cnt[:40] > 0) and np.all(cnt[40:] == -32)
+    assert np.abs(phi - (np.linalg.norm(x, axis=1) - 1.0 - shift)).max() < 1e-12
+
+
+def test_radius_eval_single_point_counts_and_limits():
+    rng = np.random.default_rng(6)
+    p, n, a = _sphere(50, seed=6)
+    a[:, 5] = -0.5 * (1.0 + 0.5 * rng.random(50))     # anisotropic, point-specific tori
+    a[:, 3] = 0.2 * rng.normal(size=50)
+    tor = oracle.fit(p, n, a)
+    # a query within R_eval of exactly one point blends that point's torus alone
+    # (R_eval below a third of the smallest spacing, lambda = 2C / R_eval)
+    dm = np.linalg.norm(p[:, None, :] - p[None, :, :], axis=2)
+    np.fill_diagonal(dm, np.inf)
+    reval = 0.3 * dm.min()
+    lam = 2 * 64.0 / reval
+    v = rng.normal(size=(10, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    x = p[:10] + 0.5 * reval * v
+    phi, cnt = oracle.eval_radius(p, tor, x, lam, reval)
+    g = oracle.torus_g(tor, x)
+    assert np.all(cnt == 1)
+    assert np.allclose(phi, g[np.arange(10), np.arange(10)], rtol=1e-14, atol=1e-15)
+    # far queries fall back to the 32 nearest (all points if fewer)
+    far = 10.0 * v
+    _, cnt = oracle.eval_radius(p, tor, far, lam, reval)
+    assert np.all(cnt == -32)
+    _, cnt = oracle.eval_radius(p[:10], oracle.fit(p[:10], n[:10], a[:10]), far, lam, reval)
+    assert np.all(cnt == -10)
+    # a very large lambda leaves the nearest point's torus (Laplace limit)
+    xq = 1.5 * v
+    phi, cnt = oracle.eval_radius(p, tor, xq, 1e9, 1e-12)
+    gq = oracle.torus_g(tor, xq)
+    nearest = np.argmin(np.linalg.norm(xq[:, None, :] - p[None], axis=2), axis=1)
+    assert np.all(cnt == -32)
+    assert np.allclose(phi, gq[np.arange(10), nearest], rtol=1e-12, atol=1e-14)
+    # a NaN query gives NaN and blends nothing
+    phi, cnt = oracle.eval_radius(p, tor, np.array([[np.nan, 0.0, 0.0]]), lam, reval)
+    assert np.isnan(phi[0]) and cnt[0] == 0
