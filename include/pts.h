@@ -237,6 +237,43 @@ int pts_trace(const void* rec, int64_t N, const float* origin, const float* dir,
               int32_t* steps_out, const pts_params* prm, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Radius-limited evaluation (Sec. 4.2, "Acceleration and adaptive lambda"):
+ * the paper's accelerated form of Eq. (BasicFormulaShifted) with a constant
+ * lambda per cloud.  It is a different function from pts_eval's all-points phi.
+ *
+ *   D      = mean over points of the mean distance to their 64 nearest other
+ *            points (all others if N <= 64; D = 1 if N = 1),
+ *   lambda = 1e3 / D,   R_eval = 2 C / lambda,   sigma = R_eval / 2,
+ *   phi(x) = sum_{|x-p_i| <= R_eval} g_i w_i / sum w_i,
+ *            w_i = exp(-lambda (|x - p_i| - sigma));
+ *   if no point lies within R_eval: the same blend over the 32 nearest points
+ *   (all if N < 32), shifted by the nearest distance instead of sigma.
+ * ------------------------------------------------------------------------- */
+
+typedef struct pts_radius_info {
+  double D;       /* mean 64-nearest-neighbour distance */
+  float lam;      /* lambda = 1e3 / D */
+  float reval;    /* 2 C / lambda */
+  int ready;      /* 1 after pts_radius_prepare */
+  int reserved;
+} pts_radius_info;
+
+/* Compute D, lambda and R_eval for a built record (stored in the record;
+ * pts_params.C sets C).  Asynchronous; uses the record's own build scratch. */
+int pts_radius_prepare(void* rec, int64_t N, const pts_params* prm, void* stream);
+
+/* Read them back (blocks). */
+int pts_radius_info_get(const void* rec, pts_radius_info* out, void* stream);
+
+/* Radius-limited phi at Q queries (device x [Q,3] -> sdf [Q]); count [Q]
+ * int32 or NULL: number of points blended, negated when the 32-nearest
+ * fallback was used, 0 for a query with a non-finite coordinate (phi NaN).
+ * phi is NaN everywhere if pts_radius_prepare has not run on the record.
+ * Needs no workspace.  Q = 0 is a no-op. */
+int pts_eval_radius(const void* rec, int64_t N, const float* x, int64_t Q, float* sdf, int32_t* count,
+                    void* stream);
+
+/* ---------------------------------------------------------------------------
  * Serving: a resident-cloud server with continuous batching.
  *
  * The server keeps many clouds' records resident on the device and answers

@@ -44,6 +44,11 @@ class CloudInfo(ctypes.Structure):
                 ("kfloor", ctypes.c_float), ("version", ctypes.c_int), ("reserved", ctypes.c_int)]
 
 
+class RadiusInfo(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_double), ("lam", ctypes.c_float), ("reval", ctypes.c_float),
+                ("ready", ctypes.c_int), ("reserved", ctypes.c_int)]
+
+
 class ServerCfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_inflight", ctypes.c_int), ("max_queue", ctypes.c_int),
                 ("max_batch_work", ctypes.c_int64), ("C", ctypes.c_float), ("kfloor_rel", ctypes.c_float),
@@ -99,6 +104,9 @@ SIGNATURES = {
     "pts_trace_ws_bytes": (ctypes.c_int, [_I64, _I64, ctypes.POINTER(Params), ctypes.POINTER(_SZ)]),
     "pts_trace": (ctypes.c_int, [_P, _I64, _P, _P, _I64, ctypes.c_int, ctypes.c_float, ctypes.c_float, _P, _P, _P, _P,
                                  ctypes.POINTER(Params), _P, _SZ, _P]),
+    "pts_radius_prepare": (ctypes.c_int, [_P, _I64, ctypes.POINTER(Params), _P]),
+    "pts_radius_info_get": (ctypes.c_int, [_P, ctypes.POINTER(RadiusInfo), _P]),
+    "pts_eval_radius": (ctypes.c_int, [_P, _I64, _P, _I64, _P, _P, _P]),
     "pts_server_create": (ctypes.c_int, [ctypes.POINTER(ServerCfg), ctypes.POINTER(_P)]),
     "pts_server_add_cloud": (ctypes.c_int, [_P, _P, _P, _P, _I64, ctypes.POINTER(ctypes.c_int)]),
     "pts_server_cloud_plan": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_int)]),
@@ -333,6 +341,29 @@ def trace(rec: torch.Tensor, N: int, origin: torch.Tensor, direction: torch.Tens
                            _ptr(t), _ptr(nrm), _ptr(hit), _ptr(ns), ctypes.byref(prm), _ptr(ws), ws.numel(),
                            _stream()))
     return t, hit.bool(), ns, nrm
+
+
+def radius_prepare(rec: torch.Tensor, N: int, params: Params | None = None) -> None:
+    """D, lambda = 1e3/D, R_eval = 2C/lambda of the radius-limited evaluation (Sec. 4.2), into the record."""
+    prm = params if params is not None else make_params()
+    _check(lib().pts_radius_prepare(_ptr(rec), int(N), ctypes.byref(prm), _stream()))
+
+
+def radius_info(rec: torch.Tensor) -> RadiusInfo:
+    out = RadiusInfo()
+    _check(lib().pts_radius_info_get(_ptr(rec), ctypes.byref(out), _stream()))
+    return out
+
+
+def eval_radius(rec: torch.Tensor, N: int, x: torch.Tensor, count: bool = False):
+    """Radius-limited phi (Sec. 4.2) at x [Q,3]; with count=True also the int32 count of blended points
+    (negative for the 32-nearest fallback)."""
+    _dev(x, "x", 3)
+    Q = x.shape[0]
+    sdf = torch.empty(Q, dtype=torch.float32, device=x.device)
+    cnt = torch.empty(Q, dtype=torch.int32, device=x.device) if count else None
+    _check(lib().pts_eval_radius(_ptr(rec), int(N), _ptr(x), Q, _ptr(sdf), _ptr(cnt), _stream()))
+    return (sdf, cnt) if count else sdf
 
 
 class Cloud:

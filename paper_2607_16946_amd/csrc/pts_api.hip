@@ -139,6 +139,37 @@ int pts_cloud_decode(const void* rec, int64_t N, float* out, void* stream) {
   return launch_decode(rec, N, out, static_cast<hipStream_t>(stream));
 }
 
+int pts_radius_prepare(void* rec, int64_t N, const pts_params* prm, void* stream) {
+  if (!rec) return fail(PTS_EINVAL, "null pointer");
+  if (N < 1) return fail(PTS_EINVAL, "N must be >= 1");
+  const pts_params P = resolve(prm);
+  if (int rc = check_params(P)) return rc;
+  return launch_radius_prepare(rec, N, P.C, static_cast<hipStream_t>(stream));
+}
+
+int pts_radius_info_get(const void* rec, pts_radius_info* out, void* stream) {
+  if (!rec || !out) return fail(PTS_EINVAL, "null pointer");
+  Header h;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (int rc = check_hip(hipMemcpyAsync(&h, rec, sizeof(h), hipMemcpyDeviceToHost, st), "read header")) return rc;
+  if (int rc = check_hip(hipStreamSynchronize(st), "read header")) return rc;
+  if (h.magic != kMagic) return fail(PTS_EINVAL, "not a built record");
+  std::memset(out, 0, sizeof(*out));
+  out->D = h.rl_D;
+  out->lam = h.rl_lambda;
+  out->reval = h.rl_reval;
+  out->ready = h.rl_ready;
+  return PTS_OK;
+}
+
+int pts_eval_radius(const void* rec, int64_t N, const float* x, int64_t Q, float* sdf, int32_t* count,
+                    void* stream) {
+  if (Q == 0) return PTS_OK;
+  if (!rec || !x || !sdf) return fail(PTS_EINVAL, "null pointer");
+  if (N < 1 || Q < 0) return fail(PTS_EINVAL, "N must be >= 1 and Q >= 0");
+  return launch_eval_radius(rec, N, x, Q, sdf, count, static_cast<hipStream_t>(stream));
+}
+
 int pts_eval_plan(int64_t N, int64_t Q, const pts_params* prm, int* qpl, int* splits, int64_t* per_split) {
   if (!qpl || !splits || !per_split) return fail(PTS_EINVAL, "null pointer");
   if (N < 1 || Q < 1) return fail(PTS_EINVAL, "N and Q must be >= 1");

@@ -65,6 +65,11 @@ __global__ void k_init(Header* h, int64_t N) {
   h->status = 0;
   h->pad0 = 0;
   h->kfloor64 = 0.0;
+  h->rl_D = 0.0;
+  h->rl_lambda = 0.f;
+  h->rl_reval = 0.f;
+  h->rl_ready = 0;
+  h->pad1 = 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_bbox(const float* __restrict__ p, const float* __restrict__ n,
@@ -407,7 +412,8 @@ int launch_build(const float* p, const float* n, const float* a, int64_t N, floa
                      reinterpret_cast<float4*>(base + L.rec), reinterpret_cast<int32_t*>(base + L.perm));
   hipLaunchKernelGGL(k_units, dim3(unsigned((L.nunit + 3) / 4)), dim3(kBlock), 0, st, pos4, N,
                      reinterpret_cast<float4*>(base + L.ub));
-  return check_hip(hipGetLastError(), "build kernels");
+  if (int rc = check_hip(hipGetLastError(), "build kernels")) return rc;
+  return launch_blocks(rec, N, st);
 }
 
 int launch_decode(const void* rec, int64_t N, float* out, hipStream_t st) {

@@ -21,6 +21,7 @@ constexpr int kRecF4 = 5;                 // float4 per point record
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr double kDirectMaxL = 4.0;       // direct torus form when L <= 4 D
 constexpr int kUnit = 64;                 // points per culling unit of the farthest-point pass
+constexpr int kBlkU = 64;                 // units per block of the two-level sphere hierarchy
 constexpr int kSortBits = 4;              // radix of the build's spatial sort (16 buckets per pass)
 constexpr int kSortPasses = 7;            // 25-bit keys: form bit + 3 x 8 Morton bits
 
@@ -42,13 +43,19 @@ struct alignas(256) Header {
   int32_t status;       // bit 0: zero normal, bit 1: non-finite input
   int32_t pad0;
   double kfloor64;      // curvature floor used by the fit (FP64)
+  // radius-limited evaluation (set by pts_radius_prepare)
+  double rl_D;          // mean distance to the 64 nearest other points
+  float rl_lambda;      // 1e3 / rl_D
+  float rl_reval;       // 2 C / rl_lambda
+  int32_t rl_ready;     // 1 once the three values above are set
+  int32_t pad1;
 };
 static_assert(sizeof(Header) == 256, "header is 256 bytes");
 
 constexpr int32_t kStatusZeroNormal = 1;
 constexpr int32_t kStatusNonFinite = 2;
 
-inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+__host__ __device__ inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Byte offsets of the sections of a record buffer for N points.
 //   pos4  [N]     float4 (-2 p, |p|^2), farthest-point pass
@@ -56,21 +63,24 @@ inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 //   perm  [N]     int32 original index of each slot
 //   ub    [U][2]  float4 bounds of each kUnit-point unit of slots, U = ceil(N / kUnit):
 //                 (center c, radius r) and (the unit's point farthest from c, 0)
+//   bb    [B]     float4 (center, radius) of each block of kBlkU units, B = ceil(U / kBlkU)
 //   flag  [N]     int32 build scratch (direct-form flag)
 //   blk   [2*nb]  int32 build scratch (per-block counts and offsets)
 //   key, idx [2][N] uint32 / int32 build scratch (sort keys and indices, ping-pong)
 //   rhist [16*nb] int32 build scratch (radix histograms)
 struct Layout {
-  size_t pos, rec, perm, ub, flag, blk, key, idx, rhist, total;
-  int64_t nblk, nunit;
-  explicit Layout(int64_t N) {
+  size_t pos, rec, perm, ub, bb, flag, blk, key, idx, rhist, total;
+  int64_t nblk, nunit, nbk;
+  __host__ __device__ explicit Layout(int64_t N) {
     nblk = (N + kBlock - 1) / kBlock;
     nunit = (N + kUnit - 1) / kUnit;
+    nbk = (nunit + kBlkU - 1) / kBlkU;
     pos = 256;
     rec = pos + align256(size_t(N) * 16);
     perm = rec + align256(size_t(N) * 16 * kRecF4);
     ub = perm + align256(size_t(N) * 4);
-    flag = ub + align256(size_t(nunit) * 32);
+    bb = ub + align256(size_t(nunit) * 32);
+    flag = bb + align256(size_t(nbk) * 16);
     blk = flag + align256(size_t(N) * 4);
     key = blk + align256(size_t(nblk) * 8);
     idx = key + 2 * align256(size_t(N) * 4);
@@ -117,6 +127,11 @@ int check_hip(hipError_t e, const char* what);
 int launch_build(const float* p, const float* n, const float* a, int64_t N, float kfloor_rel,
                  void* rec, hipStream_t st);
 int launch_decode(const void* rec, int64_t N, float* out, hipStream_t st);
+// Radius-limited evaluation (pts_radius.hip).
+int launch_blocks(void* rec, int64_t N, hipStream_t st);
+int launch_radius_prepare(void* rec, int64_t N, float C, hipStream_t st);
+int launch_eval_radius(const void* rec, int64_t N, const float* x, int64_t Q, float* sdf, int32_t* count,
+                       hipStream_t st);
 // Farthest-point sweep (culled by units): M^2 per query into far2[Q] and, if
 // farix is non-null, the first slot attaining it into farix[Q].
 int launch_far_cull(const void* rec, int64_t N, const float* x, int64_t Q, int qpl, float* far2, int32_t* farix,

@@ -87,7 +87,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     """ctypes structures have the sizes and field offsets gcc gives the C structs."""
     structs = {"pts_params": binding.Params, "pts_cloud_info": binding.CloudInfo,
                "pts_server_cfg": binding.ServerCfg, "pts_request": binding.Request,
-               "pts_server_stats": binding.ServerStats}
+               "pts_server_stats": binding.ServerStats, "pts_radius_info": binding.RadiusInfo}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "pts.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')

@@ -1,0 +1,149 @@
+"""Radius-limited evaluation (Sec. 4.2, "Acceleration and adaptive lambda") on
+the device against the FP64 oracle.
+
+The oracle is run with the device's lambda and R_eval, so both select points
+with the same radius.  Where the selection is decided by less than FP32
+rounding -- a point within 1e-4 R_eval of the R_eval sphere, or (in the
+nearest-point fallback) 32nd and 33rd distances within 1e-5 of each other --
+the query is left out of the comparison; everywhere else the number of blended
+points must match exactly and phi within 1e-5 of the bbox diagonal.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2607_16946_amd import binding, synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+KFB = 32
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    binding.lib()
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _prep(cl):
+    c = binding.Cloud(_dev(cl.p), _dev(cl.n), _dev(cl.a))
+    binding.radius_prepare(c.rec, c.N)
+    return c, binding.radius_info(c.rec)
+
+
+def _decided(p, x, reval, chunk=16):
+    """Queries whose selected set is not within FP32 rounding of changing."""
+    p = p.astype(np.float64)
+    out = np.zeros(len(x), bool)
+    for c0 in range(0, len(x), chunk):
+        xs = x[c0:c0 + chunk].astype(np.float64)
+        d = np.linalg.norm(xs[:, None, :] - p[None], axis=2)
+        edge = np.any(np.abs(d - reval) <= 1e-4 * reval, axis=1)
+        inside = np.any(d <= reval, axis=1)
+        if p.shape[0] > KFB:
+            ds = np.partition(d, KFB, axis=1)[:, :KFB + 1]
+            ds.sort(axis=1)
+            gap = ds[:, KFB] - ds[:, KFB - 1] > 1e-5 * ds[:, KFB - 1]
+        else:
+            gap = np.ones(len(xs), bool)
+        out[c0:c0 + chunk] = ~edge & (inside | gap)
+    return out
+
+
+def _compare(cl, c, info, x, what):
+    tor = oracle.fit(cl.p, cl.n, cl.a)
+    phi_o, cnt_o = oracle.eval_radius(cl.p, tor, x, float(info.lam), float(info.reval), KFB)
+    phi, cnt = binding.eval_radius(c.rec, c.N, _dev(x), count=True)
+    phi, cnt = phi.cpu().numpy(), cnt.cpu().numpy()
+    m = _decided(cl.p, x, float(info.reval))
+    D = max(oracle.bbox_diag(cl.p), 1.0)
+    err = np.abs(phi.astype(np.float64) - phi_o)[m]
+    print(f"{what}: {m.sum()}/{len(x)} decided, {(cnt_o[m] > 0).sum()} within R_eval, "
+          f"{(cnt_o[m] < 0).sum()} fallback; max err {err.max():.3e} tol {TOL * D:.3e}", flush=True)
+    assert np.array_equal(cnt[m], cnt_o[m]), what
+    assert err.max() <= TOL * D, what
+    return cnt_o[m]
+
+
+def test_mean_neighbour_distance_matches_oracle():
+    clouds = {"mid-8k": synth.mid(N=8192, grid=4)[0], "sphere-3k": synth.sphere_cloud(3000, seed=3)}
+    base = synth.sphere_cloud(200, seed=8)
+    for n in (1, 2, 40, 65):
+        clouds[f"N={n}"] = synth.Cloud(base.p[:n].copy(), base.n[:n].copy(), base.a[:n].copy(), {})
+    for name, cl in clouds.items():
+        c, info = _prep(cl)
+        D = oracle.knn_mean(cl.p)
+        print(f"{name}: D gpu {info.D:.9g} oracle {D:.9g}", flush=True)
+        assert info.ready == 1
+        assert abs(info.D - D) <= 2e-6 * D, name
+        assert abs(info.lam - 1e3 / info.D) <= 1e-6 * info.lam
+        assert abs(info.reval - 128.0 / info.lam) <= 1e-6 * info.reval
+
+
+def test_radius_parity_mid_both_modes():
+    cl, lattice = synth.mid(N=8192, grid=12)
+    c, info = _prep(cl)
+    rng = np.random.default_rng(4)
+    near = cl.p[rng.choice(cl.N, 600, replace=False)] + \
+        rng.uniform(-0.6, 0.6, size=(600, 3)).astype(np.float32) * info.reval
+    x = np.vstack([lattice, near]).astype(np.float32)
+    cnt = _compare(cl, c, info, x, "mid-8k")
+    assert (cnt > 0).sum() > 200 and (cnt < 0).sum() > 1000
+
+
+def test_radius_sphere_closed_form():
+    cl = synth.sphere_cloud(4000, seed=12, jitter=0.0)
+    c, info = _prep(cl)
+    rng = np.random.default_rng(5)
+    u = rng.normal(size=(800, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    x = np.vstack([u * rng.uniform(0.2, 2.5, size=(800, 1)),
+                   cl.p[:400] * (1 + 0.4 * float(info.reval) * rng.uniform(-1, 1, size=(400, 1)))])
+    x = x.astype(np.float32)
+    phi, cnt = binding.eval_radius(c.rec, c.N, _dev(x), count=True)
+    ref = np.linalg.norm(x.astype(np.float64), axis=1) - 1.0
+    err = np.abs(phi.cpu().numpy() - ref).max()
+    print(f"sphere: max err {err:.3e}", flush=True)
+    assert err <= TOL * oracle.bbox_diag(cl.p)
+    cnt = cnt.cpu().numpy()
+    assert (cnt > 0).any() and (cnt == -KFB).any()
+
+
+def test_radius_large_sampled():
+    cl, x = synth.large(Q=1 << 16)
+    c, info = _prep(cl)
+    print(f"large: D {info.D:.6g} lambda {info.lam:.6g} R_eval {info.reval:.6g}", flush=True)
+    rng = np.random.default_rng(7)
+    sample = np.vstack([x[:300], cl.p[rng.choice(cl.N, 100, replace=False)]]).astype(np.float32)
+    _compare(cl, c, info, sample, "large (sampled)")
+    # the full query set in one launch: finite everywhere, every query blended something
+    phi, cnt = binding.eval_radius(c.rec, c.N, _dev(x), count=True)
+    assert torch.isfinite(phi).all() and bool((cnt != 0).all())
+
+
+def test_radius_edge_cases():
+    base = synth.sphere_cloud(100, seed=13)
+    one = synth.Cloud(base.p[:1].copy(), base.n[:1].copy(), base.a[:1].copy(), {})
+    c, info = _prep(one)
+    assert info.D == 1.0
+    x = np.array([[3.0, 0.0, 0.0], [np.nan, 0.0, 0.0]], np.float32)
+    phi, cnt = binding.eval_radius(c.rec, c.N, _dev(x), count=True)
+    g = oracle.torus_g(oracle.fit(one.p, one.n, one.a), x[:1])[0, 0]
+    assert cnt.cpu().tolist() == [-1, 0]
+    assert abs(phi[0].item() - g) <= 1e-5 * max(1.0, abs(g)) and np.isnan(phi[1].item())
+    five = synth.Cloud(base.p[:5].copy(), base.n[:5].copy(), base.a[:5].copy(), {})
+    c5, _ = _prep(five)
+    _, cnt = binding.eval_radius(c5.rec, c5.N, _dev(x[:1] * 10), count=True)
+    assert cnt.item() == -5
+    # a record that was never prepared gives NaN
+    fresh = binding.Cloud(_dev(base.p), _dev(base.n), _dev(base.a))
+    phi, cnt = binding.eval_radius(fresh.rec, fresh.N, _dev(x[:1]), count=True)
+    assert np.isnan(phi.item()) and cnt.item() == 0
