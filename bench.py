@@ -185,6 +185,32 @@ def diff_bench(reps: int):
     return out
 
 
+def radius_bench(name: str, cl, x, reps: int = 3):
+    """Radius-limited evaluation (Sec. 4.2, constant lambda = 1e3/D, R_eval =
+    2C/lambda, 32-nearest fallback): preparation (the mean 64-nearest distance
+    D over all points) and evaluation at every query, HIP-event timed."""
+    import numpy as np
+    import torch
+    from paper_2607_16946_amd import binding
+    p, n, a, xd = (torch.from_numpy(v).cuda() for v in (cl.p, cl.n, cl.a, x))
+    prm = binding.make_params()
+    rec = binding.cloud_build(p, n, a, prm)
+    ms_prep = _timed(lambda: binding.radius_prepare(rec, cl.N, prm), reps)
+    info = binding.radius_info(rec)
+    sdf = torch.empty(x.shape[0], dtype=torch.float32, device="cuda")
+    ms_eval = _timed(lambda: binding.eval_radius(rec, cl.N, xd), reps)
+    _, cnt = binding.eval_radius(rec, cl.N, xd, count=True)
+    cnt = cnt.cpu().numpy()
+    out = {"workload": name, "N": cl.N, "Q": int(x.shape[0]), "D": info.D, "lambda": float(info.lam),
+           "R_eval": float(info.reval), "prepare_ms": ms_prep, "eval_ms": ms_eval,
+           "queries_per_s": x.shape[0] / (ms_eval * 1e-3),
+           "frac_within_R_eval": float(np.mean(cnt > 0)), "mean_points_blended": float(np.mean(np.abs(cnt)))}
+    log(f"radius ({name}): prepare {ms_prep:.2f} ms, eval {ms_eval:.2f} ms ({out['queries_per_s']:.4g} queries/s), "
+        f"{100 * out['frac_within_R_eval']:.1f}% within R_eval, {out['mean_points_blended']:.1f} points blended")
+    del sdf
+    return out
+
+
 def large_bench(reps: int, trace: bool):
     """Large photogrammetry-like cloud: N = 2^20 points on 32 primitives (density
     varying 10x, sigma 0.005 noise, 3% outliers), 2^20 uniform queries; and,
@@ -206,6 +232,7 @@ def large_bench(reps: int, trace: bool):
                        f"3% outliers; {Q} uniform queries", "N": N, "Q": Q,
            "eval_ms": ms_eval, "build_ms": ms_build, "pairs_per_s": float(N) * Q / (ms_eval * 1e-3)}
     log(f"large: eval {ms_eval:.1f} ms ({out['pairs_per_s']:.4g} pairs/s), build {ms_build:.2f} ms")
+    out["radius_limited"] = radius_bench("large", cl, x)
     if trace:
         import numpy as np
         lo, hi = cl.p.min(0), cl.p.max(0)
@@ -455,6 +482,7 @@ def main():
         "stages_ms": stage,
         "roofline": roofline,
     }
+    out["radius_limited"] = radius_bench("mid", cl, x)
     if not args.no_diff:
         out["diff"] = diff_bench(5)
     if not args.no_large:
