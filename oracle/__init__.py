@@ -5,14 +5,17 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 shares no code with it.  The C++ source is ``pts_oracle.cpp`` in this folder.
 Each function there cites the passage of the paper it follows (Sec. 4.1 torus
 fitting, Sec. 4.2 Eqs. (BasicFormulaShifted)/(RelationshipBetweenLambdaAndRadius),
-Sec. 5.3 sphere tracing).  Derivatives are exact derivatives of the same code,
-via forward-mode dual numbers.
+Sec. 5.3 sphere tracing, Sec. 4.2 radius-limited evaluation).  Derivatives
+(in x, the coefficients a, the points p and normals n, and the Laplacian in x)
+are exact derivatives of the same code, via forward-mode dual and hyper-dual
+numbers.
 
-Parity pins (see ``tests/test_oracle_pins.py``): sphere closed form, single
-torus vs. brute-force surface distance, torus round trip, principal curvatures
-vs. a generic shape-operator computation, orientation/scale/translation/
-permutation invariances, the large-C nearest-point limit, and finite
-differences for both gradients.
+Parity pins (see ``tests/test_oracle_pins.py``): sphere closed form (values and
+Laplacian 2/|x|), single torus vs. brute-force surface distance, torus round
+trip, principal curvatures vs. a generic shape-operator computation,
+orientation/scale/translation/permutation invariances, the large-C
+nearest-point limit, finite differences for every gradient and the Laplacian,
+and brute-force nearest neighbours for the radius-limited evaluation.
 """
 
 from __future__ import annotations
@@ -72,6 +75,11 @@ def lib():
         L.orc_trace.argtypes = [i64, P, P, i64, P, P, ctypes.c_int, ctypes.c_double,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_int, P, P, P, P]
         L.orc_trace.restype = ctypes.c_int
+        L.orc_laplacian.argtypes = [i64, P, P, i64, P, ctypes.c_double, ctypes.c_int, P]
+        L.orc_laplacian.restype = ctypes.c_int
+        L.orc_grad_points.argtypes = [i64, P, P, P, ctypes.c_double, ctypes.c_int, i64, P, ctypes.c_double, P,
+                                      ctypes.c_int, P, P, P]
+        L.orc_grad_points.restype = ctypes.c_int
         L.orc_knn_mean.argtypes = [i64, P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
         L.orc_knn_mean.restype = ctypes.c_int
         L.orc_eval_radius.argtypes = [i64, P, P, i64, P, ctypes.c_double, ctypes.c_double, ctypes.c_int,
@@ -209,6 +217,37 @@ def grad_a(p, n, a, x, gout, C: float = C_DEFAULT, kfloor: float | None = None,
     if rc != 0:
         raise ValueError("oracle grad_a: empty cloud")
     return ga
+
+
+def laplacian(p, tori: Tori, x, C: float = C_DEFAULT, nthreads: int = 0) -> np.ndarray:
+    """Laplacian of phi (Eq. BasicFormulaShifted, lambda_x moving with x; App. D), [Q]."""
+    p = _f64(p, 3)
+    x = _f64(x, 3)
+    lap = np.zeros(x.shape[0])
+    if lib().orc_laplacian(p.shape[0], _ptr(p), _ptr(tori.raw), x.shape[0], _ptr(x), float(C), int(nthreads),
+                           _ptr(lap)) != 0:
+        raise ValueError("oracle laplacian: empty cloud")
+    return lap
+
+
+def grad_points(p, n, a, x, gout, C: float = C_DEFAULT, kfloor: float | None = None, center_mode: int = 0,
+                nthreads: int = 0):
+    """(dL/da [N,6], dL/dp [N,3], dL/dn [N,3]) for L = sum_q gout_q phi(x_q): exact derivatives through
+    each point's torus fit, its weight and (as the farthest point of a query) lambda_x."""
+    p = _f64(p, 3)
+    n = _f64(n, 3)
+    a = _f64(a, 6)
+    x = _f64(x, 3)
+    gout = _f64(gout).reshape(-1)
+    if kfloor is None:
+        kfloor = kfloor_for(p)
+    N = p.shape[0]
+    ga, gp, gn = np.zeros((N, 6)), np.zeros((N, 3)), np.zeros((N, 3))
+    rc = lib().orc_grad_points(N, _ptr(p), _ptr(n), _ptr(a), float(kfloor), int(center_mode), x.shape[0],
+                               _ptr(x), float(C), _ptr(gout), int(nthreads), _ptr(ga), _ptr(gp), _ptr(gn))
+    if rc != 0:
+        raise ValueError("oracle grad_points: empty cloud")
+    return ga, gp, gn
 
 
 def trace(p, tori: Tori, org, dirs, steps: int, eps: float, tmax: float, C: float = C_DEFAULT,

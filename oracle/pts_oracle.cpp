@@ -15,10 +15,13 @@
 //   * sphere tracing           Sec. 5.3 ("Direct visualization")
 // There is no blocking, fusion or reordering beyond those definitions.
 //
-// Derivatives (d phi/dx, d phi/da) are not hand-derived here: the same
-// templated code is evaluated on forward-mode dual numbers, so they are the
-// exact derivatives of what this file computes.  The GPU path implements the
-// closed-form gradient of App. D (plus the x-dependence of lambda_x) instead.
+// Derivatives (d phi/dx, d phi/da, d phi/dp, d phi/dn, and the Laplacian of
+// phi in x; Sec. 6 and App. D) are not hand-derived here: the same templated
+// code is evaluated on forward-mode dual numbers (first derivatives) and
+// hyper-dual numbers (exact second derivatives along one coordinate), so they
+// are the exact derivatives of what this file computes.  The GPU path
+// implements the closed forms of App. D (plus the x-dependence of lambda_x)
+// instead.
 //
 // Readings of the paper where it is silent or inconsistent (kept identical on
 // both sides; each is listed in the design notes):
@@ -91,6 +94,43 @@ template <int K> inline Dual<K> operator*(double a, const Dual<K>& b) { return D
 template <int K> inline Dual<K> operator/(const Dual<K>& a, double b) { return a / Dual<K>(b); }
 template <int K> inline Dual<K> operator/(double a, const Dual<K>& b) { return Dual<K>(a) / b; }
 
+// Hyper-dual numbers a + b e1 + c e2 + d e1 e2 (e1^2 = e2^2 = 0): with
+// b = c = 1 along one coordinate, d is the exact second derivative along it.
+struct HD {
+  double a = 0.0, b = 0.0, c = 0.0, d = 0.0;
+  HD() = default;
+  HD(double v) : a(v) {}
+  HD(double a_, double b_, double c_, double d_) : a(a_), b(b_), c(c_), d(d_) {}
+};
+inline HD operator+(const HD& x, const HD& y) { return HD(x.a + y.a, x.b + y.b, x.c + y.c, x.d + y.d); }
+inline HD operator-(const HD& x, const HD& y) { return HD(x.a - y.a, x.b - y.b, x.c - y.c, x.d - y.d); }
+inline HD operator-(const HD& x) { return HD(-x.a, -x.b, -x.c, -x.d); }
+inline HD operator*(const HD& x, const HD& y) {
+  return HD(x.a * y.a, x.a * y.b + x.b * y.a, x.a * y.c + x.c * y.a, x.a * y.d + x.b * y.c + x.c * y.b + x.d * y.a);
+}
+// f(x) from f(a), f'(a), f''(a)
+inline HD chain(const HD& x, double f0, double f1, double f2) {
+  return HD(f0, f1 * x.b, f1 * x.c, f1 * x.d + f2 * x.b * x.c);
+}
+inline HD inv(const HD& y) { const double r = 1.0 / y.a; return chain(y, r, -r * r, 2.0 * r * r * r); }
+inline HD operator/(const HD& x, const HD& y) { return x * inv(y); }
+inline HD operator+(const HD& x, double y) { return x + HD(y); }
+inline HD operator+(double x, const HD& y) { return HD(x) + y; }
+inline HD operator-(const HD& x, double y) { return x - HD(y); }
+inline HD operator-(double x, const HD& y) { return HD(x) - y; }
+inline HD operator*(const HD& x, double y) { return HD(x.a * y, x.b * y, x.c * y, x.d * y); }
+inline HD operator*(double x, const HD& y) { return y * x; }
+inline HD operator/(const HD& x, double y) { return x * (1.0 / y); }
+inline HD operator/(double x, const HD& y) { return HD(x) / y; }
+inline double val(const HD& x) { return x.a; }
+inline HD Sqrt(const HD& x) {
+  if (x.a <= 0.0) return HD(0.0);  // no derivative at 0 (as for the dual numbers)
+  const double s = std::sqrt(x.a);
+  return chain(x, s, 0.5 / s, -0.25 / (s * x.a));
+}
+inline HD Exp(const HD& x) { const double e = std::exp(x.a); return chain(x, e, e, e); }
+inline HD Abs(const HD& x) { return x.a < 0.0 ? -x : x; }
+
 inline double val(double x) { return x; }
 template <int K> inline double val(const Dual<K>& x) { return x.v; }
 
@@ -129,15 +169,16 @@ struct Torus {
 };
 
 // R-frame: the fixed orthonormal basis (s, t, n) at a point.
-void local_frame(const double* n_in, double* nh, double* s, double* t) {
-  double len = std::sqrt(n_in[0] * n_in[0] + n_in[1] * n_in[1] + n_in[2] * n_in[2]);
+template <class T>
+void local_frame(const T* n_in, T* nh, T* s, T* t) {
+  T len = Sqrt(dot3(n_in, n_in));
   for (int k = 0; k < 3; ++k) nh[k] = n_in[k] / len;
   double e[3] = {0.0, 0.0, 0.0};
-  if (std::fabs(nh[0]) < 0.9) e[0] = 1.0; else e[1] = 1.0;
-  double en = dot3(e, nh);
+  if (std::fabs(val(nh[0])) < 0.9) e[0] = 1.0; else e[1] = 1.0;
+  T en = e[0] * nh[0] + e[1] * nh[1] + e[2] * nh[2];
   for (int k = 0; k < 3; ++k) s[k] = e[k] - en * nh[k];
-  double sl = norm3(s);
-  for (int k = 0; k < 3; ++k) s[k] /= sl;
+  T sl = norm3(s);
+  for (int k = 0; k < 3; ++k) s[k] = s[k] / sl;
   cross3(nh, s, t);
 }
 
@@ -149,12 +190,13 @@ template <class T> T floor_curvature(const T& k, double kfloor) {
 }
 
 // Torus fitting of Sec. 4.1 for one point.  a = (a00, a01, a10, a11, a02, a20).
+// p, n and a may all carry derivatives (T = double or a dual number).
 template <class T>
-Torus<T> fit_torus(const double* p, const double* n_in, const T* a, double kfloor, int center_mode) {
+Torus<T> fit_torus(const T* p, const T* n_in, const T* a, double kfloor, int center_mode) {
   Torus<T> tor;
   const T& a00 = a[0]; const T& a01 = a[1]; const T& a10 = a[2];
   const T& a11 = a[3]; const T& a02 = a[4]; const T& a20 = a[5];
-  double nh[3], s[3], t[3];
+  T nh[3], s[3], t[3];
   local_frame(n_in, nh, s, t);
 
   // Fundamental forms at (0,0) and Eq. (MeanAndGaussCurvatures).
@@ -192,7 +234,7 @@ Torus<T> fit_torus(const double* p, const double* n_in, const T* a, double kfloo
   tor.umbilic = 0;
   if (!(std::sqrt(nw) > 1e-12 * scale)) {
     tor.umbilic = 1;  // R-umbilic
-    for (int k = 0; k < 3; ++k) vmin[k] = T(s[k]);
+    for (int k = 0; k < 3; ++k) vmin[k] = s[k];
   } else {
     T v[3];
     for (int k = 0; k < 3; ++k) v[k] = wx * (s[k] + a10 * nh[k]) + wy * (t[k] + a01 * nh[k]);
@@ -459,7 +501,9 @@ int orc_grad_a(int64_t N, const double* p, const double* n, const double* a, dou
   for (int64_t i = 0; i < N; ++i) {
     Dual<6> ad[6];
     for (int j = 0; j < 6; ++j) { ad[j] = Dual<6>(a[6 * i + j]); ad[j].d[j] = 1.0; }
-    Torus<Dual<6>> t = fit_torus<Dual<6>>(p + 3 * i, n + 3 * i, ad, kfloor, center_mode);
+    Dual<6> pd[3], nd[3];
+    for (int k = 0; k < 3; ++k) { pd[k] = Dual<6>(p[3 * i + k]); nd[k] = Dual<6>(n[3 * i + k]); }
+    Torus<Dual<6>> t = fit_torus<Dual<6>>(pd, nd, ad, kfloor, center_mode);
     double acc[6] = {0, 0, 0, 0, 0, 0};
     for (int64_t q = 0; q < Q; ++q) {
       if (gout[q] == 0.0) continue;
@@ -509,6 +553,115 @@ int orc_trace(int64_t N, const double* p, const double* tor, int64_t Rn, const d
       double gl = std::sqrt(f.d[0] * f.d[0] + f.d[1] * f.d[1] + f.d[2] * f.d[2]);
       if (gl > 0.0) for (int j = 0; j < 3; ++j) normal_out[3 * r + j] = f.d[j] / gl;
     }
+  }
+  return 0;
+}
+
+// Laplacian of phi at Q queries: the exact sum of second derivatives of
+// Eq. (BasicFormulaShifted) with sigma_x, lambda_x moving with x (App. D gives
+// the fixed-lambda terms), one hyper-dual evaluation per coordinate.
+int orc_laplacian(int64_t N, const double* p, const double* tor, int64_t Q, const double* x, double C,
+                  int nthreads, double* lap) {
+  if (N <= 0) return 1;
+  set_threads(nthreads);
+  std::vector<Torus<double>> tt(N);
+  for (int64_t i = 0; i < N; ++i) tt[i] = load_torus(tor + (size_t)TSTRIDE * i);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t q = 0; q < Q; ++q) {
+    double s = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      HD xh[3];
+      for (int c = 0; c < 3; ++c) xh[c] = HD(x[3 * q + c]);
+      xh[k].b = 1.0;
+      xh[k].c = 1.0;
+      s += blend_at(N, p, tt, xh, C, nullptr, nullptr).d;
+    }
+    lap[q] = s;
+  }
+  return 0;
+}
+
+// dL/da [N,6], dL/dp [N,3], dL/dn [N,3] for L = sum_q gout_q phi(x_q)
+// (differentiable representation, Sec. 6): exact forward-mode derivatives of
+// phi through each point's torus fit (a, p, n), its weight (p) and, for the
+// queries whose farthest point it is, lambda_x = 2C/M (p).  The normal n is
+// the input vector (not normalised), as in the fit.
+int orc_grad_points(int64_t N, const double* p, const double* n, const double* a, double kfloor,
+                    int center_mode, int64_t Q, const double* x, double C, const double* gout, int nthreads,
+                    double* ga, double* gp, double* gn) {
+  if (N <= 0) return 1;
+  set_threads(nthreads);
+  std::vector<Torus<double>> tt(N);
+  for (int64_t i = 0; i < N; ++i) tt[i] = fit_torus<double>(p + 3 * i, n + 3 * i, a + 6 * i, kfloor, center_mode);
+  // per query: M, its first farthest point, W and phi (Eq. BasicFormulaShifted)
+  std::vector<double> M(Q), W(Q), PHI(Q);
+  std::vector<int64_t> IM(Q);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t q = 0; q < Q; ++q) {
+    std::vector<double> d(N);
+    int64_t im = 0;
+    for (int64_t i = 0; i < N; ++i) {
+      double dv[3];
+      for (int k = 0; k < 3; ++k) dv[k] = x[3 * q + k] - p[3 * i + k];
+      d[i] = norm3(dv);
+      if (d[i] > d[im]) im = i;
+    }
+    const double m = d[im];
+    double num = 0.0, den = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+      const double w = (m == 0.0) ? 1.0 : std::exp(-(C / (0.5 * m)) * (d[i] - 0.5 * m));
+      num += w * torus_g(tt[i], x + 3 * q);
+      den += w;
+    }
+    M[q] = m; IM[q] = im; W[q] = den; PHI[q] = num / den;
+  }
+  using D12 = Dual<12>;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < N; ++i) {
+    D12 ad[6], pd[3], nd[3];
+    for (int j = 0; j < 6; ++j) { ad[j] = D12(a[6 * i + j]); ad[j].d[j] = 1.0; }
+    for (int k = 0; k < 3; ++k) {
+      pd[k] = D12(p[3 * i + k]); pd[k].d[6 + k] = 1.0;
+      nd[k] = D12(n[3 * i + k]); nd[k].d[9 + k] = 1.0;
+    }
+    const Torus<D12> t = fit_torus<D12>(pd, nd, ad, kfloor, center_mode);
+    double acc[12] = {0};
+    for (int64_t q = 0; q < Q; ++q) {
+      if (gout[q] == 0.0) continue;
+      const double* xq = x + 3 * q;
+      D12 dv[3];
+      for (int k = 0; k < 3; ++k) dv[k] = xq[k] - pd[k];
+      const D12 di = norm3(dv);
+      const D12 gi = torus_g(t, xq);
+      D12 phi;
+      if (M[q] == 0.0) {
+        phi = gi / double(N);                      // R-M0: uniform weights (only g_i moves)
+      } else if (IM[q] != i) {
+        const double sig = 0.5 * M[q], lam = C / sig;
+        const D12 wi = Exp(-lam * (di - sig));
+        phi = (wi * gi - PHI[q] * wi) / W[q];      // d/dtheta of (num_rest + w g)/(W_rest + w)
+      } else {                                     // point i fixes M, hence sigma_x and lambda_x
+        const D12 sig = 0.5 * di, lam = C / sig;
+        D12 num(0.0), den(0.0);
+        for (int64_t j = 0; j < N; ++j) {
+          if (j == i) {
+            const D12 w = Exp(-lam * (di - sig));
+            num = num + w * gi;
+            den = den + w;
+          } else {
+            double dj[3];
+            for (int k = 0; k < 3; ++k) dj[k] = xq[k] - p[3 * j + k];
+            const D12 w = Exp(-lam * (norm3(dj) - sig));
+            num = num + w * torus_g(tt[j], xq);
+            den = den + w;
+          }
+        }
+        phi = num / den;
+      }
+      for (int j = 0; j < 12; ++j) acc[j] += gout[q] * phi.d[j];
+    }
+    for (int j = 0; j < 6; ++j) ga[6 * i + j] = acc[j];
+    for (int k = 0; k < 3; ++k) { gp[3 * i + k] = acc[6 + k]; gn[3 * i + k] = acc[9 + k]; }
   }
   return 0;
 }

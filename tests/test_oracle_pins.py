@@ -447,6 +447,70 @@ def test_grad_a_matches_finite_differences():
             assert abs(fd - ga[i, j]) < 1e-6 * max(1.0, abs(fd)), (i, j, fd, ga[i, j])
 
 
+def test_grad_points_matches_finite_differences():
+    # dL/dp and dL/dn move the torus, the weight and, for a query's farthest
+    # point, lambda_x; central differences of the oracle's phi pin all three
+    p, n, a = _mixed_cloud(N=300)
+    rng = np.random.default_rng(36)
+    x = rng.uniform(-1.0, 1.0, size=(80, 3))
+    gout = rng.normal(size=80)
+    kf = oracle.kfloor_for(p)
+    ga, gp, gn = oracle.grad_points(p, n, a, x, gout, kfloor=kf)
+    assert np.allclose(ga, oracle.grad_a(p, n, a, x, gout, kfloor=kf), rtol=1e-10, atol=1e-12)
+    far = np.argmax(np.linalg.norm(x[:, None, :] - p[None], axis=2), axis=1)
+    idx = list(rng.choice(p.shape[0], size=10, replace=False)) + list(np.unique(far)[:4])
+    h = 1e-6
+    for i in idx:
+        for arr, g in ((p, gp), (n, gn)):
+            for k in range(3):
+                ap, am = arr.copy(), arr.copy()
+                ap[i, k] += h
+                am[i, k] -= h
+                if arr is p:
+                    Lp = gout @ oracle.sdf(ap, n, a, x, kfloor=kf)
+                    Lm = gout @ oracle.sdf(am, n, a, x, kfloor=kf)
+                else:
+                    Lp = gout @ oracle.sdf(p, ap, a, x, kfloor=kf)
+                    Lm = gout @ oracle.sdf(p, am, a, x, kfloor=kf)
+                fd = (Lp - Lm) / (2 * h)
+                assert abs(fd - g[i, k]) < 2e-6 * max(1.0, abs(fd)), (i, k, arr is p, fd, g[i, k])
+
+
+def test_laplacian_sphere_closed_form():
+    # every torus of the exact unit sphere is the sphere itself, so phi = |x| - 1
+    # and its Laplacian is 2 / |x| wherever the weights move
+    p, n, a = _sphere(400, 1.0, seed=37)
+    tor = oracle.fit(p, n, a)
+    rng = np.random.default_rng(38)
+    x = rng.uniform(-2.5, 2.5, size=(40, 3))
+    x = x[np.linalg.norm(x, axis=1) > 0.05]
+    lap = oracle.laplacian(p, tor, x)
+    assert np.allclose(lap, 2.0 / np.linalg.norm(x, axis=1), rtol=1e-9, atol=1e-9)
+
+
+def test_laplacian_matches_second_differences():
+    # the sum of the three second central differences of the oracle's phi
+    # (Richardson-extrapolated over h and h/2 to cancel the h^2 error)
+    p, n, a = _mixed_cloud(N=300)
+    tor = oracle.fit(p, n, a)
+    rng = np.random.default_rng(39)
+    x = rng.uniform(-1.0, 1.0, size=(24, 3))
+    lap = oracle.laplacian(p, tor, x)
+    phi0 = oracle.eval_sdf(p, tor, x)
+
+    def second_diff(h):
+        out = np.zeros(len(x))
+        for k in range(3):
+            e = np.zeros(3)
+            e[k] = h
+            out += (oracle.eval_sdf(p, tor, x + e) - 2 * phi0 + oracle.eval_sdf(p, tor, x - e)) / (h * h)
+        return out
+
+    fd = (4 * second_diff(5e-4) - second_diff(1e-3)) / 3
+    assert np.abs(fd).max() > 5.0
+    assert np.allclose(lap, fd, rtol=1e-5, atol=1e-5 * np.abs(fd).max())
+
+
 # ---------------------------------------------------------------------------
 # Sphere tracing on the exact sphere
 # ---------------------------------------------------------------------------
