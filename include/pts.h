@@ -189,6 +189,30 @@ int pts_grad_x(const void* rec, int64_t N, const float* x, int64_t Q, const floa
                const float* stats, float* gx, const pts_params* prm, void* ws, size_t ws_bytes,
                void* stream);
 
+/* Scratch bytes for pts_laplacian. */
+int pts_laplacian_ws_bytes(int64_t N, int64_t Q, const pts_params* prm, size_t* out_bytes);
+
+/* Second-order quantities of phi at Q queries (App. D gives the Laplacian for
+ * a fixed lambda; here lambda_x = 2C/M moves with x as in pts_eval's
+ * gradient), from the statistics a pts_eval call wrote for the same queries:
+ *   lap [Q]    Laplacian of phi: the fixed-lambda Laplacian plus
+ *              2 kappa grad V . e_* + kappa^2 F_ll, kappa = 2C/M^2,
+ *              V = (1/W) sum_i w_i (g_i - phi) d_i, F_ll = <(g - phi) d^2> - 2 <d> V
+ *              (1/M is harmonic in 3D, so lambda_x adds no Laplacian of its own);
+ *   grad [Q,3] grad phi (the quantity pts_eval computes, here from the same
+ *              sweep);
+ *   eik [Q]    eikonal residual |grad phi| - 1 (its absolute value, averaged
+ *              over queries, is the eikonal term of Eq. LossFunction, Sec. 4.3).
+ * Each output may be NULL; at least one must be given.  One query-major sweep
+ * over all points with 22 weighted sums per query, then a fixed-order
+ * combine; deterministic.  On a torus's axis, core circle and at a query on a
+ * point the undefined factor is 0, as for the gradient.  Per-pair arithmetic
+ * in FP32; the weighted sums are carried and combined in FP64 because the
+ * formula cancels terms of size 2C/M down to the Laplacian.
+ * ws_bytes >= pts_laplacian_ws_bytes(N, Q, prm). */
+int pts_laplacian(const void* rec, int64_t N, const float* x, int64_t Q, const float* stats, float* lap,
+                  float* grad, float* eik, const pts_params* prm, void* ws, size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Backward with respect to the per-point coefficients (the representation is
  * differentiable, Sec. 6): ga[i] = dL/da_i for L = sum_q gout[q] phi(x_q).
@@ -211,6 +235,34 @@ int pts_backward_ws_bytes(int64_t N, int64_t Q, const pts_params* prm, size_t* o
 int pts_backward_params(const void* rec, int64_t N, const float* p, const float* n, const float* a,
                         const float* x, int64_t Q, const float* gout, const float* stats, float* ga,
                         const pts_params* prm, void* ws, size_t ws_bytes, void* stream);
+
+/* Scratch bytes for pts_backward_points (any combination of outputs). */
+int pts_backward_points_ws_bytes(int64_t N, int64_t Q, const pts_params* prm, size_t* out_bytes);
+
+/* dL/da [N,6], dL/dp [N,3] and dL/dn [N,3] for L = sum_q gout[q] phi(x_q)
+ * (device float32, the caller's point order; each output may be NULL, at
+ * least one must be given).  Arguments as pts_backward_params.
+ *   ga  as pts_backward_params (the same values, bit for bit).
+ *   gn  through the torus fit of Sec. 4.1 on the (not necessarily unit)
+ *       input normal: its normalisation, the tangent frame built from it and
+ *       the anchor o = p + a00 n.  The choice of the frame's seed axis (x-hat
+ *       unless |n_x| >= 0.9) is piecewise constant and not differentiated.
+ *   gp  the torus moves rigidly with its point, so its share is minus the
+ *       force on the anchor; the weights of Eq. (BasicFormulaShifted) add
+ *       sum_q gout_q (w_qi/W_q) lambda_q (g_i - phi_q) e_qi with
+ *       e = (x - p_i)/|x - p_i|, and the farthest point p_* of each query
+ *       (which sets M, hence sigma_x and lambda_x of
+ *       Eq. RelationshipBetweenLambdaAndRadius) adds
+ *       -gout_q (2C/M^2) V_q e_*, V_q = (1/W) sum_j w_j (g_j - phi_q) d_j.
+ *       Ties for the farthest point go to the lowest record slot (the
+ *       build's spatial order).
+ * With gp the call re-runs the culled farthest-point sweep and one weighted
+ * query sweep before the point sweep.  Deterministic (fixed-order reductions,
+ * no atomics).  ws_bytes >= pts_backward_points_ws_bytes(N, Q, prm). */
+int pts_backward_points(const void* rec, int64_t N, const float* p, const float* n, const float* a,
+                        const float* x, int64_t Q, const float* gout, const float* stats, float* ga,
+                        float* gp, float* gn, const pts_params* prm, void* ws, size_t ws_bytes,
+                        void* stream);
 
 /* ---------------------------------------------------------------------------
  * Sphere tracing (Sec. 5.3, "Direct visualization of point cloud surfaces").

@@ -98,9 +98,14 @@ SIGNATURES = {
     "pts_eval_combine": (ctypes.c_int, [_I64, _I64, _P, ctypes.POINTER(Params), _P, _SZ, _P]),
     "pts_grad_ws_bytes": (ctypes.c_int, [_I64, _I64, ctypes.POINTER(Params), ctypes.POINTER(_SZ)]),
     "pts_grad_x": (ctypes.c_int, [_P, _I64, _P, _I64, _P, _P, _P, ctypes.POINTER(Params), _P, _SZ, _P]),
+    "pts_laplacian_ws_bytes": (ctypes.c_int, [_I64, _I64, ctypes.POINTER(Params), ctypes.POINTER(_SZ)]),
+    "pts_laplacian": (ctypes.c_int, [_P, _I64, _P, _I64, _P, _P, _P, _P, ctypes.POINTER(Params), _P, _SZ, _P]),
     "pts_backward_ws_bytes": (ctypes.c_int, [_I64, _I64, ctypes.POINTER(Params), ctypes.POINTER(_SZ)]),
     "pts_backward_params": (ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _I64, _P, _P, _P, ctypes.POINTER(Params), _P,
                                            _SZ, _P]),
+    "pts_backward_points_ws_bytes": (ctypes.c_int, [_I64, _I64, ctypes.POINTER(Params), ctypes.POINTER(_SZ)]),
+    "pts_backward_points": (ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _I64, _P, _P, _P, _P, _P,
+                                           ctypes.POINTER(Params), _P, _SZ, _P]),
     "pts_trace_ws_bytes": (ctypes.c_int, [_I64, _I64, ctypes.POINTER(Params), ctypes.POINTER(_SZ)]),
     "pts_trace": (ctypes.c_int, [_P, _I64, _P, _P, _I64, ctypes.c_int, ctypes.c_float, ctypes.c_float, _P, _P, _P, _P,
                                  ctypes.POINTER(Params), _P, _SZ, _P]),
@@ -289,6 +294,36 @@ def eval_combine(N: int, Q: int, sdf: torch.Tensor, params: Params, ws: torch.Te
     _check(lib().pts_eval_combine(int(N), int(Q), _ptr(sdf), ctypes.byref(params), _ptr(ws), ws.numel(), _stream()))
 
 
+def laplacian_ws_bytes(N: int, Q: int, params: Params | None = None) -> int:
+    out = _SZ(0)
+    prm = params if params is not None else make_params()
+    _check(lib().pts_laplacian_ws_bytes(int(N), int(Q), ctypes.byref(prm), ctypes.byref(out)))
+    return int(out.value)
+
+
+def laplacian(rec: torch.Tensor, N: int, x: torch.Tensor, stats: torch.Tensor, params: Params | None = None,
+              want: str = "lge", ws: torch.Tensor | None = None):
+    """(Laplacian [Q], grad phi [Q,3], eikonal residual |grad phi| - 1 [Q]) from the statistics of an eval at x;
+    entries not in `want` ('l', 'g', 'e') are None."""
+    _dev(x, "x", 3)
+    _dev(stats, "stats", 6)
+    if not want or set(want) - set("lge"):
+        raise ValueError("want must be a non-empty subset of 'lge'")
+    Q = x.shape[0]
+    prm = params if params is not None else make_params()
+    lap = torch.empty(Q, dtype=torch.float32, device=x.device) if "l" in want else None
+    grad = torch.empty((Q, 3), dtype=torch.float32, device=x.device) if "g" in want else None
+    eik = torch.empty(Q, dtype=torch.float32, device=x.device) if "e" in want else None
+    if Q == 0:
+        return lap, grad, eik
+    need = laplacian_ws_bytes(N, Q, prm)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device=x.device)
+    _check(lib().pts_laplacian(_ptr(rec), int(N), _ptr(x), Q, _ptr(stats), _ptr(lap), _ptr(grad), _ptr(eik),
+                               ctypes.byref(prm), _ptr(ws), ws.numel(), _stream()))
+    return lap, grad, eik
+
+
 def backward_ws_bytes(N: int, Q: int, params: Params | None = None) -> int:
     out = _SZ(0)
     prm = params if params is not None else make_params()
@@ -318,6 +353,42 @@ def backward_params(rec: torch.Tensor, p: torch.Tensor, n: torch.Tensor, a: torc
     _check(lib().pts_backward_params(_ptr(rec), N, _ptr(p), _ptr(n), _ptr(a), _ptr(x), Q, _ptr(gout), _ptr(stats),
                                      _ptr(ga), ctypes.byref(prm), _ptr(ws), ws.numel(), _stream()))
     return ga
+
+
+def backward_points_ws_bytes(N: int, Q: int, params: Params | None = None) -> int:
+    out = _SZ(0)
+    prm = params if params is not None else make_params()
+    _check(lib().pts_backward_points_ws_bytes(int(N), int(Q), ctypes.byref(prm), ctypes.byref(out)))
+    return int(out.value)
+
+
+def backward_points(rec: torch.Tensor, p: torch.Tensor, n: torch.Tensor, a: torch.Tensor, x: torch.Tensor,
+                    stats: torch.Tensor, gout: torch.Tensor | None = None, params: Params | None = None,
+                    want: str = "apn", ws: torch.Tensor | None = None):
+    """(dL/da [N,6], dL/dp [N,3], dL/dn [N,3]) for L = sum_q gout_q phi(x_q); entries not in `want` are None."""
+    _dev(p, "p", 3)
+    _dev(n, "n", 3)
+    _dev(a, "a", 6)
+    _dev(x, "x", 3)
+    _dev(stats, "stats", 6)
+    N, Q = p.shape[0], x.shape[0]
+    if gout is not None:
+        _dev(gout, "gout")
+        if gout.numel() != Q:
+            raise ValueError("gout must have one value per query")
+    if not want or set(want) - set("apn"):
+        raise ValueError("want must be a non-empty subset of 'apn'")
+    prm = params if params is not None else make_params()
+    ga = torch.empty((N, 6), dtype=torch.float32, device=p.device) if "a" in want else None
+    gp = torch.empty((N, 3), dtype=torch.float32, device=p.device) if "p" in want else None
+    gn = torch.empty((N, 3), dtype=torch.float32, device=p.device) if "n" in want else None
+    need = backward_points_ws_bytes(N, Q, prm)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device=p.device)
+    _check(lib().pts_backward_points(_ptr(rec), N, _ptr(p), _ptr(n), _ptr(a), _ptr(x), Q, _ptr(gout), _ptr(stats),
+                                     _ptr(ga), _ptr(gp), _ptr(gn), ctypes.byref(prm), _ptr(ws), ws.numel(),
+                                     _stream()))
+    return ga, gp, gn
 
 
 def trace(rec: torch.Tensor, N: int, origin: torch.Tensor, direction: torch.Tensor, steps: int, eps: float,

@@ -280,6 +280,29 @@ int pts_grad_x(const void* rec, int64_t N, const float* x, int64_t Q, const floa
                      static_cast<hipStream_t>(stream));
 }
 
+int pts_laplacian_ws_bytes(int64_t N, int64_t Q, const pts_params* prm, size_t* out_bytes) {
+  if (!out_bytes) return fail(PTS_EINVAL, "out_bytes is NULL");
+  if (N < 1 || Q < 0) return fail(PTS_EINVAL, "N must be >= 1 and Q >= 0");
+  const pts_params P = resolve(prm);
+  if (int rc = check_params(P)) return rc;
+  *out_bytes = Q == 0 ? 0 : lap_ws_bytes(make_plan(N, Q, &P), Q);
+  return PTS_OK;
+}
+
+int pts_laplacian(const void* rec, int64_t N, const float* x, int64_t Q, const float* stats, float* lap,
+                  float* grad, float* eik, const pts_params* prm, void* ws, size_t ws_bytes, void* stream) {
+  if (N < 1 || Q < 0) return fail(PTS_EINVAL, "N must be >= 1 and Q >= 0");
+  if (Q > (int64_t(1) << 31) - 1) return fail(PTS_EINVAL, "Q must be < 2^31");
+  if (!lap && !grad && !eik) return fail(PTS_EINVAL, "no output requested");
+  const pts_params P = resolve(prm);
+  if (int rc = check_params(P)) return rc;
+  if (Q == 0) return PTS_OK;
+  if (!rec || !x || !stats || !ws) return fail(PTS_EINVAL, "null pointer");
+  const Plan plan = make_plan(N, Q, &P);
+  if (ws_bytes < lap_ws_bytes(plan, Q)) return fail(PTS_EINVAL, "workspace too small");
+  return launch_lap(rec, N, x, Q, stats, lap, grad, eik, P.C, plan, ws, static_cast<hipStream_t>(stream));
+}
+
 int pts_backward_ws_bytes(int64_t N, int64_t Q, const pts_params* prm, size_t* out_bytes) {
   if (!out_bytes) return fail(PTS_EINVAL, "out_bytes is NULL");
   if (N < 1 || Q < 0) return fail(PTS_EINVAL, "N must be >= 1 and Q >= 0");
@@ -300,7 +323,37 @@ int pts_backward_params(const void* rec, int64_t N, const float* p, const float*
   if (int rc = check_params(P)) return rc;
   if (ws_bytes < back_ws_bytes(N, Q == 0 ? 1 : Q)) return fail(PTS_EINVAL, "workspace too small");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  return launch_backward(rec, N, p, n, a, x, Q, gout, stats, ga, P.C, ws, st);
+  return launch_backward(rec, N, p, n, a, x, Q, gout, stats, ga, nullptr, nullptr, P.C, Plan{}, ws, st);
+}
+
+int pts_backward_points_ws_bytes(int64_t N, int64_t Q, const pts_params* prm, size_t* out_bytes) {
+  if (!out_bytes) return fail(PTS_EINVAL, "out_bytes is NULL");
+  if (N < 1 || Q < 0) return fail(PTS_EINVAL, "N must be >= 1 and Q >= 0");
+  const pts_params P = resolve(prm);
+  if (int rc = check_params(P)) return rc;
+  const int64_t Qe = Q == 0 ? 1 : Q;
+  const size_t wp = back_points_ws(N, Qe, make_plan(N, Qe, &P), nullptr).bytes;
+  const size_t wa = back_ws_bytes(N, Qe);
+  *out_bytes = wp > wa ? wp : wa;
+  return PTS_OK;
+}
+
+int pts_backward_points(const void* rec, int64_t N, const float* p, const float* n, const float* a,
+                        const float* x, int64_t Q, const float* gout, const float* stats, float* ga, float* gp,
+                        float* gn, const pts_params* prm, void* ws, size_t ws_bytes, void* stream) {
+  if (N < 1 || Q < 0) return fail(PTS_EINVAL, "N must be >= 1 and Q >= 0");
+  if (Q > (int64_t(1) << 31) - 1) return fail(PTS_EINVAL, "Q must be < 2^31");
+  if (!ga && !gp && !gn) return fail(PTS_EINVAL, "no output requested");
+  if (!rec || !p || !n || !a || !ws) return fail(PTS_EINVAL, "null pointer");
+  if (Q > 0 && (!x || !stats)) return fail(PTS_EINVAL, "null queries or statistics");
+  const pts_params P = resolve(prm);
+  if (int rc = check_params(P)) return rc;
+  const int64_t Qe = Q == 0 ? 1 : Q;
+  const Plan plan = make_plan(N, Qe, &P);
+  const size_t need = gp ? back_points_ws(N, Qe, plan, nullptr).bytes : back_ws_bytes(N, Qe);
+  if (ws_bytes < need) return fail(PTS_EINVAL, "workspace too small");
+  return launch_backward(rec, N, p, n, a, x, Q, gout, stats, ga, gp, gn, P.C, plan, ws,
+                         static_cast<hipStream_t>(stream));
 }
 
 int pts_trace_ws_bytes(int64_t N, int64_t R, const pts_params* prm, size_t* out_bytes) {

@@ -1,62 +1,82 @@
 // pts_fit.h -- torus fitting of one point (Sec. 4.1), templated on the scalar
-// type so that the build kernel runs it on double and the parameter backward
-// runs it on 6-direction dual numbers (derivatives with respect to the six
-// coefficients).  Device code only.
+// type so that the build kernel runs it on double and the backward sweeps run
+// it on forward-mode dual numbers with K tangent directions (the six
+// coefficients, and optionally the three components of the normal).  Device
+// code only.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
 namespace pts {
 
-// Forward-mode dual number with six tangent directions.
-struct D6 {
+// Forward-mode dual number with K tangent directions.
+template <int K>
+struct Dual {
   double v;
-  double d[6];
+  double d[K];
 };
-__device__ __forceinline__ D6 d6(double v) {
-  D6 r;
+template <int K>
+__device__ __forceinline__ Dual<K> dual(double v) {
+  Dual<K> r;
   r.v = v;
-  for (int k = 0; k < 6; ++k) r.d[k] = 0.0;
+  for (int k = 0; k < K; ++k) r.d[k] = 0.0;
   return r;
 }
-__device__ __forceinline__ D6 operator+(const D6& a, const D6& b) {
-  D6 r; r.v = a.v + b.v; for (int k = 0; k < 6; ++k) r.d[k] = a.d[k] + b.d[k]; return r; }
-__device__ __forceinline__ D6 operator-(const D6& a, const D6& b) {
-  D6 r; r.v = a.v - b.v; for (int k = 0; k < 6; ++k) r.d[k] = a.d[k] - b.d[k]; return r; }
-__device__ __forceinline__ D6 operator-(const D6& a) {
-  D6 r; r.v = -a.v; for (int k = 0; k < 6; ++k) r.d[k] = -a.d[k]; return r; }
-__device__ __forceinline__ D6 operator*(const D6& a, const D6& b) {
-  D6 r; r.v = a.v * b.v; for (int k = 0; k < 6; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k]; return r; }
-__device__ __forceinline__ D6 operator/(const D6& a, const D6& b) {
-  D6 r; r.v = a.v / b.v;
+template <int K>
+__device__ __forceinline__ Dual<K> operator+(const Dual<K>& a, const Dual<K>& b) {
+  Dual<K> r; r.v = a.v + b.v; for (int k = 0; k < K; ++k) r.d[k] = a.d[k] + b.d[k]; return r; }
+template <int K>
+__device__ __forceinline__ Dual<K> operator-(const Dual<K>& a, const Dual<K>& b) {
+  Dual<K> r; r.v = a.v - b.v; for (int k = 0; k < K; ++k) r.d[k] = a.d[k] - b.d[k]; return r; }
+template <int K>
+__device__ __forceinline__ Dual<K> operator-(const Dual<K>& a) {
+  Dual<K> r; r.v = -a.v; for (int k = 0; k < K; ++k) r.d[k] = -a.d[k]; return r; }
+template <int K>
+__device__ __forceinline__ Dual<K> operator*(const Dual<K>& a, const Dual<K>& b) {
+  Dual<K> r; r.v = a.v * b.v; for (int k = 0; k < K; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k]; return r; }
+template <int K>
+__device__ __forceinline__ Dual<K> operator/(const Dual<K>& a, const Dual<K>& b) {
+  Dual<K> r; r.v = a.v / b.v;
   const double ib = 1.0 / b.v;
-  for (int k = 0; k < 6; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) * ib;
+  for (int k = 0; k < K; ++k) r.d[k] = (a.d[k] - r.v * b.d[k]) * ib;
   return r; }
-__device__ __forceinline__ D6 operator+(const D6& a, double b) { D6 r = a; r.v += b; return r; }
-__device__ __forceinline__ D6 operator+(double a, const D6& b) { return b + a; }
-__device__ __forceinline__ D6 operator-(const D6& a, double b) { D6 r = a; r.v -= b; return r; }
-__device__ __forceinline__ D6 operator-(double a, const D6& b) { return -b + a; }
-__device__ __forceinline__ D6 operator*(const D6& a, double b) {
-  D6 r; r.v = a.v * b; for (int k = 0; k < 6; ++k) r.d[k] = a.d[k] * b; return r; }
-__device__ __forceinline__ D6 operator*(double a, const D6& b) { return b * a; }
-__device__ __forceinline__ D6 operator/(const D6& a, double b) { return a * (1.0 / b); }
-__device__ __forceinline__ D6 operator/(double a, const D6& b) { return d6(a) / b; }
+template <int K>
+__device__ __forceinline__ Dual<K> operator+(const Dual<K>& a, double b) { Dual<K> r = a; r.v += b; return r; }
+template <int K>
+__device__ __forceinline__ Dual<K> operator+(double a, const Dual<K>& b) { return b + a; }
+template <int K>
+__device__ __forceinline__ Dual<K> operator-(const Dual<K>& a, double b) { Dual<K> r = a; r.v -= b; return r; }
+template <int K>
+__device__ __forceinline__ Dual<K> operator-(double a, const Dual<K>& b) { return -b + a; }
+template <int K>
+__device__ __forceinline__ Dual<K> operator*(const Dual<K>& a, double b) {
+  Dual<K> r; r.v = a.v * b; for (int k = 0; k < K; ++k) r.d[k] = a.d[k] * b; return r; }
+template <int K>
+__device__ __forceinline__ Dual<K> operator*(double a, const Dual<K>& b) { return b * a; }
+template <int K>
+__device__ __forceinline__ Dual<K> operator/(const Dual<K>& a, double b) { return a * (1.0 / b); }
+template <int K>
+__device__ __forceinline__ Dual<K> operator/(double a, const Dual<K>& b) { return dual<K>(a) / b; }
 
 __device__ __forceinline__ double val(double x) { return x; }
-__device__ __forceinline__ double val(const D6& x) { return x.v; }
+template <int K>
+__device__ __forceinline__ double val(const Dual<K>& x) { return x.v; }
 __device__ __forceinline__ double sq_root(double x) { return sqrt(x); }
 __device__ __forceinline__ double absval(double x) { return fabs(x); }
 // d sqrt at 0 is taken as 0 (umbilic points, where the curvatures are not differentiable)
-__device__ __forceinline__ D6 sq_root(const D6& a) {
-  D6 r; r.v = sqrt(a.v);
+template <int K>
+__device__ __forceinline__ Dual<K> sq_root(const Dual<K>& a) {
+  Dual<K> r; r.v = sqrt(a.v);
   const double f = r.v > 0.0 ? 0.5 / r.v : 0.0;
-  for (int k = 0; k < 6; ++k) r.d[k] = a.d[k] * f;
+  for (int k = 0; k < K; ++k) r.d[k] = a.d[k] * f;
   return r; }
-__device__ __forceinline__ D6 absval(const D6& a) { return a.v < 0.0 ? -a : a; }
+template <int K>
+__device__ __forceinline__ Dual<K> absval(const Dual<K>& a) { return a.v < 0.0 ? -a : a; }
 
-template <class T> __device__ __forceinline__ T lift(double x);
-template <> __device__ __forceinline__ double lift<double>(double x) { return x; }
-template <> __device__ __forceinline__ D6 lift<D6>(double x) { return d6(x); }
+template <class T> struct Lift;
+template <> struct Lift<double> { __device__ static double of(double x) { return x; } };
+template <int K> struct Lift<Dual<K>> { __device__ static Dual<K> of(double x) { return dual<K>(x); } };
+template <class T> __device__ __forceinline__ T lift(double x) { return Lift<T>::of(x); }
 
 // |kappa| <- max(|kappa|, floor), sign kept, sign(0) = -1
 template <class T>
@@ -74,18 +94,19 @@ struct FitT {
 
 // p, n: point and (not necessarily unit) normal; a = (a00, a01, a10, a11, a02, a20).
 template <class T>
-__device__ FitT<T> fit_point(const double* p, const double* nin, const T* a, double kfloor) {
+__device__ FitT<T> fit_point(const double* p, const T* nin, const T* a, double kfloor) {
   FitT<T> F;
   const T &a00 = a[0], &a01 = a[1], &a10 = a[2], &a11 = a[3], &a02 = a[4], &a20 = a[5];
-  // unit normal and the fixed frame (s, t, n)
-  double nl = sqrt(nin[0] * nin[0] + nin[1] * nin[1] + nin[2] * nin[2]);
-  const double n[3] = {nin[0] / nl, nin[1] / nl, nin[2] / nl};
-  const double ex = fabs(n[0]) < 0.9 ? 1.0 : 0.0, ey = 1.0 - ex;
-  const double en = ex * n[0] + ey * n[1];
-  double s[3] = {ex - en * n[0], ey - en * n[1], -en * n[2]};
-  const double sl = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
-  for (int i = 0; i < 3; ++i) s[i] /= sl;
-  const double t[3] = {n[1] * s[2] - n[2] * s[1], n[2] * s[0] - n[0] * s[2], n[0] * s[1] - n[1] * s[0]};
+  // unit normal and the tangent frame (s, t, n): s from the axis e = x-hat
+  // unless |n_x| >= 0.9 (then y-hat), with its normal component removed
+  const T nl = sq_root(nin[0] * nin[0] + nin[1] * nin[1] + nin[2] * nin[2]);
+  const T n[3] = {nin[0] / nl, nin[1] / nl, nin[2] / nl};
+  const double ex = fabs(val(n[0])) < 0.9 ? 1.0 : 0.0, ey = 1.0 - ex;
+  const T en = ex * n[0] + ey * n[1];
+  T s[3] = {ex - en * n[0], ey - en * n[1], -(en * n[2])};
+  const T sl = sq_root(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+  for (int i = 0; i < 3; ++i) s[i] = s[i] / sl;
+  const T t[3] = {n[1] * s[2] - n[2] * s[1], n[2] * s[0] - n[0] * s[2], n[0] * s[1] - n[1] * s[0]};
 
   // mean and Gaussian curvature of the height polynomial at (0,0)
   const T E = 1.0 + a10 * a10, G = 1.0 + a01 * a01, Fm = a10 * a01;
@@ -117,7 +138,7 @@ __device__ FitT<T> fit_point(const double* p, const double* nin, const T* a, dou
     const T vl = sq_root(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
     for (int i = 0; i < 3; ++i) v[i] = v[i] / vl;
   } else {  // umbilic: any tangent direction
-    for (int i = 0; i < 3; ++i) v[i] = lift<T>(s[i]);
+    for (int i = 0; i < 3; ++i) v[i] = s[i];
   }
 
   // polynomial normal n*(0,0)

@@ -63,7 +63,8 @@ __global__ __launch_bounds__(kBlock) void k_combine_stats(const Header* __restri
   o[5] = e[2];
 }
 
-template <bool kDirect>
+// kFull = false: only D (the weight sweep of the point backward).
+template <bool kDirect, bool kFull>
 __device__ __forceinline__ void grad_pair(float qx, float qy, float qz, float nl, float C2, float phi,
                                           const float4& P, const float4& U, const float4& Mv, const float4& K,
                                           const float4& G, float* A, float* B, float& D) {
@@ -71,29 +72,33 @@ __device__ __forceinline__ void grad_pair(float qx, float qy, float qz, float nl
   const float d = hw_sqrt(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
   const float w = hw_exp2(fmaf(d, nl, C2));
   const Geo r = kDirect ? geo_direct(qx, qy, qz, U, Mv, K, G) : geo_anchored(qx, qy, qz, P.w, U, Mv, K, G);
-  const float sq = G.z * safe_rcp(r.qn);
-  const float f1 = sq * r.b * safe_rcp(r.rho);
-  const float f2 = sq * r.vu;
-  const float a1 = f1 * r.vm, a2 = f1 * r.vk;
-  const float gx = fmaf(a1, Mv.x, fmaf(a2, K.x, f2 * U.x));
-  const float gy = fmaf(a1, Mv.y, fmaf(a2, K.y, f2 * U.y));
-  const float gz = fmaf(a1, Mv.z, fmaf(a2, K.z, f2 * U.z));
-  A[0] = fmaf(w, gx, A[0]);
-  A[1] = fmaf(w, gy, A[1]);
-  A[2] = fmaf(w, gz, A[2]);
   const float we = w * (r.g - phi);
-  const float c = we * safe_rcp(d);
-  B[0] = fmaf(c, dx, B[0]);
-  B[1] = fmaf(c, dy, B[1]);
-  B[2] = fmaf(c, dz, B[2]);
+  if (kFull) {
+    const float sq = G.z * safe_rcp(r.qn);
+    const float f1 = sq * r.b * safe_rcp(r.rho);
+    const float f2 = sq * r.vu;
+    const float a1 = f1 * r.vm, a2 = f1 * r.vk;
+    const float gx = fmaf(a1, Mv.x, fmaf(a2, K.x, f2 * U.x));
+    const float gy = fmaf(a1, Mv.y, fmaf(a2, K.y, f2 * U.y));
+    const float gz = fmaf(a1, Mv.z, fmaf(a2, K.z, f2 * U.z));
+    A[0] = fmaf(w, gx, A[0]);
+    A[1] = fmaf(w, gy, A[1]);
+    A[2] = fmaf(w, gz, A[2]);
+    const float c = we * safe_rcp(d);
+    B[0] = fmaf(c, dx, B[0]);
+    B[1] = fmaf(c, dy, B[1]);
+    B[2] = fmaf(c, dz, B[2]);
+  }
   D = fmaf(we, d, D);
 }
 
-template <int QPL>
+// kFull: the seven accumulators of grad phi into gpart; otherwise only
+// sum w (g - phi) d into vpart [S][Q].
+template <int QPL, bool kFull>
 __global__ __launch_bounds__(kBlock) void k_grad(const Header* __restrict__ h, const float4* __restrict__ rec,
                                                  const float* __restrict__ x, int64_t Q, int S, int64_t per_split,
                                                  const float* __restrict__ stats, float C2,
-                                                 float4* __restrict__ gpart) {
+                                                 float4* __restrict__ gpart, float* __restrict__ vpart) {
   __shared__ float4 tile[kTile2 * kRecF4];
   const int split = int(blockIdx.x % unsigned(S));
   const int64_t qb = blockIdx.x / unsigned(S);
@@ -134,13 +139,13 @@ __global__ __launch_bounds__(kBlock) void k_grad(const Header* __restrict__ h, c
       const float4 P = tile[j * kRecF4 + 0], U = tile[j * kRecF4 + 1], Mv = tile[j * kRecF4 + 2],
                    K = tile[j * kRecF4 + 3], G = tile[j * kRecF4 + 4];
 #pragma unroll
-      for (int k = 0; k < QPL; ++k) grad_pair<true>(qx[k], qy[k], qz[k], nl[k], C2, ph[k], P, U, Mv, K, G, tA[k], tB[k], tD[k]);
+      for (int k = 0; k < QPL; ++k) grad_pair<true, kFull>(qx[k], qy[k], qz[k], nl[k], C2, ph[k], P, U, Mv, K, G, tA[k], tB[k], tD[k]);
     }
     for (int j = jd; j < cnt; ++j) {
       const float4 P = tile[j * kRecF4 + 0], U = tile[j * kRecF4 + 1], Mv = tile[j * kRecF4 + 2],
                    K = tile[j * kRecF4 + 3], G = tile[j * kRecF4 + 4];
 #pragma unroll
-      for (int k = 0; k < QPL; ++k) grad_pair<false>(qx[k], qy[k], qz[k], nl[k], C2, ph[k], P, U, Mv, K, G, tA[k], tB[k], tD[k]);
+      for (int k = 0; k < QPL; ++k) grad_pair<false, kFull>(qx[k], qy[k], qz[k], nl[k], C2, ph[k], P, U, Mv, K, G, tA[k], tB[k], tD[k]);
     }
 #pragma unroll
     for (int k = 0; k < QPL; ++k) {
@@ -152,9 +157,13 @@ __global__ __launch_bounds__(kBlock) void k_grad(const Header* __restrict__ h, c
   for (int k = 0; k < QPL; ++k) {
     const int64_t q = qb * (kBlock * QPL) + k * kBlock + threadIdx.x;
     if (q < Q) {
-      float4* o = gpart + 2 * (int64_t(split) * Q + q);
-      o[0] = make_float4(A[k][0], A[k][1], A[k][2], D[k]);
-      o[1] = make_float4(B[k][0], B[k][1], B[k][2], 0.f);
+      if (kFull) {
+        float4* o = gpart + 2 * (int64_t(split) * Q + q);
+        o[0] = make_float4(A[k][0], A[k][1], A[k][2], D[k]);
+        o[1] = make_float4(B[k][0], B[k][1], B[k][2], 0.f);
+      } else {
+        vpart[int64_t(split) * Q + q] = D[k];
+      }
     }
   }
 }
@@ -180,11 +189,11 @@ __global__ __launch_bounds__(kBlock) void k_grad_combine(const float4* __restric
   for (int c = 0; c < 3; ++c) gx[3 * q + c] = s * (iw * (A[c] - lam * B[c] + cm * st[3 + c]));
 }
 
-template <int QPL>
+template <int QPL, bool kFull>
 void launch_grad_sweep(const Header* h, const float4* rec, const float* x, int64_t Q, const Plan& plan,
-                       const float* stats, float C2, float4* gpart, hipStream_t st) {
-  hipLaunchKernelGGL(k_grad<QPL>, dim3(unsigned(plan.nqb * plan.S)), dim3(kBlock), 0, st, h, rec, x, Q, plan.S,
-                     plan.per_split, stats, C2, gpart);
+                       const float* stats, float C2, float4* gpart, float* vpart, hipStream_t st) {
+  hipLaunchKernelGGL((k_grad<QPL, kFull>), dim3(unsigned(plan.nqb * plan.S)), dim3(kBlock), 0, st, h, rec, x, Q,
+                     plan.S, plan.per_split, stats, C2, gpart, vpart);
 }
 
 }  // namespace
@@ -214,12 +223,28 @@ int launch_grad(const void* rec, int64_t N, const float* x, int64_t Q, const flo
   const int qpl = plan.qpl > 2 ? 2 : plan.qpl;
   const Plan p = with_qpl(plan, qpl, Q);
   switch (qpl) {
-    case 1: launch_grad_sweep<1>(h, recs, x, Q, p, stats, C2, ws.gpart, st); break;
-    default: launch_grad_sweep<2>(h, recs, x, Q, p, stats, C2, ws.gpart, st); break;
+    case 1: launch_grad_sweep<1, true>(h, recs, x, Q, p, stats, C2, ws.gpart, nullptr, st); break;
+    default: launch_grad_sweep<2, true>(h, recs, x, Q, p, stats, C2, ws.gpart, nullptr, st); break;
   }
   hipLaunchKernelGGL(k_grad_combine, dim3(unsigned((Q + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, ws.gpart,
                      stats, plan.S, Q, C, gout, gx);
   return check_hip(hipGetLastError(), "gradient kernels");
+}
+
+int launch_vsum(const void* rec, int64_t N, const float* x, int64_t Q, const float* stats, float C,
+                const Plan& plan, float* vpart, hipStream_t st) {
+  const Layout L(N);
+  const char* base = static_cast<const char*>(rec);
+  const Header* h = reinterpret_cast<const Header*>(base);
+  const float4* recs = reinterpret_cast<const float4*>(base + L.rec);
+  const float C2 = C * kLog2e;
+  const int qpl = plan.qpl > 2 ? 2 : plan.qpl;
+  const Plan p = with_qpl(plan, qpl, Q);
+  switch (qpl) {
+    case 1: launch_grad_sweep<1, false>(h, recs, x, Q, p, stats, C2, nullptr, vpart, st); break;
+    default: launch_grad_sweep<2, false>(h, recs, x, Q, p, stats, C2, nullptr, vpart, st); break;
+  }
+  return check_hip(hipGetLastError(), "weight sweep kernel");
 }
 
 }  // namespace pts

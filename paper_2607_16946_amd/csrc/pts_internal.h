@@ -148,6 +148,11 @@ int launch_combine_stats(const void* rec, int64_t N, const float* x, int64_t Q, 
 int launch_grad(const void* rec, int64_t N, const float* x, int64_t Q, const float* stats, const float* gout,
                 float* gx, float C, const Plan& plan, const WsView& ws, hipStream_t st);
 
+// Laplacian, gradient and eikonal residual from one query-major sweep (pts_lap.hip).
+size_t lap_ws_bytes(const Plan& plan, int64_t Q);
+int launch_lap(const void* rec, int64_t N, const float* x, int64_t Q, const float* stats, float* lap, float* grad,
+               float* eik, float C, const Plan& plan, void* ws, hipStream_t st);
+
 // Parameter backward: point blocks x query ranges.
 struct BackPlan {
   int Sq;          // query ranges
@@ -155,9 +160,27 @@ struct BackPlan {
   int64_t pbs;     // point blocks of kBlock points
 };
 BackPlan make_back_plan(int64_t N, int64_t Q);
-size_t back_ws_bytes(int64_t N, int64_t Q);
+size_t back_ws_bytes(int64_t N, int64_t Q);  // dL/da and dL/dn only
+// Workspace of the backward with dL/dp: per-range point partials (12 floats),
+// M^2 and farthest slot per query, weight-sweep partials [S][Q] and the query
+// records [Q][3] float4.  With ws = nullptr only `bytes` is meaningful.
+struct BackPointsWs {
+  float* gpp;
+  float* far2;
+  int32_t* farix;
+  float* vpart;
+  float4* qrec;
+  size_t bytes;
+};
+BackPointsWs back_points_ws(int64_t N, int64_t Q, const Plan& plan, void* ws);
+// sum_j w_j (g_j - phi) d_j per query and point split into vpart [S][Q].
+int launch_vsum(const void* rec, int64_t N, const float* x, int64_t Q, const float* stats, float C,
+                const Plan& plan, float* vpart, hipStream_t st);
+// ga [N,6], gp [N,3], gn [N,3]: each may be null.  With gp, ws is a
+// BackPointsWs of the plan; otherwise back_ws_bytes.
 int launch_backward(const void* rec, int64_t N, const float* p, const float* n, const float* a, const float* x,
-                    int64_t Q, const float* gout, const float* stats, float* ga, float C, void* ws, hipStream_t st);
+                    int64_t Q, const float* gout, const float* stats, float* ga, float* gp, float* gn, float C,
+                    const Plan& plan, void* ws, hipStream_t st);
 
 // Sphere tracing (point splits fixed by N so that rays do not affect each other).
 int march_splits(int64_t N);

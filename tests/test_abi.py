@@ -57,6 +57,14 @@ def test_host_side_errors(L):
     bad = binding.make_params(splits=3)
     assert L.pts_eval_ws_bytes(10, 10, ctypes.byref(bad), ctypes.byref(out)) == binding.PTS_EINVAL
     assert L.pts_cloud_build(None, None, None, 10, None, None, 0, None) == binding.PTS_EINVAL
+    # the point backward needs at least one output, and its workspace covers every combination
+    assert L.pts_backward_points(None, 10, None, None, None, None, 5, None, None, None, None, None,
+                                 ctypes.byref(prm), None, 0, None) == binding.PTS_EINVAL
+    assert b"no output" in L.pts_last_error()
+    wa, wp = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert L.pts_backward_ws_bytes(5000, 3000, ctypes.byref(prm), ctypes.byref(wa)) == binding.PTS_OK
+    assert L.pts_backward_points_ws_bytes(5000, 3000, ctypes.byref(prm), ctypes.byref(wp)) == binding.PTS_OK
+    assert wp.value >= wa.value * 12 // 8 + 3000 * (4 + 4 + 48)
 
 
 def test_probe_library_exports():
