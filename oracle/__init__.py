@@ -15,7 +15,10 @@ Laplacian 2/|x|), single torus vs. brute-force surface distance, torus round
 trip, principal curvatures vs. a generic shape-operator computation,
 orientation/scale/translation/permutation invariances, the large-C
 nearest-point limit, finite differences for every gradient and the Laplacian,
-and brute-force nearest neighbours for the radius-limited evaluation.
+brute-force nearest neighbours for the radius-limited evaluation, and for the
+two baselines the planar closed form, the screened Laplace equation the
+double-layer sum satisfies, area-weight and orientation identities and the
+nearest-point limit.
 """
 
 from __future__ import annotations
@@ -75,6 +78,9 @@ def lib():
         L.orc_trace.argtypes = [i64, P, P, i64, P, P, ctypes.c_int, ctypes.c_double,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_int, P, P, P, P]
         L.orc_trace.restype = ctypes.c_int
+        L.orc_eval_baseline.argtypes = [i64, P, P, P, i64, P, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                        ctypes.c_int, P, P]
+        L.orc_eval_baseline.restype = ctypes.c_int
         L.orc_laplacian.argtypes = [i64, P, P, i64, P, ctypes.c_double, ctypes.c_int, P]
         L.orc_laplacian.restype = ctypes.c_int
         L.orc_grad_points.argtypes = [i64, P, P, P, ctypes.c_double, ctypes.c_int, i64, P, ctypes.c_double, P,
@@ -217,6 +223,28 @@ def grad_a(p, n, a, x, gout, C: float = C_DEFAULT, kfloor: float | None = None,
     if rc != 0:
         raise ValueError("oracle grad_a: empty cloud")
     return ga
+
+
+BASELINE_KINDS = {"sspd": 0, "shc": 1}
+
+
+def eval_baseline(p, n, x, kind: str, area=None, C: float = C_DEFAULT, lam_fixed: float = 0.0,
+                  raw: bool = False, nthreads: int = 0):
+    """Smoothed signed planar distance ('sspd', Eq. SmoothedSignedPlanarDistance) or signed Hopf-Cole
+    distance ('shc', Eq. ScreenedWindingNumber) at x [Q,3]; with raw, also the weighted sum itself."""
+    p = _f64(p, 3)
+    n = _f64(n, 3)
+    x = _f64(x, 3)
+    A = None if area is None else np.ascontiguousarray(np.asarray(area, dtype=np.float64).reshape(-1))
+    if A is not None and A.shape[0] != p.shape[0]:
+        raise ValueError("area must have one value per point")
+    out = np.zeros(x.shape[0])
+    r = np.zeros(x.shape[0]) if raw else None
+    rc = lib().orc_eval_baseline(p.shape[0], _ptr(p), _ptr(n), _ptr(A), x.shape[0], _ptr(x), float(C),
+                                 BASELINE_KINDS[kind], float(lam_fixed), int(nthreads), _ptr(out), _ptr(r))
+    if rc != 0:
+        raise ValueError("oracle baseline: empty cloud or unknown kind")
+    return (out, r) if raw else out
 
 
 def laplacian(p, tori: Tori, x, C: float = C_DEFAULT, nthreads: int = 0) -> np.ndarray:

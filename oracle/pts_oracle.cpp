@@ -51,6 +51,18 @@
 //             shift sigma = their smallest distance (phi does not depend on
 //             sigma; this keeps the largest weight at 1).
 
+// Baselines of the accuracy comparison (Sec. 5.2, "Signed distance
+// accuracy"): smoothed signed planar distance, Eq. (SmoothedSignedPlanarDistance),
+// and signed Hopf-Cole distance, Eq. (ScreenedWindingNumber):
+//   R-base-lambda  both use the per-query sigma_x = M/2 and lambda_x = C/sigma_x
+//             of Eq. (RelationshipBetweenLambdaAndRadius), as the blend does
+//             (the equations write sigma_x; lambda is the same heuristic).
+//   R-base-A  area weights A_i are an input; absent, A_i = 1 (the library
+//             Voronoi areas the paper uses are not part of this build).
+//   R-base-n  <x - p_i, n_i> uses the normal scaled to unit length.
+//   R-shc-zero    a double-layer sum of exactly 0 gives +inf (sign(0) = +1).
+//   R-shc-onpoint a query on a point (d_i = 0) gives NaN.
+
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -552,6 +564,61 @@ int orc_trace(int64_t N, const double* p, const double* tor, int64_t Rn, const d
       Dual<3> f = blend_at(N, p, tt, xd, C, nullptr, nullptr);
       double gl = std::sqrt(f.d[0] * f.d[0] + f.d[1] * f.d[1] + f.d[2] * f.d[2]);
       if (gl > 0.0) for (int j = 0; j < 3; ++j) normal_out[3 * r + j] = f.d[j] / gl;
+    }
+  }
+  return 0;
+}
+
+// Smoothed signed planar distance (kind 0), Eq. (SmoothedSignedPlanarDistance),
+// and signed Hopf-Cole distance (kind 1), Eq. (ScreenedWindingNumber), at Q
+// queries.  area [N] may be null (A_i = 1).  lam_fixed > 0 replaces lambda_x
+// by that constant with sigma = 0 (for the pins only).  raw [Q] (may be null)
+// receives the weighted sum itself: the double-layer sum w(x) for kind 1,
+// the numerator for kind 0.
+int orc_eval_baseline(int64_t N, const double* p, const double* n, const double* area, int64_t Q,
+                      const double* x, double C, int kind, double lam_fixed, int nthreads, double* out,
+                      double* raw) {
+  if (N <= 0 || (kind != 0 && kind != 1)) return 1;
+  set_threads(nthreads);
+  std::vector<double> nh(3 * (size_t)N);
+  for (int64_t i = 0; i < N; ++i) {
+    const double l = std::sqrt(n[3 * i] * n[3 * i] + n[3 * i + 1] * n[3 * i + 1] + n[3 * i + 2] * n[3 * i + 2]);
+    for (int k = 0; k < 3; ++k) nh[3 * i + k] = l > 0.0 ? n[3 * i + k] / l : 0.0;
+  }
+  const double two_pi = 2.0 * 3.14159265358979323846;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t q = 0; q < Q; ++q) {
+    const double* xq = x + 3 * q;
+    double sigma = 0.0, lam = lam_fixed;
+    if (lam_fixed <= 0.0) {
+      double M = 0.0;
+      for (int64_t i = 0; i < N; ++i) {
+        const double dv[3] = {xq[0] - p[3 * i], xq[1] - p[3 * i + 1], xq[2] - p[3 * i + 2]};
+        M = std::max(M, norm3(dv));
+      }
+      sigma = 0.5 * M;
+      lam = M > 0.0 ? C / sigma : 0.0;
+    }
+    double num = 0.0, den = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+      const double dv[3] = {xq[0] - p[3 * i], xq[1] - p[3 * i + 1], xq[2] - p[3 * i + 2]};
+      const double d = norm3(dv);
+      const double A = area ? area[i] : 1.0;
+      const double w = A * std::exp(-lam * (d - sigma));
+      const double planar = dot3(dv, &nh[3 * i]);
+      if (kind == 0) {
+        num += w * planar;
+        den += w;
+      } else {
+        num += (d > 0.0) ? w * (lam * d + 1.0) * planar / (two_pi * d * d * d) : std::nan("");
+      }
+    }
+    if (raw) raw[q] = num;
+    if (kind == 0) {
+      out[q] = num / den;
+    } else {
+      const double sg = num < 0.0 ? -1.0 : 1.0;
+      out[q] = sg * (-std::log(std::fabs(num)) / lam + sigma);
     }
   }
   return 0;

@@ -512,6 +512,118 @@ def test_laplacian_matches_second_differences():
 
 
 # ---------------------------------------------------------------------------
+# Baselines: smoothed signed planar distance and signed Hopf-Cole distance
+# ---------------------------------------------------------------------------
+
+def _plane_cloud(N, seed):
+    rng = np.random.default_rng(seed)
+    p = np.zeros((N, 3))
+    p[:, :2] = rng.uniform(-1, 1, size=(N, 2))
+    n = np.zeros((N, 3))
+    n[:, 2] = rng.uniform(0.5, 2.0, size=N)      # not unit: the planar distance uses n / |n|
+    return p, n
+
+
+def test_sspd_plane_closed_form():
+    # every point's planar distance is x_z, and the weights sum to one
+    p, n = _plane_cloud(300, 40)
+    x = np.random.default_rng(41).uniform(-1.5, 1.5, size=(200, 3))
+    assert np.allclose(oracle.eval_baseline(p, n, x, "sspd"), x[:, 2], rtol=1e-12, atol=1e-12)
+    assert np.allclose(oracle.eval_baseline(p, -n, x, "sspd"), -x[:, 2], rtol=1e-12, atol=1e-12)
+
+
+def test_sspd_area_weights_and_single_point():
+    p, n, _ = _mixed_cloud(N=200)
+    x = np.random.default_rng(42).uniform(-1, 1, size=(50, 3))
+    phi = oracle.eval_baseline(p, n, x, "sspd")
+    # a common factor on the areas cancels
+    assert np.allclose(oracle.eval_baseline(p, n, x, "sspd", area=np.full(200, 7.5)), phi, rtol=1e-12, atol=1e-14)
+    # all weight on one point gives that point's planar distance
+    A = np.zeros(200)
+    A[17] = 1.0
+    nh = n[17] / np.linalg.norm(n[17])
+    assert np.allclose(oracle.eval_baseline(p, n, x, "sspd", area=A), (x - p[17]) @ nh, rtol=1e-12, atol=1e-12)
+
+
+def test_shc_satisfies_screened_laplace():
+    # with lambda fixed, the double-layer sum is a sum of screened (Yukawa)
+    # dipoles, so Lap w = lambda^2 w away from the points (Eq. ScreenedLaplace)
+    rng = np.random.default_rng(43)
+    p = rng.uniform(-0.5, 0.5, size=(40, 3))
+    n = rng.normal(size=(40, 3))
+    lam = 3.0
+    x = rng.uniform(-2, 2, size=(400, 3))
+    x = x[np.linalg.norm(x[:, None, :] - p[None], axis=2).min(axis=1) > 0.5][:30]
+    _, w0 = oracle.eval_baseline(p, n, x, "shc", lam_fixed=lam, raw=True)
+
+    def second_diff(h):
+        out = np.zeros(len(x))
+        for k in range(3):
+            e = np.zeros(3)
+            e[k] = h
+            _, wp = oracle.eval_baseline(p, n, x + e, "shc", lam_fixed=lam, raw=True)
+            _, wm = oracle.eval_baseline(p, n, x - e, "shc", lam_fixed=lam, raw=True)
+            out += (wp - 2 * w0 + wm) / (h * h)
+        return out
+
+    lap = (4 * second_diff(1e-4) - second_diff(2e-4)) / 3
+    scale = np.abs(lam * lam * w0).max()
+    assert np.abs(lap - lam * lam * w0).max() <= 1e-7 * scale
+    # phi is -(1/lambda) log|w| with the sign of w (sigma = 0 at fixed lambda)
+    phi = oracle.eval_baseline(p, n, x, "shc", lam_fixed=lam)
+    assert np.allclose(phi, np.sign(w0) * (-np.log(np.abs(w0)) / lam), rtol=1e-12, atol=1e-12)
+
+
+def test_shc_orientation_areas_and_sign():
+    p, n, _ = _mixed_cloud(N=200)
+    x = np.random.default_rng(44).uniform(-1, 1, size=(60, 3))
+    phi, w = oracle.eval_baseline(p, n, x, "shc", raw=True)
+    assert np.allclose(oracle.eval_baseline(p, -n, x, "shc"), -phi, rtol=1e-12, atol=1e-12)
+    # scaling every area by k multiplies w by k: phi moves by -sign(w) log(k) / lambda_x
+    M = np.linalg.norm(x[:, None, :] - p[None], axis=2).max(axis=1)
+    lam = 2 * 64.0 / M
+    k = 3.0
+    assert np.allclose(oracle.eval_baseline(p, n, x, "shc", area=np.full(200, k)),
+                       phi - np.sign(w) * np.log(k) / lam, rtol=1e-12, atol=1e-12)
+    # one point: outside along its normal the distance is positive, inside negative
+    q = np.array([[0.0, 0.0, 0.3], [0.0, 0.0, -0.3]])
+    one = oracle.eval_baseline([[0.0, 0.0, 0.0]], [[0.0, 0.0, 2.0]], q, "shc")
+    assert one[0] > 0 and one[1] < 0
+
+
+def test_baselines_nearest_point_limit():
+    # as C grows the weights concentrate on the nearest point: SSPD tends to its
+    # planar distance and |SHC| to the distance itself, with error O(1/C)
+    p, n, _ = _mixed_cloud(N=150)
+    rng = np.random.default_rng(45)
+    x = rng.uniform(-1, 1, size=(40, 3))
+    d = np.linalg.norm(x[:, None, :] - p[None], axis=2)
+    srt = np.sort(d, axis=1)
+    x = x[srt[:, 1] - srt[:, 0] > 0.05 * srt[:, -1]]
+    d = np.linalg.norm(x[:, None, :] - p[None], axis=2)
+    nn = np.argmin(d, axis=1)
+    nh = n[nn] / np.linalg.norm(n[nn], axis=1, keepdims=True)
+    planar = np.sum((x - p[nn]) * nh, axis=1)
+    errs_s, errs_h = [], []
+    for C in (50.0, 200.0, 600.0):
+        errs_s.append(np.abs(oracle.eval_baseline(p, n, x, "sspd", C=C) - planar).max())
+        errs_h.append(np.abs(np.abs(oracle.eval_baseline(p, n, x, "shc", C=C)) - d.min(axis=1)).max())
+    assert errs_s[2] < 1e-6 and errs_s[0] > errs_s[1] > errs_s[2]
+    assert errs_h[2] < errs_h[0] / 4 and errs_h[2] < 0.02
+
+
+def test_baselines_rigid_invariance():
+    p, n, _ = _mixed_cloud(N=120)
+    x = np.random.default_rng(46).uniform(-1, 1, size=(40, 3))
+    R = _rot(47)
+    t = np.array([0.3, -1.2, 2.0])
+    for kind in ("sspd", "shc"):
+        a = oracle.eval_baseline(p, n, x, kind)
+        b = oracle.eval_baseline(p @ R.T + t, n @ R.T, x @ R.T + t, kind)
+        assert np.allclose(a, b, rtol=1e-9, atol=1e-10), kind
+
+
+# ---------------------------------------------------------------------------
 # Sphere tracing on the exact sphere
 # ---------------------------------------------------------------------------
 
