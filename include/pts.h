@@ -214,6 +214,33 @@ int pts_laplacian(const void* rec, int64_t N, const float* x, int64_t Q, const f
                   float* grad, float* eik, const pts_params* prm, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Baselines of the accuracy comparison (Sec. 5.2, "Signed distance accuracy"),
+ * evaluated over the same record and skeleton as pts_eval.
+ * ------------------------------------------------------------------------- */
+
+#define PTS_BASELINE_SSPD 0 /* smoothed signed planar distance, Eq. (SmoothedSignedPlanarDistance) */
+#define PTS_BASELINE_SHC 1  /* signed Hopf-Cole distance, Eq. (ScreenedWindingNumber) */
+
+/* Per-point area weights A_i of both baselines, area [N] device float32 in the
+ * caller's point order (NULL restores A_i = 1, the value pts_cloud_build sets).
+ * The torus blend does not use them. */
+int pts_set_areas(void* rec, int64_t N, const float* area, void* stream);
+
+/* A baseline at Q queries, with the per-query sigma_x = M/2 and
+ * lambda_x = 2C/M of Eq. (RelationshipBetweenLambdaAndRadius) and unit normals
+ * (the input normals scaled to length 1), w_i = A_i exp(-lambda_x (d_i - sigma_x)):
+ *   PTS_BASELINE_SSPD  phi = sum w_i <x - p_i, n_i> / sum w_i;
+ *   PTS_BASELINE_SHC   s = sum w_i (lambda_x d_i + 1) <x - p_i, n_i> / (2 pi d_i^3),
+ *                      phi = sign(s) (-log|s| / lambda_x + sigma_x), sign(0) = +1.
+ * sdf [Q] device float32 output.  ws_bytes >= pts_eval_ws_bytes(N, Q, prm)
+ * (the same workspace as pts_eval).  A NaN query gives NaN; for SHC a query
+ * at distance 0 from a point (in the record's FP32 coordinates) gives NaN and
+ * one within ~1e-5 (relative to the cloud's size) of a point may overflow FP32
+ * to an infinite distance.  An unknown kind is PTS_EINVAL.  Deterministic. */
+int pts_eval_baseline(const void* rec, int64_t N, const float* x, int64_t Q, int kind, float* sdf,
+                      const pts_params* prm, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Backward with respect to the per-point coefficients (the representation is
  * differentiable, Sec. 6): ga[i] = dL/da_i for L = sum_q gout[q] phi(x_q).
  * ------------------------------------------------------------------------- */

@@ -79,7 +79,7 @@ def lib():
                                 ctypes.c_double, ctypes.c_double, ctypes.c_int, P, P, P, P]
         L.orc_trace.restype = ctypes.c_int
         L.orc_eval_baseline.argtypes = [i64, P, P, P, i64, P, ctypes.c_double, ctypes.c_int, ctypes.c_double,
-                                        ctypes.c_int, P, P]
+                                        ctypes.c_int, P, P, P]
         L.orc_eval_baseline.restype = ctypes.c_int
         L.orc_laplacian.argtypes = [i64, P, P, i64, P, ctypes.c_double, ctypes.c_int, P]
         L.orc_laplacian.restype = ctypes.c_int
@@ -231,7 +231,8 @@ BASELINE_KINDS = {"sspd": 0, "shc": 1}
 def eval_baseline(p, n, x, kind: str, area=None, C: float = C_DEFAULT, lam_fixed: float = 0.0,
                   raw: bool = False, nthreads: int = 0):
     """Smoothed signed planar distance ('sspd', Eq. SmoothedSignedPlanarDistance) or signed Hopf-Cole
-    distance ('shc', Eq. ScreenedWindingNumber) at x [Q,3]; with raw, also the weighted sum itself."""
+    distance ('shc', Eq. ScreenedWindingNumber) at x [Q,3]; with raw, also the weighted sum itself and
+    the sum of the absolute values of its terms: (phi, sum, abs_sum)."""
     p = _f64(p, 3)
     n = _f64(n, 3)
     x = _f64(x, 3)
@@ -240,11 +241,13 @@ def eval_baseline(p, n, x, kind: str, area=None, C: float = C_DEFAULT, lam_fixed
         raise ValueError("area must have one value per point")
     out = np.zeros(x.shape[0])
     r = np.zeros(x.shape[0]) if raw else None
+    ra = np.zeros(x.shape[0]) if raw else None
     rc = lib().orc_eval_baseline(p.shape[0], _ptr(p), _ptr(n), _ptr(A), x.shape[0], _ptr(x), float(C),
-                                 BASELINE_KINDS[kind], float(lam_fixed), int(nthreads), _ptr(out), _ptr(r))
+                                 BASELINE_KINDS[kind], float(lam_fixed), int(nthreads), _ptr(out), _ptr(r),
+                                 _ptr(ra))
     if rc != 0:
         raise ValueError("oracle baseline: empty cloud or unknown kind")
-    return (out, r) if raw else out
+    return (out, r, ra) if raw else out
 
 
 def laplacian(p, tori: Tori, x, C: float = C_DEFAULT, nthreads: int = 0) -> np.ndarray:

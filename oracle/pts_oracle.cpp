@@ -574,10 +574,11 @@ int orc_trace(int64_t N, const double* p, const double* tor, int64_t Rn, const d
 // queries.  area [N] may be null (A_i = 1).  lam_fixed > 0 replaces lambda_x
 // by that constant with sigma = 0 (for the pins only).  raw [Q] (may be null)
 // receives the weighted sum itself: the double-layer sum w(x) for kind 1,
-// the numerator for kind 0.
+// the numerator for kind 0; raw_abs [Q] (may be null) the sum of the absolute
+// values of its terms (the scale of its rounding error in lower precision).
 int orc_eval_baseline(int64_t N, const double* p, const double* n, const double* area, int64_t Q,
                       const double* x, double C, int kind, double lam_fixed, int nthreads, double* out,
-                      double* raw) {
+                      double* raw, double* raw_abs) {
   if (N <= 0 || (kind != 0 && kind != 1)) return 1;
   set_threads(nthreads);
   std::vector<double> nh(3 * (size_t)N);
@@ -599,21 +600,25 @@ int orc_eval_baseline(int64_t N, const double* p, const double* n, const double*
       sigma = 0.5 * M;
       lam = M > 0.0 ? C / sigma : 0.0;
     }
-    double num = 0.0, den = 0.0;
+    double num = 0.0, den = 0.0, nabs = 0.0;
     for (int64_t i = 0; i < N; ++i) {
       const double dv[3] = {xq[0] - p[3 * i], xq[1] - p[3 * i + 1], xq[2] - p[3 * i + 2]};
       const double d = norm3(dv);
       const double A = area ? area[i] : 1.0;
       const double w = A * std::exp(-lam * (d - sigma));
       const double planar = dot3(dv, &nh[3 * i]);
+      double term;
       if (kind == 0) {
-        num += w * planar;
+        term = w * planar;
         den += w;
       } else {
-        num += (d > 0.0) ? w * (lam * d + 1.0) * planar / (two_pi * d * d * d) : std::nan("");
+        term = (d > 0.0) ? w * (lam * d + 1.0) * planar / (two_pi * d * d * d) : std::nan("");
       }
+      num += term;
+      nabs += std::fabs(term);
     }
     if (raw) raw[q] = num;
+    if (raw_abs) raw_abs[q] = nabs;
     if (kind == 0) {
       out[q] = num / den;
     } else {

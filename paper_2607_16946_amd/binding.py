@@ -96,6 +96,9 @@ SIGNATURES = {
     "pts_eval_far": (ctypes.c_int, [_P, _I64, _P, _I64, ctypes.POINTER(Params), _P, _SZ, _P]),
     "pts_eval_blend": (ctypes.c_int, [_P, _I64, _P, _I64, ctypes.POINTER(Params), _P, _SZ, _P]),
     "pts_eval_combine": (ctypes.c_int, [_I64, _I64, _P, ctypes.POINTER(Params), _P, _SZ, _P]),
+    "pts_set_areas": (ctypes.c_int, [_P, _I64, _P, _P]),
+    "pts_eval_baseline": (ctypes.c_int, [_P, _I64, _P, _I64, ctypes.c_int, _P, ctypes.POINTER(Params), _P, _SZ,
+                                         _P]),
     "pts_grad_ws_bytes": (ctypes.c_int, [_I64, _I64, ctypes.POINTER(Params), ctypes.POINTER(_SZ)]),
     "pts_grad_x": (ctypes.c_int, [_P, _I64, _P, _I64, _P, _P, _P, ctypes.POINTER(Params), _P, _SZ, _P]),
     "pts_laplacian_ws_bytes": (ctypes.c_int, [_I64, _I64, ctypes.POINTER(Params), ctypes.POINTER(_SZ)]),
@@ -258,6 +261,35 @@ def eval(rec: torch.Tensor, N: int, x: torch.Tensor, params: Params | None = Non
     if stats:
         res.append(st)
     return res[0] if len(res) == 1 else tuple(res)
+
+
+BASELINES = {"sspd": 0, "shc": 1}
+
+
+def set_areas(rec: torch.Tensor, N: int, area: torch.Tensor | None = None) -> None:
+    """Area weights A_i [N] of the baselines (caller's point order); None restores 1."""
+    if area is not None:
+        _dev(area, "area")
+        if area.numel() != N:
+            raise ValueError("area must have one value per point")
+    _check(lib().pts_set_areas(_ptr(rec), int(N), _ptr(area), _stream()))
+
+
+def eval_baseline(rec: torch.Tensor, N: int, x: torch.Tensor, kind: str, params: Params | None = None,
+                  ws: torch.Tensor | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Smoothed signed planar distance ('sspd') or signed Hopf-Cole distance ('shc') at x [Q,3]."""
+    _dev(x, "x", 3)
+    Q = x.shape[0]
+    prm = params if params is not None else make_params()
+    sdf = out if out is not None else torch.empty(Q, dtype=torch.float32, device=x.device)
+    if Q == 0:
+        return sdf
+    need = eval_ws_bytes(N, Q, prm)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device=x.device)
+    _check(lib().pts_eval_baseline(_ptr(rec), int(N), _ptr(x), Q, BASELINES[kind], _ptr(sdf), ctypes.byref(prm),
+                                   _ptr(ws), ws.numel(), _stream()))
+    return sdf
 
 
 def grad_x(rec: torch.Tensor, N: int, x: torch.Tensor, stats: torch.Tensor, gout: torch.Tensor | None = None,

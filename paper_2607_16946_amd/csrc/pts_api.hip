@@ -269,6 +269,24 @@ int pts_eval_combine(int64_t N, int64_t Q, float* sdf, const pts_params* prm, vo
   return launch_combine(Q, plan, ws_view(plan, Q, ws), sdf, static_cast<hipStream_t>(stream));
 }
 
+int pts_set_areas(void* rec, int64_t N, const float* area, void* stream) {
+  if (N < 1) return fail(PTS_EINVAL, "N must be >= 1");
+  if (!rec) return fail(PTS_EINVAL, "null record");
+  return launch_set_areas(rec, N, area, static_cast<hipStream_t>(stream));
+}
+
+int pts_eval_baseline(const void* rec, int64_t N, const float* x, int64_t Q, int kind, float* sdf,
+                      const pts_params* prm, void* ws, size_t ws_bytes, void* stream) {
+  if (kind != PTS_BASELINE_SSPD && kind != PTS_BASELINE_SHC) return fail(PTS_EINVAL, "unknown baseline kind");
+  Plan plan;
+  pts_params P;
+  if (int rc = eval_checks(N, Q, prm, ws_bytes, false, &plan, &P)) return rc;
+  if (Q == 0) return PTS_OK;
+  if (!rec || !x || !sdf || !ws) return fail(PTS_EINVAL, "null pointer");
+  return launch_baseline(rec, N, x, Q, kind, P.C, plan, ws_view(plan, Q, ws), sdf,
+                         static_cast<hipStream_t>(stream));
+}
+
 int pts_grad_x(const void* rec, int64_t N, const float* x, int64_t Q, const float* gout, const float* stats,
                float* gx, const pts_params* prm, void* ws, size_t ws_bytes, void* stream) {
   Plan plan;

@@ -10,7 +10,8 @@
 //   k_scan     exclusive scan of the per-block counts (one workgroup)
 //   k_rhist / k_exscan / k_rscatter
 //              stable LSD radix sort of (key, input index), 4 bits per pass
-//   k_fit      per slot: FP64 torus fit of its point, FP32 record
+//   k_fit      per slot: FP64 torus fit of its point, FP32 record, and the
+//              baseline record (p, 1), (unit normal, -<p, unit normal>)
 //   k_units    bounding sphere and extreme point of every kUnit slots
 //
 // Slots: points whose torus radius L = 1/|kappa_min| is at most 4 D (D = bbox
@@ -279,7 +280,7 @@ __global__ __launch_bounds__(kBlock) void k_fit(const float* __restrict__ p, con
                                                 const float* __restrict__ a, int64_t N, float kfloor_rel,
                                                 const Header* __restrict__ h, const int32_t* __restrict__ order,
                                                 float4* __restrict__ pos4, float4* __restrict__ rec,
-                                                int32_t* __restrict__ perm) {
+                                                int32_t* __restrict__ perm, float4* __restrict__ bas) {
   const BoxInfo b = box_info(h, kfloor_rel);
   const int64_t slot = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (slot >= N) return;
@@ -310,6 +311,12 @@ __global__ __launch_bounds__(kBlock) void k_fit(const float* __restrict__ p, con
   R[3] = make_float4(float(F.k[0]), float(F.k[1]), float(F.k[2]), float(-dot(orel, F.k)));
   R[4] = make_float4(float(F.R), float(F.zeta * F.r), float(F.sgn), float(-F.sgn * F.r));
   perm[slot] = int32_t(i);
+  const double nl = sqrt(nd[0] * nd[0] + nd[1] * nd[1] + nd[2] * nd[2]);
+  double nh[3] = {0.0, 0.0, 0.0};
+  if (nl > 0.0)
+    for (int k = 0; k < 3; ++k) nh[k] = nd[k] / nl;
+  bas[2 * slot] = make_float4(px, py, pz, 1.f);
+  bas[2 * slot + 1] = make_float4(float(nh[0]), float(nh[1]), float(nh[2]), float(-dot(pr, nh)));
 }
 
 // Bounds of each unit of kUnit consecutive slots (one wave per unit): center
@@ -409,7 +416,8 @@ int launch_build(const float* p, const float* n, const float* a, int64_t N, floa
   }
   float4* pos4 = reinterpret_cast<float4*>(base + L.pos);
   hipLaunchKernelGGL(k_fit, dim3(nb), dim3(kBlock), 0, st, p, n, a, N, kfloor_rel, h, idx[cur], pos4,
-                     reinterpret_cast<float4*>(base + L.rec), reinterpret_cast<int32_t*>(base + L.perm));
+                     reinterpret_cast<float4*>(base + L.rec), reinterpret_cast<int32_t*>(base + L.perm),
+                     reinterpret_cast<float4*>(base + L.base));
   hipLaunchKernelGGL(k_units, dim3(unsigned((L.nunit + 3) / 4)), dim3(kBlock), 0, st, pos4, N,
                      reinterpret_cast<float4*>(base + L.ub));
   if (int rc = check_hip(hipGetLastError(), "build kernels")) return rc;

@@ -13,7 +13,7 @@
 namespace pts {
 
 constexpr uint32_t kMagic = 0x31535450u;  // "PTS1"
-constexpr int kRecordVersion = 2;
+constexpr int kRecordVersion = 3;
 constexpr int kBlock = 256;               // threads per workgroup (4 waves of 64)
 constexpr int kTile2 = 128;               // points per LDS tile, blend pass (80 B each)
 constexpr int kTile1 = 512;               // points per LDS tile, farthest-point pass (16 B each)
@@ -64,12 +64,14 @@ __host__ __device__ inline size_t align256(size_t b) { return (b + 255) & ~size_
 //   ub    [U][2]  float4 bounds of each kUnit-point unit of slots, U = ceil(N / kUnit):
 //                 (center c, radius r) and (the unit's point farthest from c, 0)
 //   bb    [B]     float4 (center, radius) of each block of kBlkU units, B = ceil(U / kBlkU)
+//   base  [N][2]  float4 (p, A) and (n / |n|, -<p, n / |n|>): the baseline evaluators'
+//                 point record (A = area weight, 1 unless set by pts_set_areas)
 //   flag  [N]     int32 build scratch (direct-form flag)
 //   blk   [2*nb]  int32 build scratch (per-block counts and offsets)
 //   key, idx [2][N] uint32 / int32 build scratch (sort keys and indices, ping-pong)
 //   rhist [16*nb] int32 build scratch (radix histograms)
 struct Layout {
-  size_t pos, rec, perm, ub, bb, flag, blk, key, idx, rhist, total;
+  size_t pos, rec, perm, ub, bb, base, flag, blk, key, idx, rhist, total;
   int64_t nblk, nunit, nbk;
   __host__ __device__ explicit Layout(int64_t N) {
     nblk = (N + kBlock - 1) / kBlock;
@@ -80,7 +82,8 @@ struct Layout {
     perm = rec + align256(size_t(N) * 16 * kRecF4);
     ub = perm + align256(size_t(N) * 4);
     bb = ub + align256(size_t(nunit) * 32);
-    flag = bb + align256(size_t(nbk) * 16);
+    base = bb + align256(size_t(nbk) * 16);
+    flag = base + align256(size_t(N) * 32);
     blk = flag + align256(size_t(N) * 4);
     key = blk + align256(size_t(nblk) * 8);
     idx = key + 2 * align256(size_t(N) * 4);
@@ -127,6 +130,11 @@ int check_hip(hipError_t e, const char* what);
 int launch_build(const float* p, const float* n, const float* a, int64_t N, float kfloor_rel,
                  void* rec, hipStream_t st);
 int launch_decode(const void* rec, int64_t N, float* out, hipStream_t st);
+// Baseline evaluators (pts_baseline.hip): smoothed signed planar distance and
+// signed Hopf-Cole distance over the record's base section.
+int launch_set_areas(void* rec, int64_t N, const float* area, hipStream_t st);
+int launch_baseline(const void* rec, int64_t N, const float* x, int64_t Q, int kind, float C, const Plan& plan,
+                    const WsView& ws, float* sdf, hipStream_t st);
 // Radius-limited evaluation (pts_radius.hip).
 int launch_blocks(void* rec, int64_t N, hipStream_t st);
 int launch_radius_prepare(void* rec, int64_t N, float C, hipStream_t st);

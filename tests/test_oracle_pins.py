@@ -554,15 +554,15 @@ def test_shc_satisfies_screened_laplace():
     lam = 3.0
     x = rng.uniform(-2, 2, size=(400, 3))
     x = x[np.linalg.norm(x[:, None, :] - p[None], axis=2).min(axis=1) > 0.5][:30]
-    _, w0 = oracle.eval_baseline(p, n, x, "shc", lam_fixed=lam, raw=True)
+    _, w0, _ = oracle.eval_baseline(p, n, x, "shc", lam_fixed=lam, raw=True)
 
     def second_diff(h):
         out = np.zeros(len(x))
         for k in range(3):
             e = np.zeros(3)
             e[k] = h
-            _, wp = oracle.eval_baseline(p, n, x + e, "shc", lam_fixed=lam, raw=True)
-            _, wm = oracle.eval_baseline(p, n, x - e, "shc", lam_fixed=lam, raw=True)
+            _, wp, _ = oracle.eval_baseline(p, n, x + e, "shc", lam_fixed=lam, raw=True)
+            _, wm, _ = oracle.eval_baseline(p, n, x - e, "shc", lam_fixed=lam, raw=True)
             out += (wp - 2 * w0 + wm) / (h * h)
         return out
 
@@ -577,7 +577,7 @@ def test_shc_satisfies_screened_laplace():
 def test_shc_orientation_areas_and_sign():
     p, n, _ = _mixed_cloud(N=200)
     x = np.random.default_rng(44).uniform(-1, 1, size=(60, 3))
-    phi, w = oracle.eval_baseline(p, n, x, "shc", raw=True)
+    phi, w, _ = oracle.eval_baseline(p, n, x, "shc", raw=True)
     assert np.allclose(oracle.eval_baseline(p, -n, x, "shc"), -phi, rtol=1e-12, atol=1e-12)
     # scaling every area by k multiplies w by k: phi moves by -sign(w) log(k) / lambda_x
     M = np.linalg.norm(x[:, None, :] - p[None], axis=2).max(axis=1)
