@@ -153,8 +153,10 @@ def diff_bench(reps: int):
     """Differentiation workload: one ellipsoid, N = 32768, Q = 2^20 (half within
     0.05 of the surface, half uniform in the padded bbox), loss = sum phi^2 over
     the near-surface half.  Times the plain forward, the forward with the
-    statistics backward needs, the fused forward+gradient, d/dquery and
-    d/dcoefficients, each as pairs/s beside the plain forward."""
+    statistics backward needs, the fused forward+gradient, d/dquery,
+    d/dcoefficients, d/d(coefficients, points, normals) together, and the
+    Laplacian sweep (with the gradient and eikonal residual), each as pairs/s
+    beside the plain forward."""
     import torch
     from paper_2607_16946_amd import binding, synth
     cl, x, mask = synth.diff_workload()
@@ -166,6 +168,8 @@ def diff_bench(reps: int):
     ws_e = torch.empty(binding.eval_ws_bytes(N, Q, prm), dtype=torch.uint8, device="cuda")
     ws_g = torch.empty(binding.grad_ws_bytes(N, Q, prm), dtype=torch.uint8, device="cuda")
     ws_b = torch.empty(binding.backward_ws_bytes(N, Q, prm), dtype=torch.uint8, device="cuda")
+    ws_p = torch.empty(binding.backward_points_ws_bytes(N, Q, prm), dtype=torch.uint8, device="cuda")
+    ws_l = torch.empty(binding.laplacian_ws_bytes(N, Q, prm), dtype=torch.uint8, device="cuda")
     sdf = torch.empty(Q, dtype=torch.float32, device="cuda")
     ms = {"forward": _timed(lambda: binding.eval(rec, N, xd, prm, ws=ws_e, out=sdf), reps)}
     ms["forward_stats"] = _timed(lambda: binding.eval(rec, N, xd, prm, stats=True, ws=ws_g), reps)
@@ -174,6 +178,8 @@ def diff_bench(reps: int):
     gout = torch.where(md, 2.0 * phi, torch.zeros_like(phi))
     ms["grad_x"] = _timed(lambda: binding.grad_x(rec, N, xd, st, gout, prm, ws_g), reps)
     ms["grad_a"] = _timed(lambda: binding.backward_params(rec, p, n, a, xd, st, gout, prm, ws_b), reps)
+    ms["grad_apn"] = _timed(lambda: binding.backward_points(rec, p, n, a, xd, st, gout, prm, "apn", ws_p), reps)
+    ms["laplacian"] = _timed(lambda: binding.laplacian(rec, N, xd, st, prm, "lge", ws_l), reps)
     ms["build"] = _timed(lambda: binding.cloud_build(p, n, a, prm, rec), reps)
     pairs = float(N) * Q
     out = {"workload": f"ellipsoid, N={N}, Q={Q} (half near-surface), loss = sum phi^2 over the near half",
@@ -181,8 +187,61 @@ def diff_bench(reps: int):
            "vs_forward": {k: ms["forward"] / v for k, v in ms.items() if k != "build"},
            "train_step_ms": ms["forward_stats"] + ms["grad_x"] + ms["grad_a"]}
     log(f"diff: forward {ms['forward']:.2f} ms, +stats {ms['forward_stats']:.2f}, fused grad "
-        f"{ms['forward_grad']:.2f}, grad_x {ms['grad_x']:.2f}, grad_a {ms['grad_a']:.2f} ms")
+        f"{ms['forward_grad']:.2f}, grad_x {ms['grad_x']:.2f}, grad_a {ms['grad_a']:.2f}, grad_apn "
+        f"{ms['grad_apn']:.2f}, laplacian {ms['laplacian']:.2f} ms")
     return out
+
+
+def baseline_bench(cl, x, reps: int = 3):
+    """The two baselines of Sec. 5.2 (smoothed signed planar distance, signed
+    Hopf-Cole distance; A_i = 1) on the same workload and skeleton as the
+    blend: whole-evaluation throughput of each beside the blend's.  Then the
+    paper's accuracy measure, mean |phi - phi_true| over a 64^3 grid (the bbox
+    padded 10%), for the three methods on clouds with a closed-form SDF: the
+    unit sphere (4096 points) and a ring torus R = 0.6, r = 0.25 (4096 and
+    1024 points), analytic normals and coefficients."""
+    import numpy as np
+    import torch
+    from paper_2607_16946_amd import binding, synth
+    N, Q = cl.N, x.shape[0]
+    p, n, a, xd = (torch.from_numpy(v).cuda() for v in (cl.p, cl.n, cl.a, x))
+    prm = binding.make_params()
+    rec = binding.cloud_build(p, n, a, prm)
+    ws = torch.empty(binding.eval_ws_bytes(N, Q, prm), dtype=torch.uint8, device="cuda")
+    sdf = torch.empty(Q, dtype=torch.float32, device="cuda")
+    ms = {"torus_blend": _timed(lambda: binding.eval(rec, N, xd, prm, ws=ws, out=sdf), reps)}
+    for kind in ("sspd", "shc"):
+        ms[kind] = _timed(lambda: binding.eval_baseline(rec, N, xd, kind, prm, ws, sdf), reps)
+    pairs = float(N) * Q
+    thr = {"N": N, "Q": Q, "ms": ms, "pairs_per_s": {k: pairs / (v * 1e-3) for k, v in ms.items()}}
+
+    def truth_sphere(q):
+        return np.linalg.norm(q, axis=1) - 1.0
+
+    def truth_torus(prim):
+        def f(q):
+            y = prim.local(q)
+            return np.hypot(np.hypot(y[:, 0], y[:, 1]) - prim.R, y[:, 2]) - prim.r
+        return f
+
+    shapes = [("unit sphere, 4096 points", synth.sphere_cloud(4096), truth_sphere)]
+    for m in (4096, 1024):
+        tc, prim = synth.torus_cloud(m)
+        shapes.append((f"ring torus R=0.6 r=0.25, {m} points", tc, truth_torus(prim)))
+    acc = {}
+    for name, sc, truth in shapes:
+        lo, hi = synth.padded_bbox(sc.p, 0.1)
+        g = synth.lattice(lo, hi, 64)
+        true = truth(g.astype(np.float64))
+        c = binding.Cloud(torch.from_numpy(sc.p).cuda(), torch.from_numpy(sc.n).cuda(), torch.from_numpy(sc.a).cuda())
+        gd = torch.from_numpy(g).cuda()
+        est = {"torus_blend": c(gd)}
+        for kind in ("sspd", "shc"):
+            est[kind] = binding.eval_baseline(c.rec, c.N, gd, kind, c.params)
+        acc[name] = {k: float(np.mean(np.abs(v.cpu().numpy().astype(np.float64) - true))) for k, v in est.items()}
+        log(f"baselines: accuracy on {name}: " + ", ".join(f"{k} {v:.3e}" for k, v in acc[name].items()))
+    log(f"baselines: mid workload ms: " + ", ".join(f"{k} {v:.2f}" for k, v in ms.items()))
+    return {"throughput": thr, "accuracy_mean_abs_error_64cubed": acc}
 
 
 def radius_bench(name: str, cl, x, reps: int = 3):
@@ -368,12 +427,14 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=98304,
                     help="oracle sample (queries); about 10 s on 16 host threads at the default size")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation workload")
+    ap.add_argument("--no-baselines", action="store_true", help="skip the two baselines of the accuracy comparison")
     ap.add_argument("--no-large", action="store_true", help="skip the large (2^20 x 2^20) workload")
     ap.add_argument("--large-trace", action="store_true", help="also run the 1024^2 x 64-step trace of it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-mode measurement")
     ap.add_argument("--serving-only", action="store_true", help="only the serving-mode measurement")
+    ap.add_argument("--diff-only", action="store_true", help="only the differentiation workload")
     ap.add_argument("--serve-requests", type=int, default=600, help="measured requests per load level")
     ap.add_argument("--serve-warmup", type=int, default=50)
     ap.add_argument("--serve-loads", default="0.5,0.9", help="arrival rates as fractions of capacity")
@@ -403,6 +464,9 @@ def main():
     loads = [float(v) for v in args.serve_loads.split(",") if v]
     if args.serving_only:
         print(json.dumps({"serving": serving_bench(args.serve_requests, args.serve_warmup, loads)}))
+        return
+    if args.diff_only:
+        print(json.dumps({"diff": diff_bench(max(3, args.steps))}))
         return
     cl, x = synth.mid(N=args.points, grid=args.grid)
     N, Q = cl.N, x.shape[0]
@@ -483,6 +547,8 @@ def main():
         "roofline": roofline,
     }
     out["radius_limited"] = radius_bench("mid", cl, x)
+    if not args.no_baselines:
+        out["baselines"] = baseline_bench(cl, x)
     if not args.no_diff:
         out["diff"] = diff_bench(5)
     if not args.no_large:

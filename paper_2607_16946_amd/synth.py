@@ -274,6 +274,17 @@ def sphere_cloud(N: int = 4096, seed: int = SEED_BASE + 1, jitter: float = 0.01,
     return Cloud(p, n, a, {"shape": "sphere", "seed": seed, "radius": radius, "jitter": jitter})
 
 
+def torus_cloud(N: int, R: float = 0.6, r: float = 0.25, seed: int = SEED_BASE + 7, noise: float = 0.0):
+    """N points uniform (by area) on one ring torus with a random orientation,
+    exact normals and analytic coefficients.  Returns (cloud, the RingTorus)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    prim = RingTorus(np.zeros(3), random_rotation(rng), R, r)
+    p, n, a = sample_union(rng, [prim], N)
+    p = p + rng.normal(scale=noise, size=p.shape)
+    p, n, a = _f32(p, n, a)
+    return Cloud(p, n, a, {"shape": "ring torus", "R": R, "r": r, "seed": seed, "noise": noise}), prim
+
+
 def tiny(Q: int = 4096, N: int = 4096):
     """Plain method, tiny: N points on the unit sphere, Q queries uniform in [-1.5,1.5]^3."""
     cl = sphere_cloud(N, SEED_BASE + 1)
