@@ -244,6 +244,36 @@ def baseline_bench(cl, x, reps: int = 3):
     return {"throughput": thr, "accuracy_mean_abs_error_64cubed": acc}
 
 
+def bounded_bench(cl, x, reps: int = 3):
+    """Error-bounded evaluation on the same workload: far point units skipped
+    while a proven bound on the change of phi stays within eps (absolute,
+    given as a fraction of the bbox diagonal D).  Reports the time, the
+    fraction of pairs actually evaluated, the effective rate N Q / time and
+    the evaluated-pair rate, beside the plain evaluation."""
+    import numpy as np
+    import torch
+    from paper_2607_16946_amd import binding
+    N, Q = cl.N, x.shape[0]
+    p, n, a, xd = (torch.from_numpy(v).cuda() for v in (cl.p, cl.n, cl.a, x))
+    prm = binding.make_params()
+    rec = binding.cloud_build(p, n, a, prm)
+    D = float(binding.cloud_info(rec).diag)
+    ws = torch.empty(binding.eval_bounded_ws_bytes(N, Q, prm), dtype=torch.uint8, device="cuda")
+    sdf = torch.empty(Q, dtype=torch.float32, device="cuda")
+    pairs = float(N) * Q
+    out = {"N": N, "Q": Q, "diag": D, "runs": []}
+    for rel in (1e-6, 1e-5, 1e-4):
+        ms = _timed(lambda: binding.eval_bounded(rec, N, xd, rel * D, prm, ws, sdf), reps)
+        _, bd, kept = binding.eval_bounded(rec, N, xd, rel * D, prm, ws, sdf, bound=True, kept=True)
+        frac = float(kept.double().mean().item()) / N
+        r = {"eps_over_D": rel, "ms": ms, "evaluated_frac": frac, "effective_pairs_per_s": pairs / (ms * 1e-3),
+             "evaluated_pairs_per_s": frac * pairs / (ms * 1e-3), "max_bound_over_D": float(bd.max().item()) / D}
+        out["runs"].append(r)
+        log(f"bounded: eps {rel:g} D: {ms:.2f} ms, {100 * frac:.1f}% of pairs evaluated, effective "
+            f"{r['effective_pairs_per_s']:.3g} pairs/s (evaluated {r['evaluated_pairs_per_s']:.3g})")
+    return out
+
+
 def radius_bench(name: str, cl, x, reps: int = 3):
     """Radius-limited evaluation (Sec. 4.2, constant lambda = 1e3/D, R_eval =
     2C/lambda, 32-nearest fallback): preparation (the mean 64-nearest distance
@@ -435,6 +465,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-mode measurement")
     ap.add_argument("--serving-only", action="store_true", help="only the serving-mode measurement")
     ap.add_argument("--diff-only", action="store_true", help="only the differentiation workload")
+    ap.add_argument("--bounded-only", action="store_true", help="only the error-bounded evaluation")
     ap.add_argument("--serve-requests", type=int, default=600, help="measured requests per load level")
     ap.add_argument("--serve-warmup", type=int, default=50)
     ap.add_argument("--serve-loads", default="0.5,0.9", help="arrival rates as fractions of capacity")
@@ -467,6 +498,10 @@ def main():
         return
     if args.diff_only:
         print(json.dumps({"diff": diff_bench(max(3, args.steps))}))
+        return
+    if args.bounded_only:
+        cl, x = synth.mid(N=args.points, grid=args.grid)
+        print(json.dumps({"bounded": bounded_bench(cl, x)}))
         return
     cl, x = synth.mid(N=args.points, grid=args.grid)
     N, Q = cl.N, x.shape[0]
@@ -549,6 +584,7 @@ def main():
     out["radius_limited"] = radius_bench("mid", cl, x)
     if not args.no_baselines:
         out["baselines"] = baseline_bench(cl, x)
+    out["bounded"] = bounded_bench(cl, x)
     if not args.no_diff:
         out["diff"] = diff_bench(5)
     if not args.no_large:

@@ -165,6 +165,29 @@ int pts_grad_ws_bytes(int64_t N, int64_t Q, const pts_params* prm, size_t* out_b
 int pts_eval(const void* rec, int64_t N, const float* x, int64_t Q, float* sdf, float* grad,
              float* stats, const pts_params* prm, void* ws, size_t ws_bytes, void* stream);
 
+/* Scratch bytes for pts_eval_bounded. */
+int pts_eval_bounded_ws_bytes(int64_t N, int64_t Q, const pts_params* prm, size_t* out_bytes);
+
+/* phi at Q queries with far point units skipped under a proven error bound:
+ * |sdf[q] - phi(x_q)| <= eps in exact arithmetic (eps in the cloud's distance
+ * units, >= 0), on top of the FP32 rounding pts_eval has.  The bound rests on
+ * each torus passing through its anchor o_i = p_i + a00_i n_i (Sec. 4.1), so
+ * |g_i(x)| <= |x - p_i| + max|a00|, and on the shifted weights of
+ * Eq. (BasicFormulaShifted): a 64-point unit in the sphere (c, r) adds at most
+ * n exp(-lambda_x (|x - c| - r - sigma_x)) to the denominator.  A unit is
+ * skipped (by a whole wavefront of queries, processed in Morton order) only
+ * while the skipped bounds stay within eps times the denominator kept so far.
+ *   bound [Q] (may be NULL)  the bound actually incurred, (G_s + |phi| D_s)/D_k
+ *                            (<= eps up to FP32 rounding of the bound itself);
+ *   kept [Q]  (may be NULL)  points evaluated for the query (N without skips).
+ * eps = 0 skips nothing and returns the plain sum in another order.  Results
+ * depend on the other queries of the call (they share wavefront votes) only
+ * through which units are skipped, never beyond the bound.  ws_bytes >=
+ * pts_eval_bounded_ws_bytes(N, Q, prm).  A NaN query gives NaN. */
+int pts_eval_bounded(const void* rec, int64_t N, const float* x, int64_t Q, float eps, float* sdf,
+                     float* bound, int32_t* kept, const pts_params* prm, void* ws, size_t ws_bytes,
+                     void* stream);
+
 /* The three launches of pts_eval without gradient or statistics as separate
  * calls, with the same arguments and workspace, for callers that time or
  * schedule them individually (pts_eval is exactly these three in order):

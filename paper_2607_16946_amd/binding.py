@@ -96,6 +96,9 @@ SIGNATURES = {
     "pts_eval_far": (ctypes.c_int, [_P, _I64, _P, _I64, ctypes.POINTER(Params), _P, _SZ, _P]),
     "pts_eval_blend": (ctypes.c_int, [_P, _I64, _P, _I64, ctypes.POINTER(Params), _P, _SZ, _P]),
     "pts_eval_combine": (ctypes.c_int, [_I64, _I64, _P, ctypes.POINTER(Params), _P, _SZ, _P]),
+    "pts_eval_bounded_ws_bytes": (ctypes.c_int, [_I64, _I64, ctypes.POINTER(Params), ctypes.POINTER(_SZ)]),
+    "pts_eval_bounded": (ctypes.c_int, [_P, _I64, _P, _I64, ctypes.c_float, _P, _P, _P, ctypes.POINTER(Params), _P,
+                                        _SZ, _P]),
     "pts_set_areas": (ctypes.c_int, [_P, _I64, _P, _P]),
     "pts_eval_baseline": (ctypes.c_int, [_P, _I64, _P, _I64, ctypes.c_int, _P, ctypes.POINTER(Params), _P, _SZ,
                                          _P]),
@@ -261,6 +264,33 @@ def eval(rec: torch.Tensor, N: int, x: torch.Tensor, params: Params | None = Non
     if stats:
         res.append(st)
     return res[0] if len(res) == 1 else tuple(res)
+
+
+def eval_bounded_ws_bytes(N: int, Q: int, params: Params | None = None) -> int:
+    out = _SZ(0)
+    prm = params if params is not None else make_params()
+    _check(lib().pts_eval_bounded_ws_bytes(int(N), int(Q), ctypes.byref(prm), ctypes.byref(out)))
+    return int(out.value)
+
+
+def eval_bounded(rec: torch.Tensor, N: int, x: torch.Tensor, eps: float, params: Params | None = None,
+                 ws: torch.Tensor | None = None, out: torch.Tensor | None = None, bound: bool = False,
+                 kept: bool = False):
+    """phi at x [Q,3] with far units skipped while |change| <= eps (proven); optionally the incurred bound [Q]
+    and the number of points evaluated per query [Q].  Returns sdf, or (sdf, bound, kept) with None entries."""
+    _dev(x, "x", 3)
+    Q = x.shape[0]
+    prm = params if params is not None else make_params()
+    sdf = out if out is not None else torch.empty(Q, dtype=torch.float32, device=x.device)
+    bd = torch.empty(Q, dtype=torch.float32, device=x.device) if bound else None
+    kp = torch.empty(Q, dtype=torch.int32, device=x.device) if kept else None
+    if Q > 0:
+        need = eval_bounded_ws_bytes(N, Q, prm)
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(max(need, 256), dtype=torch.uint8, device=x.device)
+        _check(lib().pts_eval_bounded(_ptr(rec), int(N), _ptr(x), Q, float(eps), _ptr(sdf), _ptr(bd), _ptr(kp),
+                                      ctypes.byref(prm), _ptr(ws), ws.numel(), _stream()))
+    return (sdf, bd, kp) if (bound or kept) else sdf
 
 
 BASELINES = {"sspd": 0, "shc": 1}

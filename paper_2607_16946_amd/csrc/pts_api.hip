@@ -269,6 +269,29 @@ int pts_eval_combine(int64_t N, int64_t Q, float* sdf, const pts_params* prm, vo
   return launch_combine(Q, plan, ws_view(plan, Q, ws), sdf, static_cast<hipStream_t>(stream));
 }
 
+int pts_eval_bounded_ws_bytes(int64_t N, int64_t Q, const pts_params* prm, size_t* out_bytes) {
+  if (!out_bytes) return fail(PTS_EINVAL, "out_bytes is NULL");
+  if (N < 1 || Q < 0) return fail(PTS_EINVAL, "N must be >= 1 and Q >= 0");
+  const pts_params P = resolve(prm);
+  if (int rc = check_params(P)) return rc;
+  *out_bytes = Q == 0 ? 0 : bounded_ws_bytes(make_plan(N, Q, &P), Q);
+  return PTS_OK;
+}
+
+int pts_eval_bounded(const void* rec, int64_t N, const float* x, int64_t Q, float eps, float* sdf, float* bound,
+                     int32_t* kept, const pts_params* prm, void* ws, size_t ws_bytes, void* stream) {
+  if (N < 1 || Q < 0) return fail(PTS_EINVAL, "N must be >= 1 and Q >= 0");
+  if (Q > (int64_t(1) << 31) - 1) return fail(PTS_EINVAL, "Q must be < 2^31");
+  if (!(eps >= 0.f) || !(eps < 3.0e38f)) return fail(PTS_EINVAL, "eps must be finite and >= 0");
+  const pts_params P = resolve(prm);
+  if (int rc = check_params(P)) return rc;
+  if (Q == 0) return PTS_OK;
+  if (!rec || !x || !sdf || !ws) return fail(PTS_EINVAL, "null pointer");
+  const Plan plan = make_plan(N, Q, &P);
+  if (ws_bytes < bounded_ws_bytes(plan, Q)) return fail(PTS_EINVAL, "workspace too small");
+  return launch_bounded(rec, N, x, Q, eps, P.C, plan, ws, sdf, bound, kept, static_cast<hipStream_t>(stream));
+}
+
 int pts_set_areas(void* rec, int64_t N, const float* area, void* stream) {
   if (N < 1) return fail(PTS_EINVAL, "N must be >= 1");
   if (!rec) return fail(PTS_EINVAL, "null record");

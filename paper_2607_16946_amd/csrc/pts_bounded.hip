@@ -1,0 +1,312 @@
+// pts_bounded.hip -- phi of Eq. (BasicFormulaShifted) with far point units
+// skipped under a proven bound on the change of phi.
+//
+// The bound.  Every torus passes through its anchor o_i = p_i + a00_i n_i
+// (Sec. 4.1), so |g_i(x)| <= |x - o_i| <= |x - p_i| + A with A = max |a00|.
+// For a unit of n points inside the sphere (c, r) and a query x at
+// s = |x - c|, every weight is at most w_u = exp(-lambda_x (max(s - r, 0) - sigma_x))
+// and every |g_i| at most s + r + A, so the unit adds at most
+//   d_u = n w_u  to the denominator,  g_u = d_u (s + r + A)  to |numerator|.
+// If the skipped units' totals are D_s <= sum d_u and G_s <= sum g_u and the
+// kept sums give phi' = N_k / D_k, then
+//   |phi - phi'| = |N_s - phi' D_s| / (D_k + D_s) <= (G_s + |phi'| D_s) / D_k,
+// and |phi'| <= Phi = M + A (every |g_i| <= |x - p_i| + A <= M + A).  A unit
+// is skipped only while G_s + Phi D_s (totals including it) stays within
+// eps D_run, the kept denominator so far; D_run <= D_k, so the final bound
+// (G_s + |phi'| D_s) / D_k <= eps.  The kernel reports that bound per query.
+// Bounds carry a relative slack of 1e-4 for FP32 rounding of s, the exponent
+// and D_run; the returned phi' itself has the rounding of the plain blend.
+//
+// Making skips pay.  A unit's work is skipped by a whole wave or not at all,
+// so the wave's queries must agree: queries are processed in Morton order of
+// the cloud's bbox (a radix sort of the query keys on the device) and each
+// lane takes QPL consecutive sorted queries, so a wave covers a compact brick
+// of 64 QPL queries.  D_run must be large early: each workgroup starts its
+// sweep at the unit nearest to its first query and wraps around its point
+// range.  Point ranges are split over S workgroups as in the plain blend; the
+// bound holds per split (each split's skipped totals are within eps times its
+// own kept denominator) and therefore for their sum.
+//
+//   k_qkeys    Morton key (3 x 8 bits over the cloud's bbox) of every query
+//   (radix sort of the keys, pts_build.hip)
+//   k_bounded  the sweep: per tile of 128 points (two units), a wave votes
+//              per unit; kept units run the blend's pair arithmetic
+//   k_bcombine fixed-order sum over splits, phi', the bound, kept counts
+#include "pts_device.h"
+
+namespace pts {
+namespace {
+
+constexpr float kSlack = 1e-4f;
+
+__device__ inline uint32_t spread3_8(uint32_t v) {
+  uint32_t r = 0;
+  for (int k = 0; k < 8; ++k) r |= ((v >> k) & 1u) << (3 * k);
+  return r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_qkeys(const Header* __restrict__ h, const float* __restrict__ x,
+                                                  int64_t Q, uint32_t* __restrict__ key, int32_t* __restrict__ idx) {
+  const int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (q >= Q) return;
+  uint32_t m = 0;
+  for (int k = 0; k < 3; ++k) {
+    const float lo = h->lo[k], ext = h->hi[k] - h->lo[k];
+    float t = ext > 0.f ? (x[3 * q + k] - lo) / ext * 256.f : 0.f;
+    t = t < 0.f ? 0.f : (t > 255.f ? 255.f : t);   // NaN compares false: stays NaN -> below
+    int c = t == t ? int(t) : 0;
+    m |= spread3_8(uint32_t(c)) << k;
+  }
+  key[q] = m;
+  idx[q] = int32_t(q);
+}
+
+template <bool kDirect>
+__device__ __forceinline__ void pair(float qx, float qy, float qz, float nl, float C2, const float4& P,
+                                     const float4& U, const float4& Mv, const float4& K, const float4& G, float& tn,
+                                     float& td) {
+  const float dx = qx - P.x, dy = qy - P.y, dz = qz - P.z;
+  const float d = hw_sqrt(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+  const float w = hw_exp2(fmaf(d, nl, C2));
+  const float g = kDirect ? g_direct(qx, qy, qz, U, Mv, K, G) : g_anchored(qx, qy, qz, P.w, U, Mv, K, G);
+  tn = fmaf(w, g, tn);
+  td += w;
+}
+
+template <int QPL>
+__global__ __launch_bounds__(kBlock) void k_bounded(const Header* __restrict__ h, const float4* __restrict__ rec,
+                                                    const float4* __restrict__ ub, const float* __restrict__ x,
+                                                    const int32_t* __restrict__ order, int64_t Q, int S,
+                                                    int64_t per_split, const float* __restrict__ far2, float C2,
+                                                    float eps, float4* __restrict__ part,
+                                                    int32_t* __restrict__ kpart) {
+  __shared__ float4 tile[kTile2 * kRecF4];
+  __shared__ float red_v[kBlock];
+  __shared__ int32_t red_i[kBlock];
+  __shared__ float4 ref;
+  __shared__ int vote[2][kBlock / 64];
+  const int split = int(blockIdx.x % unsigned(S));
+  const int64_t qb = blockIdx.x / unsigned(S);
+  const int64_t N = h->N;
+  const int64_t nd = h->n_direct;
+  const float A = __uint_as_float(h->a00max_bits);
+  const int64_t j0 = qb * (kBlock * QPL);          // first sorted position of the block
+  float qx[QPL], qy[QPL], qz[QPL], nl[QPL], phimax[QPL], num[QPL], den[QPL], gs[QPL], ds[QPL];
+  bool live[QPL];
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) {
+    const int64_t j = j0 + int64_t(threadIdx.x) * QPL + k;
+    live[k] = j < Q;
+    const int64_t q = live[k] ? order[j] : 0;
+    const QueryIn qi = load_query(x, q, live[k] ? Q : 0, h);
+    qx[k] = qi.x; qy[k] = qi.y; qz[k] = qi.z;
+    float M = 0.f;
+    nl[k] = 0.f;
+    if (qi.valid) far_of(far2, 1, Q, q, C2, M, nl[k]);
+    phimax[k] = M + A;
+    num[k] = den[k] = gs[k] = ds[k] = 0.f;
+  }
+  const int64_t beg = int64_t(split) * per_split;
+  const int64_t end = min(N, beg + per_split);
+  const int64_t ntile = (end - beg + kTile2 - 1) / kTile2;
+  // seed: the tile holding the unit nearest (by sphere lower bound) to the block's first query
+  if (threadIdx.x == 0) {
+    const QueryIn r = load_query(x, order[j0], Q, h);
+    ref = make_float4(r.x, r.y, r.z, 0.f);
+  }
+  __syncthreads();
+  const int64_t u_beg = beg / kUnit, u_end = (end + kUnit - 1) / kUnit;
+  float best = 3.0e38f;
+  int32_t bi = int32_t(u_beg);
+  for (int64_t u = u_beg + threadIdx.x; u < u_end; u += kBlock) {
+    const float4 cb = ub[2 * u];
+    const float ex = ref.x - cb.x, ey = ref.y - cb.y, ez = ref.z - cb.z;
+    const float lb = sqrtf(fmaf(ez, ez, fmaf(ey, ey, ex * ex))) - cb.w;
+    if (lb < best) { best = lb; bi = int32_t(u); }
+  }
+  red_v[threadIdx.x] = best;
+  red_i[threadIdx.x] = bi;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if (int(threadIdx.x) < o) {
+      const float v2 = red_v[threadIdx.x + o];
+      const int32_t i2 = red_i[threadIdx.x + o];
+      if (v2 < red_v[threadIdx.x] || (v2 == red_v[threadIdx.x] && i2 < red_i[threadIdx.x])) {
+        red_v[threadIdx.x] = v2;
+        red_i[threadIdx.x] = i2;
+      }
+    }
+    __syncthreads();
+  }
+  const int64_t t_seed = (int64_t(red_i[0]) * kUnit - beg) / kTile2;
+  const int wave = int(threadIdx.x >> 6);
+  int32_t kept = 0;
+  for (int64_t it = 0; it < ntile; ++it) {
+    int64_t tix = t_seed + it;
+    if (tix >= ntile) tix -= ntile;
+    const int64_t t0 = beg + tix * kTile2;
+    const int cnt = int(min<int64_t>(kTile2, end - t0));
+    // votes, against the kept denominator at the start of the tile (a lower
+    // bound of it at any later point): one per unit, wave-wide
+    int need = 0;
+    for (int ju = 0, ui = 0; ju < cnt; ju += kUnit, ++ui) {
+      const int je = min(cnt, ju + kUnit);
+      const float4 cb = ub[2 * ((t0 + ju) / kUnit)];
+      float du[QPL], gu[QPL];
+      bool ok = true;
+#pragma unroll
+      for (int k = 0; k < QPL; ++k) {
+        const float ex = qx[k] - cb.x, ey = qy[k] - cb.y, ez = qz[k] - cb.z;
+        const float s = sqrtf(fmaf(ez, ez, fmaf(ey, ey, ex * ex)));
+        const float dmin = fmaxf(s * (1.f - kSlack) - cb.w * (1.f + kSlack), 0.f);
+        du[k] = float(je - ju) * exp2f(fmaf(dmin, nl[k], C2)) * (1.f + kSlack);
+        gu[k] = du[k] * (s + cb.w + A) * (1.f + kSlack);
+        const bool skip = (gs[k] + gu[k]) + phimax[k] * (ds[k] + du[k]) <= eps * den[k] * (1.f - kSlack);
+        ok = ok && (skip || !live[k]);
+      }
+      if (__ballot(!ok) == 0ull) {
+#pragma unroll
+        for (int k = 0; k < QPL; ++k) {
+          gs[k] += gu[k];
+          ds[k] += du[k];
+        }
+      } else {
+        need |= 1 << ui;
+      }
+    }
+    if ((threadIdx.x & 63) == 0) vote[it & 1][wave] = need;
+    __syncthreads();
+    const int any = vote[it & 1][0] | vote[it & 1][1] | vote[it & 1][2] | vote[it & 1][3];
+    if (any == 0) continue;          // workgroup-uniform: every wave skips both units
+    for (int j = threadIdx.x; j < cnt * kRecF4; j += kBlock) tile[j] = rec[t0 * kRecF4 + j];
+    __syncthreads();
+    const int jd = int(max<int64_t>(0, min<int64_t>(cnt, nd - t0)));
+    float tn[QPL], td[QPL];
+#pragma unroll
+    for (int k = 0; k < QPL; ++k) { tn[k] = 0.f; td[k] = 0.f; }
+    for (int ju = 0, ui = 0; ju < cnt; ju += kUnit, ++ui) {
+      if (!(need & (1 << ui))) continue;   // wave-uniform
+      const int je = min(cnt, ju + kUnit);
+      kept += je - ju;
+      for (int j = ju; j < min(je, jd); ++j) {
+        const float4 P = tile[j * kRecF4 + 0], U = tile[j * kRecF4 + 1], Mv = tile[j * kRecF4 + 2],
+                     K = tile[j * kRecF4 + 3], G = tile[j * kRecF4 + 4];
+#pragma unroll
+        for (int k = 0; k < QPL; ++k) pair<true>(qx[k], qy[k], qz[k], nl[k], C2, P, U, Mv, K, G, tn[k], td[k]);
+      }
+      for (int j = max(ju, jd); j < je; ++j) {
+        const float4 P = tile[j * kRecF4 + 0], U = tile[j * kRecF4 + 1], Mv = tile[j * kRecF4 + 2],
+                     K = tile[j * kRecF4 + 3], G = tile[j * kRecF4 + 4];
+#pragma unroll
+        for (int k = 0; k < QPL; ++k) pair<false>(qx[k], qy[k], qz[k], nl[k], C2, P, U, Mv, K, G, tn[k], td[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < QPL; ++k) { num[k] += tn[k]; den[k] += td[k]; }
+    __syncthreads();                 // the tile is read; the next staging may overwrite it
+  }
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) {
+    const int64_t j = j0 + int64_t(threadIdx.x) * QPL + k;
+    if (j < Q) {
+      part[int64_t(split) * Q + j] = make_float4(num[k], den[k], gs[k], ds[k]);
+      kpart[int64_t(split) * Q + j] = kept;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bcombine(const float4* __restrict__ part,
+                                                     const int32_t* __restrict__ kpart,
+                                                     const int32_t* __restrict__ order, int S, int64_t Q,
+                                                     float* __restrict__ sdf, float* __restrict__ bound,
+                                                     int32_t* __restrict__ kept) {
+  const int64_t j = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (j >= Q) return;
+  float num = 0.f, den = 0.f, gs = 0.f, ds = 0.f;
+  int32_t kc = 0;
+  for (int s = 0; s < S; ++s) {
+    const float4 v = part[int64_t(s) * Q + j];
+    num += v.x;
+    den += v.y;
+    gs += v.z;
+    ds += v.w;
+    kc += kpart[int64_t(s) * Q + j];
+  }
+  const int64_t q = order[j];
+  const float phi = num / den;
+  sdf[q] = phi;
+  if (bound) bound[q] = (gs + fabsf(phi) * ds) / den;
+  if (kept) kept[q] = kc;
+}
+
+template <int QPL>
+void launch_bounded_q(const Header* h, const float4* rec, const float4* ub, const float* x, const int32_t* order,
+                      int64_t Q, const Plan& plan, const float* far2, float C2, float eps, float4* part,
+                      int32_t* kpart, hipStream_t st) {
+  hipLaunchKernelGGL(k_bounded<QPL>, dim3(unsigned(plan.nqb * plan.S)), dim3(kBlock), 0, st, h, rec, ub, x, order,
+                     Q, plan.S, plan.per_split, far2, C2, eps, part, kpart);
+}
+
+// Workspace: far2 [Q], partials float4 [S][Q], kept int32 [S][Q], keys and
+// indices [2][Q] each, radix histograms.
+struct BoundedWs {
+  float* far2;
+  float4* part;
+  int32_t* kpart;
+  uint32_t* key[2];
+  int32_t* idx[2];
+  int32_t* rhist;
+  size_t bytes;
+};
+
+BoundedWs bounded_ws(const Plan& plan, int64_t Q, void* ws) {
+  char* c = static_cast<char*>(ws);
+  BoundedWs v;
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    char* r = c ? c + o : nullptr;
+    o += align256(b);
+    return r;
+  };
+  v.far2 = reinterpret_cast<float*>(take(size_t(Q) * 4));
+  v.part = reinterpret_cast<float4*>(take(size_t(plan.S) * size_t(Q) * 16));
+  v.kpart = reinterpret_cast<int32_t*>(take(size_t(plan.S) * size_t(Q) * 4));
+  for (int i = 0; i < 2; ++i) v.key[i] = reinterpret_cast<uint32_t*>(take(size_t(Q) * 4));
+  for (int i = 0; i < 2; ++i) v.idx[i] = reinterpret_cast<int32_t*>(take(size_t(Q) * 4));
+  v.rhist = reinterpret_cast<int32_t*>(take(size_t((Q + kBlock - 1) / kBlock) * 16 * 4));
+  v.bytes = o;
+  return v;
+}
+
+}  // namespace
+
+size_t bounded_ws_bytes(const Plan& plan, int64_t Q) { return bounded_ws(plan, Q, nullptr).bytes; }
+
+int launch_bounded(const void* rec, int64_t N, const float* x, int64_t Q, float eps, float C, const Plan& plan,
+                   void* ws, float* sdf, float* bound, int32_t* kept, hipStream_t st) {
+  const Layout L(N);
+  const char* base = static_cast<const char*>(rec);
+  const Header* h = reinterpret_cast<const Header*>(base);
+  const float4* recs = reinterpret_cast<const float4*>(base + L.rec);
+  const float4* ub = reinterpret_cast<const float4*>(base + L.ub);
+  BoundedWs v = bounded_ws(plan, Q, ws);
+  const unsigned qblocks = unsigned((Q + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL(k_qkeys, dim3(qblocks), dim3(kBlock), 0, st, h, x, Q, v.key[0], v.idx[0]);
+  int cur = 0;
+  if (int rc = launch_radix_sort(v.key, v.idx, Q, 6, v.rhist, st, &cur)) return rc;
+  const int32_t* order = v.idx[cur];
+  if (int rc = launch_far_cull(rec, N, x, Q, plan.qpl, v.far2, nullptr, st)) return rc;
+  const float C2 = C * kLog2e;
+  switch (plan.qpl) {
+    case 1: launch_bounded_q<1>(h, recs, ub, x, order, Q, plan, v.far2, C2, eps, v.part, v.kpart, st); break;
+    case 2: launch_bounded_q<2>(h, recs, ub, x, order, Q, plan, v.far2, C2, eps, v.part, v.kpart, st); break;
+    default:
+      launch_bounded_q<4>(h, recs, ub, x, order, Q, with_qpl(plan, 4, Q), v.far2, C2, eps, v.part, v.kpart, st);
+      break;
+  }
+  hipLaunchKernelGGL(k_bcombine, dim3(qblocks), dim3(kBlock), 0, st, v.part, v.kpart, order, plan.S, Q, sdf, bound,
+                     kept);
+  return check_hip(hipGetLastError(), "bounded evaluation kernels");
+}
+
+}  // namespace pts

@@ -71,6 +71,8 @@ __global__ void k_init(Header* h, int64_t N) {
   h->rl_reval = 0.f;
   h->rl_ready = 0;
   h->pad1 = 0;
+  h->a00max_bits = 0u;
+  h->pad2 = 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_bbox(const float* __restrict__ p, const float* __restrict__ n,
@@ -280,7 +282,8 @@ __global__ __launch_bounds__(kBlock) void k_fit(const float* __restrict__ p, con
                                                 const float* __restrict__ a, int64_t N, float kfloor_rel,
                                                 const Header* __restrict__ h, const int32_t* __restrict__ order,
                                                 float4* __restrict__ pos4, float4* __restrict__ rec,
-                                                int32_t* __restrict__ perm, float4* __restrict__ bas) {
+                                                int32_t* __restrict__ perm, float4* __restrict__ bas,
+                                                Header* hw) {
   const BoxInfo b = box_info(h, kfloor_rel);
   const int64_t slot = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (slot >= N) return;
@@ -315,6 +318,8 @@ __global__ __launch_bounds__(kBlock) void k_fit(const float* __restrict__ p, con
   double nh[3] = {0.0, 0.0, 0.0};
   if (nl > 0.0)
     for (int k = 0; k < 3; ++k) nh[k] = nd[k] / nl;
+  // the torus passes through o = p + a00 n, so |g(x)| <= |x - p| + |a00|
+  atomicMax(&hw->a00max_bits, __float_as_uint(fabsf(a[6 * i])));
   bas[2 * slot] = make_float4(px, py, pz, 1.f);
   bas[2 * slot + 1] = make_float4(float(nh[0]), float(nh[1]), float(nh[2]), float(-dot(pr, nh)));
 }
@@ -387,6 +392,22 @@ __global__ __launch_bounds__(kBlock) void k_decode(const Header* __restrict__ h,
 
 }  // namespace
 
+int launch_radix_sort(uint32_t* key[2], int32_t* idx[2], int64_t n, int passes, int32_t* rhist, hipStream_t st,
+                      int* out) {
+  const unsigned nb = unsigned((n + kBlock - 1) / kBlock);
+  int cur = 0;
+  for (int pass = 0; pass < passes; ++pass) {
+    const int shift = pass * kSortBits;
+    hipLaunchKernelGGL(k_rhist, dim3(nb), dim3(kBlock), 0, st, key[cur], n, shift, rhist, int64_t(nb));
+    hipLaunchKernelGGL(k_exscan, dim3(1), dim3(1024), 0, st, rhist, int64_t(nb) << kSortBits);
+    hipLaunchKernelGGL(k_rscatter, dim3(nb), dim3(kBlock), 0, st, key[cur], idx[cur], key[1 - cur], idx[1 - cur], n,
+                       shift, rhist, int64_t(nb));
+    cur = 1 - cur;
+  }
+  *out = cur;
+  return check_hip(hipGetLastError(), "radix sort");
+}
+
 int launch_build(const float* p, const float* n, const float* a, int64_t N, float kfloor_rel, void* rec,
                  hipStream_t st) {
   const Layout L(N);
@@ -406,18 +427,11 @@ int launch_build(const float* p, const float* n, const float* a, int64_t N, floa
   hipLaunchKernelGGL(k_flags, dim3(nb), dim3(kBlock), 0, st, p, a, N, kfloor_rel, h, flag, blk, key[0], idx[0]);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, blk, int64_t(nb), N, kfloor_rel, h);
   int cur = 0;
-  for (int pass = 0; pass < kSortPasses; ++pass) {
-    const int shift = pass * kSortBits;
-    hipLaunchKernelGGL(k_rhist, dim3(nb), dim3(kBlock), 0, st, key[cur], N, shift, rhist, int64_t(nb));
-    hipLaunchKernelGGL(k_exscan, dim3(1), dim3(1024), 0, st, rhist, int64_t(nb) << kSortBits);
-    hipLaunchKernelGGL(k_rscatter, dim3(nb), dim3(kBlock), 0, st, key[cur], idx[cur], key[1 - cur], idx[1 - cur], N,
-                       shift, rhist, int64_t(nb));
-    cur = 1 - cur;
-  }
+  if (int rc = launch_radix_sort(key, idx, N, kSortPasses, rhist, st, &cur)) return rc;
   float4* pos4 = reinterpret_cast<float4*>(base + L.pos);
   hipLaunchKernelGGL(k_fit, dim3(nb), dim3(kBlock), 0, st, p, n, a, N, kfloor_rel, h, idx[cur], pos4,
                      reinterpret_cast<float4*>(base + L.rec), reinterpret_cast<int32_t*>(base + L.perm),
-                     reinterpret_cast<float4*>(base + L.base));
+                     reinterpret_cast<float4*>(base + L.base), h);
   hipLaunchKernelGGL(k_units, dim3(unsigned((L.nunit + 3) / 4)), dim3(kBlock), 0, st, pos4, N,
                      reinterpret_cast<float4*>(base + L.ub));
   if (int rc = check_hip(hipGetLastError(), "build kernels")) return rc;

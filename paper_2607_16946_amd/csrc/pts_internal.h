@@ -49,6 +49,8 @@ struct alignas(256) Header {
   float rl_reval;       // 2 C / rl_lambda
   int32_t rl_ready;     // 1 once the three values above are set
   int32_t pad1;
+  uint32_t a00max_bits; // bits of max_i |a00_i| (non-negative, so integer order is float order)
+  int32_t pad2;
 };
 static_assert(sizeof(Header) == 256, "header is 256 bytes");
 
@@ -130,6 +132,18 @@ int check_hip(hipError_t e, const char* what);
 int launch_build(const float* p, const float* n, const float* a, int64_t N, float kfloor_rel,
                  void* rec, hipStream_t st);
 int launch_decode(const void* rec, int64_t N, float* out, hipStream_t st);
+// Stable LSD radix sort of (key, index) pairs, kSortBits per pass, `passes`
+// passes from the lowest digit; key[0]/idx[0] hold the input and the result
+// ends in key[*out]/idx[*out].  rhist: 16 * ceil(n / kBlock) int32 of scratch.
+int launch_radix_sort(uint32_t* key[2], int32_t* idx[2], int64_t n, int passes, int32_t* rhist, hipStream_t st,
+                      int* out);
+
+// Error-bounded evaluation (pts_bounded.hip): the blend with point units
+// skipped while a proven bound on the change of phi stays within eps.
+size_t bounded_ws_bytes(const Plan& plan, int64_t Q);
+int launch_bounded(const void* rec, int64_t N, const float* x, int64_t Q, float eps, float C, const Plan& plan,
+                   void* ws, float* sdf, float* bound, int32_t* kept, hipStream_t st);
+
 // Baseline evaluators (pts_baseline.hip): smoothed signed planar distance and
 // signed Hopf-Cole distance over the record's base section.
 int launch_set_areas(void* rec, int64_t N, const float* area, hipStream_t st);

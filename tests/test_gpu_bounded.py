@@ -1,0 +1,92 @@
+"""Error-bounded evaluation: far point units skipped under a proven bound.
+
+For every query: |phi_bounded - phi_oracle| <= eps + 1e-5 D (the blend's FP32
+tolerance on top of the proven bound), the reported bound is <= eps (1e-3
+relative slack for its own FP32 evaluation), and |phi_bounded - phi_eval| <=
+bound + 2e-6 D against the unculled device sum (both carry FP32 rounding of
+differently ordered sums).  eps = 0 must skip nothing.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2607_16946_amd import binding, synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    binding.lib()
+
+
+def _check(cl, x, eps_rel, sample=None, what=""):
+    c = binding.Cloud(_dev(cl.p), _dev(cl.n), _dev(cl.a))
+    D = max(oracle.bbox_diag(cl.p), 1.0)
+    eps = eps_rel * D
+    xs = _dev(x)
+    phi, bd, kept = binding.eval_bounded(c.rec, c.N, xs, eps, c.params, bound=True, kept=True)
+    full = c(xs)
+    phi, bd, kept, full = (t.cpu().numpy() for t in (phi, bd, kept, full))
+    assert np.all(bd <= eps * (1 + 1e-3) + 1e-30)
+    dev = np.abs(phi.astype(np.float64) - full)
+    assert np.all(dev <= bd + 2e-6 * D)
+    idx = np.arange(len(x)) if sample is None else sample
+    ref = oracle.sdf(cl.p, cl.n, cl.a, x[idx])
+    err = np.abs(phi[idx].astype(np.float64) - ref)
+    frac = kept.mean() / c.N
+    print(f"{what} eps {eps_rel:g} D: max |phi - oracle| {err.max():.3e} (bound up to {bd.max():.3e}), "
+          f"max |phi - unculled| {dev.max():.3e}, points evaluated {100 * frac:.1f}%", flush=True)
+    assert np.all(err <= eps + TOL * D)
+    return frac, kept
+
+
+@pytest.mark.parametrize("eps_rel", [0.0, 1e-6, 1e-4, 1e-2])
+def test_bounded_mid_small(eps_rel):
+    cl, x = synth.mid(N=6000, grid=12)
+    frac, kept = _check(cl, x, eps_rel, what="mid-6k")
+    if eps_rel == 0.0:
+        assert np.all(kept == cl.N)
+    if eps_rel >= 1e-4:
+        assert frac < 0.9
+
+
+def test_bounded_ragged_and_random_queries():
+    cl, _ = synth.mid(N=4097, grid=4)
+    x = np.random.default_rng(8).uniform(-1.3, 1.3, size=(1001, 3)).astype(np.float32)
+    _check(cl, x, 1e-5, what="ragged")
+
+
+def test_bounded_benchmark_size_sampled():
+    # the benchmark cloud (131072 points) on a 64^3 lattice; the oracle on a sample
+    cl, x = synth.mid(N=131072, grid=64)
+    sample = np.random.default_rng(9).choice(len(x), 300, replace=False)
+    frac, _ = _check(cl, x, 1e-6, sample=sample, what="mid-131k")
+    assert frac < 0.5
+
+
+def test_bounded_edge_cases():
+    cl, x = synth.tiny(Q=50, N=700)
+    c = binding.Cloud(_dev(cl.p), _dev(cl.n), _dev(cl.a))
+    assert binding.eval_bounded(c.rec, c.N, _dev(x[:0]), 1e-3, c.params).numel() == 0
+    q = np.array([[np.nan, 0.0, 0.0], [0.1, 0.2, 0.3]], np.float32)
+    phi = binding.eval_bounded(c.rec, c.N, _dev(q), 1e-3, c.params).cpu().numpy()
+    assert np.isnan(phi[0]) and np.isfinite(phi[1])
+    with pytest.raises(binding.PtsError):
+        binding.eval_bounded(c.rec, c.N, _dev(x), -1.0, c.params)
+    # deterministic
+    a = binding.eval_bounded(c.rec, c.N, _dev(x), 1e-3, c.params)
+    assert torch.equal(a, binding.eval_bounded(c.rec, c.N, _dev(x), 1e-3, c.params))
+    # one point: nothing to skip
+    one = synth.Cloud(cl.p[:1].copy(), cl.n[:1].copy(), cl.a[:1].copy(), {})
+    _check(one, x, 1e-2, what="one point")
