@@ -274,7 +274,7 @@ int pts_eval_bounded_ws_bytes(int64_t N, int64_t Q, const pts_params* prm, size_
   if (N < 1 || Q < 0) return fail(PTS_EINVAL, "N must be >= 1 and Q >= 0");
   const pts_params P = resolve(prm);
   if (int rc = check_params(P)) return rc;
-  *out_bytes = Q == 0 ? 0 : bounded_ws_bytes(make_plan(N, Q, &P), Q);
+  *out_bytes = Q == 0 ? 0 : bounded_ws_bytes(bounded_plan(N, Q), Q);
   return PTS_OK;
 }
 
@@ -287,7 +287,7 @@ int pts_eval_bounded(const void* rec, int64_t N, const float* x, int64_t Q, floa
   if (int rc = check_params(P)) return rc;
   if (Q == 0) return PTS_OK;
   if (!rec || !x || !sdf || !ws) return fail(PTS_EINVAL, "null pointer");
-  const Plan plan = make_plan(N, Q, &P);
+  const Plan plan = bounded_plan(N, Q);
   if (ws_bytes < bounded_ws_bytes(plan, Q)) return fail(PTS_EINVAL, "workspace too small");
   return launch_bounded(rec, N, x, Q, eps, P.C, plan, ws, sdf, bound, kept, static_cast<hipStream_t>(stream));
 }

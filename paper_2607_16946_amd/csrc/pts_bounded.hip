@@ -21,16 +21,31 @@
 // so the wave's queries must agree: queries are processed in Morton order of
 // the cloud's bbox (a radix sort of the query keys on the device) and each
 // lane takes QPL consecutive sorted queries, so a wave covers a compact brick
-// of 64 QPL queries.  D_run must be large early: each workgroup starts its
-// sweep at the unit nearest to its first query and wraps around its point
-// range.  Point ranges are split over S workgroups as in the plain blend; the
-// bound holds per split (each split's skipped totals are within eps times its
-// own kept denominator) and therefore for their sum.
+// of 64 QPL queries.  Each workgroup is one wave, which stages into LDS only
+// the units it keeps: no wave waits on units only another keeps.  D_run must
+// be large early: each wave starts its sweep at the unit nearest to its first
+// query and wraps around its point range.
+//
+// Splits.  The path has its own plan: one point range per query block unless
+// that leaves fewer than ~2048 workgroups, then S ranges.  A range far from
+// its queries keeps only tiny weights, so its own kept denominator would
+// allow few skips; instead every workgroup of a query block first computes the
+// weights W_seed of one shared seed unit (the unit nearest the block's first
+// query).  The range holding it sweeps it first and always keeps it (nothing is
+// skipped against an empty denominator); every other range skips against
+// W_seed plus its own kept sum, each with budget eps / (S + 1).  Summed over
+// ranges the skipped bounds are at most eps / (S + 1) (S W_seed + D_k) <= eps D_k.
 //
 //   k_qkeys    Morton key (3 x 8 bits over the cloud's bbox) of every query
 //   (radix sort of the keys, pts_build.hip)
-//   k_bounded  the sweep: per tile of 128 points (two units), a wave votes
-//              per unit; kept units run the blend's pair arithmetic
+//   k_bwork    per query block: a work estimate (units whose sphere comes
+//              within 25 / lambda of the nearest one, seen from the block's
+//              first query), sorted so that heavy blocks launch first and the
+//              tail of the launch is light (ordering only: a block's result
+//              does not depend on when it runs)
+//   k_bounded  the sweep: a wave votes per block of 64 units (4096 points)
+//              and, in blocks it keeps, per 64-point unit; kept units are
+//              staged and run the blend's pair arithmetic
 //   k_bcombine fixed-order sum over splits, phi', the bound, kept counts
 #include "pts_device.h"
 
@@ -73,25 +88,112 @@ __device__ __forceinline__ void pair(float qx, float qy, float qz, float nl, flo
   td += w;
 }
 
+// One wavefront per workgroup: waves sweep, vote and stage independently (a
+// wave never waits on units only another wave keeps).
+constexpr int kBW = 64;
+
+// Unit nearest (by sphere lower bound) to (rx, ry, rz) among units [u0, u1);
+// ties to the lower index.  Wave-wide.
+__device__ int64_t nearest_unit(const float4* __restrict__ ub, int64_t u0, int64_t u1, float rx, float ry, float rz,
+                                float* red_v, int32_t* red_i) {
+  float best = 3.0e38f;
+  int32_t bi = int32_t(u0);
+  for (int64_t u = u0 + threadIdx.x; u < u1; u += kBW) {
+    const float4 cb = ub[2 * u];
+    const float ex = rx - cb.x, ey = ry - cb.y, ez = rz - cb.z;
+    const float lb = sqrtf(fmaf(ez, ez, fmaf(ey, ey, ex * ex))) - cb.w;
+    if (lb < best) { best = lb; bi = int32_t(u); }
+  }
+  __syncthreads();
+  red_v[threadIdx.x] = best;
+  red_i[threadIdx.x] = bi;
+  __syncthreads();
+  for (int o = kBW / 2; o > 0; o >>= 1) {
+    if (int(threadIdx.x) < o) {
+      const float v2 = red_v[threadIdx.x + o];
+      const int32_t i2 = red_i[threadIdx.x + o];
+      if (v2 < red_v[threadIdx.x] || (v2 == red_v[threadIdx.x] && i2 < red_i[threadIdx.x])) {
+        red_v[threadIdx.x] = v2;
+        red_i[threadIdx.x] = i2;
+      }
+    }
+    __syncthreads();
+  }
+  return red_i[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_bwork(const Header* __restrict__ h, const float4* __restrict__ ub,
+                                                  const float* __restrict__ x, const int32_t* __restrict__ order,
+                                                  int64_t Q, int64_t nqb, int qpl, const float* __restrict__ far2,
+                                                  float C, uint32_t* __restrict__ key, int32_t* __restrict__ idx) {
+  const int64_t b = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (b >= nqb) return;
+  const int64_t q = order[b * kBW * qpl];
+  const QueryIn r = load_query(x, q, Q, h);
+  const float M = sqrtf(fmaxf(far2[q], 0.f));
+  const int64_t nunit = (h->N + kUnit - 1) / kUnit;
+  float lo = 3.0e38f;
+  for (int64_t u = 0; u < nunit; ++u) {
+    const float4 cb = ub[2 * u];
+    const float ex = r.x - cb.x, ey = r.y - cb.y, ez = r.z - cb.z;
+    lo = fminf(lo, sqrtf(fmaf(ez, ez, fmaf(ey, ey, ex * ex))) - cb.w);
+  }
+  const float cut = lo + 25.f * M / (2.f * C);
+  uint32_t cnt = 0;
+  for (int64_t u = 0; u < nunit; ++u) {
+    const float4 cb = ub[2 * u];
+    const float ex = r.x - cb.x, ey = r.y - cb.y, ez = r.z - cb.z;
+    cnt += (sqrtf(fmaf(ez, ez, fmaf(ey, ey, ex * ex))) - cb.w <= cut) ? 1u : 0u;
+  }
+  key[b] = 0xffffffu - (cnt < 0xffffffu ? cnt : 0xffffffu);   // ascending sort = heaviest first
+  idx[b] = int32_t(b);
+}
+
+// The wave's vote on skipping n points inside the sphere sb = (c, r): true
+// (and the skipped bounds added) if every live query's budget allows it.
 template <int QPL>
-__global__ __launch_bounds__(kBlock) void k_bounded(const Header* __restrict__ h, const float4* __restrict__ rec,
-                                                    const float4* __restrict__ ub, const float* __restrict__ x,
-                                                    const int32_t* __restrict__ order, int64_t Q, int S,
-                                                    int64_t per_split, const float* __restrict__ far2, float C2,
-                                                    float eps, float4* __restrict__ part,
-                                                    int32_t* __restrict__ kpart) {
-  __shared__ float4 tile[kTile2 * kRecF4];
-  __shared__ float red_v[kBlock];
-  __shared__ int32_t red_i[kBlock];
-  __shared__ float4 ref;
-  __shared__ int vote[2][kBlock / 64];
+__device__ __forceinline__ bool vote(const float4& sb, float n, const float* qx, const float* qy, const float* qz,
+                                     const float* nl, float C2, float A, const float* phimax, float* gs, float* ds,
+                                     const float* den, const float* wseed, float eps, const bool* live) {
+  float du[QPL], gu[QPL];
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) {
+    const float ex = qx[k] - sb.x, ey = qy[k] - sb.y, ez = qz[k] - sb.z;
+    const float s = hw_sqrt(fmaf(ez, ez, fmaf(ey, ey, ex * ex)));
+    const float dmin = fmaxf(s * (1.f - kSlack) - sb.w * (1.f + kSlack), 0.f);
+    du[k] = n * hw_exp2(fmaf(dmin, nl[k], C2)) * (1.f + kSlack);
+    gu[k] = du[k] * (s + sb.w + A) * (1.f + kSlack);
+    const bool skip = (gs[k] + gu[k]) + phimax[k] * (ds[k] + du[k]) <= eps * (den[k] * (1.f - kSlack) + wseed[k]);
+    ok = ok && (skip || !live[k]);
+  }
+  if (__ballot(!ok) != 0ull) return false;
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) {
+    gs[k] += gu[k];
+    ds[k] += du[k];
+  }
+  return true;
+}
+
+template <int QPL>
+__global__ __launch_bounds__(kBW) void k_bounded(const Header* __restrict__ h, const float4* __restrict__ rec,
+                                                 const float4* __restrict__ ub, const float4* __restrict__ bb,
+                                                 const float* __restrict__ x,
+                                                 const int32_t* __restrict__ order, const int32_t* __restrict__ border,
+                                                 int64_t Q, int S, int64_t per_split,
+                                                 const float* __restrict__ far2, float C2, float eps_total,
+                                                 float4* __restrict__ part, int32_t* __restrict__ kpart) {
+  __shared__ float4 tile[kUnit * kRecF4];
+  __shared__ float red_v[kBW];
+  __shared__ int32_t red_i[kBW];
   const int split = int(blockIdx.x % unsigned(S));
-  const int64_t qb = blockIdx.x / unsigned(S);
+  const int64_t qb = border[blockIdx.x / unsigned(S)];
   const int64_t N = h->N;
   const int64_t nd = h->n_direct;
   const float A = __uint_as_float(h->a00max_bits);
-  const int64_t j0 = qb * (kBlock * QPL);          // first sorted position of the block
-  float qx[QPL], qy[QPL], qz[QPL], nl[QPL], phimax[QPL], num[QPL], den[QPL], gs[QPL], ds[QPL];
+  const int64_t j0 = qb * (kBW * QPL);          // first sorted position of the wave
+  float qx[QPL], qy[QPL], qz[QPL], nl[QPL], phimax[QPL], num[QPL], den[QPL], gs[QPL], ds[QPL], wseed[QPL];
   bool live[QPL];
 #pragma unroll
   for (int k = 0; k < QPL; ++k) {
@@ -104,106 +206,74 @@ __global__ __launch_bounds__(kBlock) void k_bounded(const Header* __restrict__ h
     nl[k] = 0.f;
     if (qi.valid) far_of(far2, 1, Q, q, C2, M, nl[k]);
     phimax[k] = M + A;
-    num[k] = den[k] = gs[k] = ds[k] = 0.f;
+    num[k] = den[k] = gs[k] = ds[k] = wseed[k] = 0.f;
   }
   const int64_t beg = int64_t(split) * per_split;
   const int64_t end = min(N, beg + per_split);
-  const int64_t ntile = (end - beg + kTile2 - 1) / kTile2;
-  // seed: the tile holding the unit nearest (by sphere lower bound) to the block's first query
-  if (threadIdx.x == 0) {
-    const QueryIn r = load_query(x, order[j0], Q, h);
-    ref = make_float4(r.x, r.y, r.z, 0.f);
-  }
-  __syncthreads();
   const int64_t u_beg = beg / kUnit, u_end = (end + kUnit - 1) / kUnit;
-  float best = 3.0e38f;
-  int32_t bi = int32_t(u_beg);
-  for (int64_t u = u_beg + threadIdx.x; u < u_end; u += kBlock) {
-    const float4 cb = ub[2 * u];
-    const float ex = ref.x - cb.x, ey = ref.y - cb.y, ez = ref.z - cb.z;
-    const float lb = sqrtf(fmaf(ez, ez, fmaf(ey, ey, ex * ex))) - cb.w;
-    if (lb < best) { best = lb; bi = int32_t(u); }
-  }
-  red_v[threadIdx.x] = best;
-  red_i[threadIdx.x] = bi;
-  __syncthreads();
-  for (int o = kBlock / 2; o > 0; o >>= 1) {
-    if (int(threadIdx.x) < o) {
-      const float v2 = red_v[threadIdx.x + o];
-      const int32_t i2 = red_i[threadIdx.x + o];
-      if (v2 < red_v[threadIdx.x] || (v2 == red_v[threadIdx.x] && i2 < red_i[threadIdx.x])) {
-        red_v[threadIdx.x] = v2;
-        red_i[threadIdx.x] = i2;
-      }
-    }
-    __syncthreads();
-  }
-  const int64_t t_seed = (int64_t(red_i[0]) * kUnit - beg) / kTile2;
-  const int wave = int(threadIdx.x >> 6);
-  int32_t kept = 0;
-  for (int64_t it = 0; it < ntile; ++it) {
-    int64_t tix = t_seed + it;
-    if (tix >= ntile) tix -= ntile;
-    const int64_t t0 = beg + tix * kTile2;
-    const int cnt = int(min<int64_t>(kTile2, end - t0));
-    // votes, against the kept denominator at the start of the tile (a lower
-    // bound of it at any later point): one per unit, wave-wide
-    int need = 0;
-    for (int ju = 0, ui = 0; ju < cnt; ju += kUnit, ++ui) {
-      const int je = min(cnt, ju + kUnit);
-      const float4 cb = ub[2 * ((t0 + ju) / kUnit)];
-      float du[QPL], gu[QPL];
-      bool ok = true;
+  const float eps = S > 1 ? eps_total / float(S + 1) : eps_total;
+  // the wave's first query, in record coordinates
+  const QueryIn r0 = load_query(x, order[j0], Q, h);
+  const int64_t useed = nearest_unit(ub, 0, (N + kUnit - 1) / kUnit, r0.x, r0.y, r0.z, red_v, red_i);
+  int64_t ustart = useed;
+  if (useed < u_beg || useed >= u_end) {
+    // W_seed per query (the range holding the seed keeps it), then this range's own nearest unit
+    const int64_t s0 = useed * kUnit, s1 = min(N, s0 + kUnit);
+    for (int64_t sl = s0; sl < s1; ++sl) {
+      const float4 P = rec[sl * kRecF4];
 #pragma unroll
       for (int k = 0; k < QPL; ++k) {
-        const float ex = qx[k] - cb.x, ey = qy[k] - cb.y, ez = qz[k] - cb.z;
-        const float s = sqrtf(fmaf(ez, ez, fmaf(ey, ey, ex * ex)));
-        const float dmin = fmaxf(s * (1.f - kSlack) - cb.w * (1.f + kSlack), 0.f);
-        du[k] = float(je - ju) * exp2f(fmaf(dmin, nl[k], C2)) * (1.f + kSlack);
-        gu[k] = du[k] * (s + cb.w + A) * (1.f + kSlack);
-        const bool skip = (gs[k] + gu[k]) + phimax[k] * (ds[k] + du[k]) <= eps * den[k] * (1.f - kSlack);
-        ok = ok && (skip || !live[k]);
-      }
-      if (__ballot(!ok) == 0ull) {
-#pragma unroll
-        for (int k = 0; k < QPL; ++k) {
-          gs[k] += gu[k];
-          ds[k] += du[k];
-        }
-      } else {
-        need |= 1 << ui;
+        const float dx = qx[k] - P.x, dy = qy[k] - P.y, dz = qz[k] - P.z;
+        const float d = hw_sqrt(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+        wseed[k] += hw_exp2(fmaf(d, nl[k], C2));
       }
     }
-    if ((threadIdx.x & 63) == 0) vote[it & 1][wave] = need;
-    __syncthreads();
-    const int any = vote[it & 1][0] | vote[it & 1][1] | vote[it & 1][2] | vote[it & 1][3];
-    if (any == 0) continue;          // workgroup-uniform: every wave skips both units
-    for (int j = threadIdx.x; j < cnt * kRecF4; j += kBlock) tile[j] = rec[t0 * kRecF4 + j];
-    __syncthreads();
-    const int jd = int(max<int64_t>(0, min<int64_t>(cnt, nd - t0)));
-    float tn[QPL], td[QPL];
 #pragma unroll
-    for (int k = 0; k < QPL; ++k) { tn[k] = 0.f; td[k] = 0.f; }
-    for (int ju = 0, ui = 0; ju < cnt; ju += kUnit, ++ui) {
-      if (!(need & (1 << ui))) continue;   // wave-uniform
-      const int je = min(cnt, ju + kUnit);
-      kept += je - ju;
-      for (int j = ju; j < min(je, jd); ++j) {
+    for (int k = 0; k < QPL; ++k) wseed[k] *= (1.f - kSlack);
+    ustart = nearest_unit(ub, u_beg, u_end, r0.x, r0.y, r0.z, red_v, red_i);
+  }
+  int32_t kept = 0;
+  // blocks of kBlkU units (their bounding spheres from the build), starting at
+  // the seed's block; within that block, starting at the seed unit
+  const int64_t b_beg = u_beg / kBlkU, b_end = (u_end + kBlkU - 1) / kBlkU, nbk = b_end - b_beg;
+  const int64_t bstart = ustart / kBlkU;
+  for (int64_t ib = 0; ib < nbk; ++ib) {
+    int64_t b = bstart + ib;
+    if (b >= b_end) b -= nbk;
+    const int64_t bu0 = max(b * kBlkU, u_beg), bu1 = min(b * kBlkU + kBlkU, u_end);
+    if (ib > 0 && vote<QPL>(bb[b], float(min(end, bu1 * kUnit) - bu0 * kUnit), qx, qy, qz, nl, C2, A, phimax, gs, ds, den,
+                       wseed, eps, live)) continue;
+    const int64_t nub = bu1 - bu0;
+    const int64_t us = ib == 0 ? ustart : bu0;
+    for (int64_t iu = 0; iu < nub; ++iu) {
+      int64_t u = us + iu;
+      if (u >= bu1) u -= nub;
+      const int64_t t0 = u * kUnit;
+      const int cnt = int(min<int64_t>(kUnit, end - t0));
+      if (vote<QPL>(ub[2 * u], float(cnt), qx, qy, qz, nl, C2, A, phimax, gs, ds, den, wseed, eps, live)) continue;
+      kept += cnt;
+      __syncthreads();                 // the previous unit is read
+      for (int j = threadIdx.x; j < cnt * kRecF4; j += kBW) tile[j] = rec[t0 * kRecF4 + j];
+      __syncthreads();
+      const int jd = int(max<int64_t>(0, min<int64_t>(cnt, nd - t0)));
+      float tn[QPL], td[QPL];
+#pragma unroll
+      for (int k = 0; k < QPL; ++k) { tn[k] = 0.f; td[k] = 0.f; }
+      for (int j = 0; j < jd; ++j) {
         const float4 P = tile[j * kRecF4 + 0], U = tile[j * kRecF4 + 1], Mv = tile[j * kRecF4 + 2],
                      K = tile[j * kRecF4 + 3], G = tile[j * kRecF4 + 4];
 #pragma unroll
         for (int k = 0; k < QPL; ++k) pair<true>(qx[k], qy[k], qz[k], nl[k], C2, P, U, Mv, K, G, tn[k], td[k]);
       }
-      for (int j = max(ju, jd); j < je; ++j) {
+      for (int j = jd; j < cnt; ++j) {
         const float4 P = tile[j * kRecF4 + 0], U = tile[j * kRecF4 + 1], Mv = tile[j * kRecF4 + 2],
                      K = tile[j * kRecF4 + 3], G = tile[j * kRecF4 + 4];
 #pragma unroll
         for (int k = 0; k < QPL; ++k) pair<false>(qx[k], qy[k], qz[k], nl[k], C2, P, U, Mv, K, G, tn[k], td[k]);
       }
-    }
 #pragma unroll
-    for (int k = 0; k < QPL; ++k) { num[k] += tn[k]; den[k] += td[k]; }
-    __syncthreads();                 // the tile is read; the next staging may overwrite it
+      for (int k = 0; k < QPL; ++k) { num[k] += tn[k]; den[k] += td[k]; }
+    }
   }
 #pragma unroll
   for (int k = 0; k < QPL; ++k) {
@@ -240,11 +310,11 @@ __global__ __launch_bounds__(kBlock) void k_bcombine(const float4* __restrict__ 
 }
 
 template <int QPL>
-void launch_bounded_q(const Header* h, const float4* rec, const float4* ub, const float* x, const int32_t* order,
-                      int64_t Q, const Plan& plan, const float* far2, float C2, float eps, float4* part,
-                      int32_t* kpart, hipStream_t st) {
-  hipLaunchKernelGGL(k_bounded<QPL>, dim3(unsigned(plan.nqb * plan.S)), dim3(kBlock), 0, st, h, rec, ub, x, order,
-                     Q, plan.S, plan.per_split, far2, C2, eps, part, kpart);
+void launch_bounded_q(const Header* h, const float4* rec, const float4* ub, const float4* bb, const float* x,
+                      const int32_t* order, const int32_t* border, int64_t Q, const Plan& plan, const float* far2,
+                      float C2, float eps, float4* part, int32_t* kpart, hipStream_t st) {
+  hipLaunchKernelGGL(k_bounded<QPL>, dim3(unsigned(plan.nqb * plan.S)), dim3(kBW), 0, st, h, rec, ub, bb, x, order,
+                     border, Q, plan.S, plan.per_split, far2, C2, eps, part, kpart);
 }
 
 // Workspace: far2 [Q], partials float4 [S][Q], kept int32 [S][Q], keys and
@@ -256,8 +326,29 @@ struct BoundedWs {
   uint32_t* key[2];
   int32_t* idx[2];
   int32_t* rhist;
+  uint32_t* bkey[2];
+  int32_t* bidx[2];
   size_t bytes;
 };
+
+}  // namespace
+
+// The bounded path's plan: QPL = 2 queries per lane, one wavefront per
+// workgroup, one point range per query block unless that leaves fewer than
+// 8192 workgroups, then up to 64 ranges (multiples of a 64-point unit, at
+// least 512 points each).
+Plan bounded_plan(int64_t N, int64_t Q) {
+  Plan p;
+  p.qpl = 1;
+  p.nqb = (Q + int64_t(kBW) * p.qpl - 1) / (int64_t(kBW) * p.qpl);
+  int S = 1;
+  while (S < 64 && p.nqb * S < 8192 && (N + 2 * S - 1) / (2 * S) >= 512) S *= 2;
+  p.per_split = ((N + S - 1) / S + kUnit - 1) / kUnit * kUnit;
+  p.S = int((N + p.per_split - 1) / p.per_split);
+  return p;
+}
+
+namespace {
 
 BoundedWs bounded_ws(const Plan& plan, int64_t Q, void* ws) {
   char* c = static_cast<char*>(ws);
@@ -274,6 +365,8 @@ BoundedWs bounded_ws(const Plan& plan, int64_t Q, void* ws) {
   for (int i = 0; i < 2; ++i) v.key[i] = reinterpret_cast<uint32_t*>(take(size_t(Q) * 4));
   for (int i = 0; i < 2; ++i) v.idx[i] = reinterpret_cast<int32_t*>(take(size_t(Q) * 4));
   v.rhist = reinterpret_cast<int32_t*>(take(size_t((Q + kBlock - 1) / kBlock) * 16 * 4));
+  for (int i = 0; i < 2; ++i) v.bkey[i] = reinterpret_cast<uint32_t*>(take(size_t(plan.nqb) * 4));
+  for (int i = 0; i < 2; ++i) v.bidx[i] = reinterpret_cast<int32_t*>(take(size_t(plan.nqb) * 4));
   v.bytes = o;
   return v;
 }
@@ -289,6 +382,7 @@ int launch_bounded(const void* rec, int64_t N, const float* x, int64_t Q, float 
   const Header* h = reinterpret_cast<const Header*>(base);
   const float4* recs = reinterpret_cast<const float4*>(base + L.rec);
   const float4* ub = reinterpret_cast<const float4*>(base + L.ub);
+  const float4* bb = reinterpret_cast<const float4*>(base + L.bb);
   BoundedWs v = bounded_ws(plan, Q, ws);
   const unsigned qblocks = unsigned((Q + kBlock - 1) / kBlock);
   hipLaunchKernelGGL(k_qkeys, dim3(qblocks), dim3(kBlock), 0, st, h, x, Q, v.key[0], v.idx[0]);
@@ -296,13 +390,17 @@ int launch_bounded(const void* rec, int64_t N, const float* x, int64_t Q, float 
   if (int rc = launch_radix_sort(v.key, v.idx, Q, 6, v.rhist, st, &cur)) return rc;
   const int32_t* order = v.idx[cur];
   if (int rc = launch_far_cull(rec, N, x, Q, plan.qpl, v.far2, nullptr, st)) return rc;
+  // heavy query blocks first
+  hipLaunchKernelGGL(k_bwork, dim3(unsigned((plan.nqb + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, h, ub, x, order,
+                     Q, plan.nqb, plan.qpl, v.far2, C, v.bkey[0], v.bidx[0]);
+  int bcur = 0;
+  if (int rc = launch_radix_sort(v.bkey, v.bidx, plan.nqb, 6, v.rhist, st, &bcur)) return rc;
+  const int32_t* border = v.bidx[bcur];
   const float C2 = C * kLog2e;
   switch (plan.qpl) {
-    case 1: launch_bounded_q<1>(h, recs, ub, x, order, Q, plan, v.far2, C2, eps, v.part, v.kpart, st); break;
-    case 2: launch_bounded_q<2>(h, recs, ub, x, order, Q, plan, v.far2, C2, eps, v.part, v.kpart, st); break;
-    default:
-      launch_bounded_q<4>(h, recs, ub, x, order, Q, with_qpl(plan, 4, Q), v.far2, C2, eps, v.part, v.kpart, st);
-      break;
+    case 1: launch_bounded_q<1>(h, recs, ub, bb, x, order, border, Q, plan, v.far2, C2, eps, v.part, v.kpart, st); break;
+    case 2: launch_bounded_q<2>(h, recs, ub, bb, x, order, border, Q, plan, v.far2, C2, eps, v.part, v.kpart, st); break;
+    default: launch_bounded_q<4>(h, recs, ub, bb, x, order, border, Q, plan, v.far2, C2, eps, v.part, v.kpart, st); break;
   }
   hipLaunchKernelGGL(k_bcombine, dim3(qblocks), dim3(kBlock), 0, st, v.part, v.kpart, order, plan.S, Q, sdf, bound,
                      kept);

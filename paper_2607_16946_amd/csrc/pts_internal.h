@@ -140,6 +140,7 @@ int launch_radix_sort(uint32_t* key[2], int32_t* idx[2], int64_t n, int passes, 
 
 // Error-bounded evaluation (pts_bounded.hip): the blend with point units
 // skipped while a proven bound on the change of phi stays within eps.
+Plan bounded_plan(int64_t N, int64_t Q);
 size_t bounded_ws_bytes(const Plan& plan, int64_t Q);
 int launch_bounded(const void* rec, int64_t N, const float* x, int64_t Q, float eps, float C, const Plan& plan,
                    void* ws, float* sdf, float* bound, int32_t* kept, hipStream_t st);
