@@ -79,7 +79,13 @@ typedef struct pts_params {
   int splits;        /* 0 = automatic.  Otherwise the number of point ranges a
                         query's sum is split over (power of two, <= 64); results
                         depend on it only through FP32 rounding order. */
-  int reserved;
+  float offset;      /* default 0.  pts_eval, pts_eval_bounded and pts_eval_baseline
+                        return phi - offset, the signed distance to the offset
+                        surface phi = offset (Sec. 5.2, "Offset surfaces and
+                        Booleans"), and pts_trace marches on it; gradients,
+                        statistics and backward passes are those of phi itself.
+                        Must be finite.  0 leaves every result bitwise unchanged.
+                        pts_eval_radius and the server do not take it. */
 } pts_params;
 
 /* ---------------------------------------------------------------------------
@@ -235,6 +241,24 @@ int pts_laplacian_ws_bytes(int64_t N, int64_t Q, const pts_params* prm, size_t* 
  * ws_bytes >= pts_laplacian_ws_bytes(N, Q, prm). */
 int pts_laplacian(const void* rec, int64_t N, const float* x, int64_t Q, const float* stats, float* lap,
                   float* grad, float* eik, const pts_params* prm, void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Offsets and Booleans of signed distances (Sec. 5.2, "Offset surfaces and
+ * Booleans"): elementwise on values already evaluated, e.g. two clouds' phi
+ * at the same queries.
+ * ------------------------------------------------------------------------- */
+
+#define PTS_OP_OFFSET 0    /* out = a - c            (offset surface a = c) */
+#define PTS_OP_UNION 1     /* out = min(a, b)                                 */
+#define PTS_OP_INTERSECT 2 /* out = max(a, b)                                 */
+#define PTS_OP_SUBTRACT 3  /* out = max(a, -b)        (a minus b)             */
+
+/* out [n] = op(a, b) on device float32 arrays (b unused, may be NULL, for
+ * PTS_OP_OFFSET; c used only there).  A NaN in an operand gives NaN.  The
+ * results are exact signed distances where the operands are, up to the usual
+ * caveat of min/max compositions (exact outside the union and inside the
+ * intersection; a bound elsewhere).  out may alias a or b. */
+int pts_compose(const float* a, const float* b, int64_t n, int op, float c, float* out, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Baselines of the accuracy comparison (Sec. 5.2, "Signed distance accuracy"),

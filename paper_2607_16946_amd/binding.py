@@ -35,7 +35,7 @@ class PtsError(RuntimeError):
 
 class Params(ctypes.Structure):
     _fields_ = [("C", ctypes.c_float), ("kfloor_rel", ctypes.c_float), ("splits", ctypes.c_int),
-                ("reserved", ctypes.c_int)]
+                ("offset", ctypes.c_float)]
 
 
 class CloudInfo(ctypes.Structure):
@@ -99,6 +99,7 @@ SIGNATURES = {
     "pts_eval_bounded_ws_bytes": (ctypes.c_int, [_I64, _I64, ctypes.POINTER(Params), ctypes.POINTER(_SZ)]),
     "pts_eval_bounded": (ctypes.c_int, [_P, _I64, _P, _I64, ctypes.c_float, _P, _P, _P, ctypes.POINTER(Params), _P,
                                         _SZ, _P]),
+    "pts_compose": (ctypes.c_int, [_P, _P, _I64, ctypes.c_int, ctypes.c_float, _P, _P]),
     "pts_set_areas": (ctypes.c_int, [_P, _I64, _P, _P]),
     "pts_eval_baseline": (ctypes.c_int, [_P, _I64, _P, _I64, ctypes.c_int, _P, ctypes.POINTER(Params), _P, _SZ,
                                          _P]),
@@ -173,8 +174,9 @@ def _dev(t: torch.Tensor, name: str, cols: int | None = None, dtype=torch.float3
     return t
 
 
-def make_params(C: float = 64.0, kfloor_rel: float = 1e-6, splits: int = 0) -> Params:
-    return Params(float(C), float(kfloor_rel), int(splits), 0)
+def make_params(C: float = 64.0, kfloor_rel: float = 1e-6, splits: int = 0, offset: float = 0.0) -> Params:
+    """pts_params; offset: evaluators return phi - offset and tracing follows the offset surface."""
+    return Params(float(C), float(kfloor_rel), int(splits), float(offset))
 
 
 # ---------------------------------------------------------------------------
@@ -291,6 +293,25 @@ def eval_bounded(rec: torch.Tensor, N: int, x: torch.Tensor, eps: float, params:
         _check(lib().pts_eval_bounded(_ptr(rec), int(N), _ptr(x), Q, float(eps), _ptr(sdf), _ptr(bd), _ptr(kp),
                                       ctypes.byref(prm), _ptr(ws), ws.numel(), _stream()))
     return (sdf, bd, kp) if (bound or kept) else sdf
+
+
+COMPOSE_OPS = {"offset": 0, "union": 1, "intersect": 2, "subtract": 3}
+
+
+def compose(a: torch.Tensor, b: torch.Tensor | None, op: str, c: float = 0.0,
+            out: torch.Tensor | None = None) -> torch.Tensor:
+    """Offsets and Booleans of signed distances, elementwise: a - c, min(a, b), max(a, b), max(a, -b)."""
+    _dev(a, "a")
+    n = a.numel()
+    if op != "offset":
+        if b is None:
+            raise ValueError(f"{op} needs two operands")
+        _dev(b, "b")
+        if b.numel() != n:
+            raise ValueError("operands must have the same length")
+    res = out if out is not None else torch.empty_like(a)
+    _check(lib().pts_compose(_ptr(a), _ptr(b), n, COMPOSE_OPS[op], float(c), _ptr(res), _stream()))
+    return res
 
 
 BASELINES = {"sspd": 0, "shc": 1}

@@ -19,11 +19,12 @@ pts_params resolve(const pts_params* prm) {
   r.C = 64.0f;
   r.kfloor_rel = 1e-6f;
   r.splits = 0;
-  r.reserved = 0;
+  r.offset = 0.0f;
   if (prm) {
     if (prm->C != 0.0f) r.C = prm->C;
     if (prm->kfloor_rel != 0.0f) r.kfloor_rel = prm->kfloor_rel;
     r.splits = prm->splits;
+    r.offset = prm->offset;
   }
   return r;
 }
@@ -33,6 +34,7 @@ int check_params(const pts_params& p) {
   if (!(p.kfloor_rel > 0.0f && std::isfinite(p.kfloor_rel))) return fail(PTS_EINVAL, "kfloor_rel must be > 0");
   if (p.splits < 0 || p.splits > 64 || (p.splits & (p.splits - 1)) != 0)
     return fail(PTS_EINVAL, "splits must be 0 or a power of two <= 64");
+  if (!std::isfinite(p.offset)) return fail(PTS_EINVAL, "offset must be finite");
   return PTS_OK;
 }
 }  // namespace
@@ -229,12 +231,12 @@ int pts_eval(const void* rec, int64_t N, const float* x, int64_t Q, float* sdf, 
   if (!grad && !stats) {
     if (int rc = launch_far(rec, N, x, Q, plan, v, st)) return rc;
     if (int rc = launch_blend(rec, N, x, Q, P.C, plan, v, st)) return rc;
-    return launch_combine(Q, plan, v, sdf, st);
+    return launch_combine(Q, plan, v, sdf, st, P.offset);
   }
   float* st6 = stats ? stats : v.stats;
   if (int rc = launch_far_arg(rec, N, x, Q, plan, v, st)) return rc;
   if (int rc = launch_blend(rec, N, x, Q, P.C, plan, v, st)) return rc;
-  if (int rc = launch_combine_stats(rec, N, x, Q, plan, v, sdf, st6, st)) return rc;
+  if (int rc = launch_combine_stats(rec, N, x, Q, plan, v, sdf, st6, st, P.offset)) return rc;
   if (grad) return launch_grad(rec, N, x, Q, st6, nullptr, grad, P.C, plan, v, st);
   return PTS_OK;
 }
@@ -266,7 +268,7 @@ int pts_eval_combine(int64_t N, int64_t Q, float* sdf, const pts_params* prm, vo
   if (int rc = eval_checks(N, Q, prm, ws_bytes, false, &plan, &P)) return rc;
   if (Q == 0) return PTS_OK;
   if (!sdf || !ws) return fail(PTS_EINVAL, "null pointer");
-  return launch_combine(Q, plan, ws_view(plan, Q, ws), sdf, static_cast<hipStream_t>(stream));
+  return launch_combine(Q, plan, ws_view(plan, Q, ws), sdf, static_cast<hipStream_t>(stream), P.offset);
 }
 
 int pts_eval_bounded_ws_bytes(int64_t N, int64_t Q, const pts_params* prm, size_t* out_bytes) {
@@ -289,7 +291,8 @@ int pts_eval_bounded(const void* rec, int64_t N, const float* x, int64_t Q, floa
   if (!rec || !x || !sdf || !ws) return fail(PTS_EINVAL, "null pointer");
   const Plan plan = bounded_plan(N, Q);
   if (ws_bytes < bounded_ws_bytes(plan, Q)) return fail(PTS_EINVAL, "workspace too small");
-  return launch_bounded(rec, N, x, Q, eps, P.C, plan, ws, sdf, bound, kept, static_cast<hipStream_t>(stream));
+  return launch_bounded(rec, N, x, Q, eps, P.C, plan, ws, sdf, bound, kept, static_cast<hipStream_t>(stream),
+                        P.offset);
 }
 
 int pts_set_areas(void* rec, int64_t N, const float* area, void* stream) {
@@ -307,7 +310,16 @@ int pts_eval_baseline(const void* rec, int64_t N, const float* x, int64_t Q, int
   if (Q == 0) return PTS_OK;
   if (!rec || !x || !sdf || !ws) return fail(PTS_EINVAL, "null pointer");
   return launch_baseline(rec, N, x, Q, kind, P.C, plan, ws_view(plan, Q, ws), sdf,
-                         static_cast<hipStream_t>(stream));
+                         static_cast<hipStream_t>(stream), P.offset);
+}
+
+int pts_compose(const float* a, const float* b, int64_t n, int op, float c, float* out, void* stream) {
+  if (n < 0) return fail(PTS_EINVAL, "n must be >= 0");
+  if (op < PTS_OP_OFFSET || op > PTS_OP_SUBTRACT) return fail(PTS_EINVAL, "unknown composition");
+  if (!std::isfinite(c)) return fail(PTS_EINVAL, "c must be finite");
+  if (n == 0) return PTS_OK;
+  if (!a || !out || (op != PTS_OP_OFFSET && !b)) return fail(PTS_EINVAL, "null pointer");
+  return launch_compose(a, b, n, op, c, out, static_cast<hipStream_t>(stream));
 }
 
 int pts_grad_x(const void* rec, int64_t N, const float* x, int64_t Q, const float* gout, const float* stats,

@@ -89,7 +89,7 @@ __global__ __launch_bounds__(kBlock) void k_base(const Header* __restrict__ h, c
 template <int KIND>
 __global__ __launch_bounds__(kBlock) void k_base_combine(const float2* __restrict__ part,
                                                          const float* __restrict__ far2, int S, int64_t Q, float C,
-                                                         float* __restrict__ sdf) {
+                                                         float* __restrict__ sdf, float offset) {
   const int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (q >= Q) return;
   float num = 0.f, den = 0.f;
@@ -99,11 +99,11 @@ __global__ __launch_bounds__(kBlock) void k_base_combine(const float2* __restric
     den += v.y;
   }
   if (KIND == PTS_BASELINE_SSPD) {
-    sdf[q] = num / den;
+    sdf[q] = num / den - offset;
   } else {
     const float M = sqrtf(fmaxf(far2[q], 0.f));
     const float sg = num < 0.f ? -1.f : 1.f;
-    sdf[q] = sg * (-logf(fabsf(num)) * M / (2.f * C) + 0.5f * M);
+    sdf[q] = sg * (-logf(fabsf(num)) * M / (2.f * C) + 0.5f * M) - offset;
   }
 }
 
@@ -123,14 +123,14 @@ void launch_base_q(const Header* h, const float4* bas, const float* x, int64_t Q
 
 template <int KIND>
 void launch_base_kind(const Header* h, const float4* bas, const float* x, int64_t Q, const Plan& plan,
-                      const float* far2, float C, float2* part, float* sdf, hipStream_t st) {
+                      const float* far2, float C, float2* part, float* sdf, float offset, hipStream_t st) {
   switch (plan.qpl) {
     case 1: launch_base_q<1, KIND>(h, bas, x, Q, plan, far2, C, part, st); break;
     case 2: launch_base_q<2, KIND>(h, bas, x, Q, plan, far2, C, part, st); break;
     default: launch_base_q<4, KIND>(h, bas, x, Q, with_qpl(plan, 4, Q), far2, C, part, st); break;
   }
   hipLaunchKernelGGL(k_base_combine<KIND>, dim3(unsigned((Q + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, part,
-                     far2, plan.S, Q, C, sdf);
+                     far2, plan.S, Q, C, sdf, offset);
 }
 
 }  // namespace
@@ -145,16 +145,16 @@ int launch_set_areas(void* rec, int64_t N, const float* area, hipStream_t st) {
 }
 
 int launch_baseline(const void* rec, int64_t N, const float* x, int64_t Q, int kind, float C, const Plan& plan,
-                    const WsView& ws, float* sdf, hipStream_t st) {
+                    const WsView& ws, float* sdf, hipStream_t st, float offset) {
   const Layout L(N);
   const char* base = static_cast<const char*>(rec);
   const Header* h = reinterpret_cast<const Header*>(base);
   const float4* bas = reinterpret_cast<const float4*>(base + L.base);
   if (int rc = launch_far_cull(rec, N, x, Q, plan.qpl, ws.far2, nullptr, st)) return rc;
   if (kind == PTS_BASELINE_SSPD)
-    launch_base_kind<PTS_BASELINE_SSPD>(h, bas, x, Q, plan, ws.far2, C, ws.part, sdf, st);
+    launch_base_kind<PTS_BASELINE_SSPD>(h, bas, x, Q, plan, ws.far2, C, ws.part, sdf, offset, st);
   else
-    launch_base_kind<PTS_BASELINE_SHC>(h, bas, x, Q, plan, ws.far2, C, ws.part, sdf, st);
+    launch_base_kind<PTS_BASELINE_SHC>(h, bas, x, Q, plan, ws.far2, C, ws.part, sdf, offset, st);
   return check_hip(hipGetLastError(), "baseline kernels");
 }
 

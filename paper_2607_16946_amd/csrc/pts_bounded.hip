@@ -289,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void k_bcombine(const float4* __restrict__ 
                                                      const int32_t* __restrict__ kpart,
                                                      const int32_t* __restrict__ order, int S, int64_t Q,
                                                      float* __restrict__ sdf, float* __restrict__ bound,
-                                                     int32_t* __restrict__ kept) {
+                                                     int32_t* __restrict__ kept, float offset) {
   const int64_t j = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (j >= Q) return;
   float num = 0.f, den = 0.f, gs = 0.f, ds = 0.f;
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(kBlock) void k_bcombine(const float4* __restrict__ 
   }
   const int64_t q = order[j];
   const float phi = num / den;
-  sdf[q] = phi;
+  sdf[q] = phi - offset;
   if (bound) bound[q] = (gs + fabsf(phi) * ds) / den;
   if (kept) kept[q] = kc;
 }
@@ -376,7 +376,7 @@ BoundedWs bounded_ws(const Plan& plan, int64_t Q, void* ws) {
 size_t bounded_ws_bytes(const Plan& plan, int64_t Q) { return bounded_ws(plan, Q, nullptr).bytes; }
 
 int launch_bounded(const void* rec, int64_t N, const float* x, int64_t Q, float eps, float C, const Plan& plan,
-                   void* ws, float* sdf, float* bound, int32_t* kept, hipStream_t st) {
+                   void* ws, float* sdf, float* bound, int32_t* kept, hipStream_t st, float offset) {
   const Layout L(N);
   const char* base = static_cast<const char*>(rec);
   const Header* h = reinterpret_cast<const Header*>(base);
@@ -403,7 +403,7 @@ int launch_bounded(const void* rec, int64_t N, const float* x, int64_t Q, float 
     default: launch_bounded_q<4>(h, recs, ub, bb, x, order, border, Q, plan, v.far2, C2, eps, v.part, v.kpart, st); break;
   }
   hipLaunchKernelGGL(k_bcombine, dim3(qblocks), dim3(kBlock), 0, st, v.part, v.kpart, order, plan.S, Q, sdf, bound,
-                     kept);
+                     kept, offset);
   return check_hip(hipGetLastError(), "bounded evaluation kernels");
 }
 

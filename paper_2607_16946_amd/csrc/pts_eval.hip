@@ -244,7 +244,7 @@ __global__ __launch_bounds__(kBlock) void k_blend(const Header* __restrict__ h, 
 
 // Fixed-order combine of the split partials.
 __global__ __launch_bounds__(kBlock) void k_combine(const float2* __restrict__ part, int S, int64_t Q,
-                                                    float* __restrict__ sdf) {
+                                                    float* __restrict__ sdf, float offset) {
   const int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (q >= Q) return;
   float num = 0.f, den = 0.f;
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(kBlock) void k_combine(const float2* __restrict__ p
     num += v.x;
     den += v.y;
   }
-  sdf[q] = num / den;
+  sdf[q] = num / den - offset;
 }
 
 template <int QPL, bool kArg>
@@ -347,9 +347,9 @@ int launch_blend(const void* rec, int64_t N, const float* x, int64_t Q, float C,
   return check_hip(hipGetLastError(), "blend kernel");
 }
 
-int launch_combine(int64_t Q, const Plan& plan, const WsView& ws, float* sdf, hipStream_t st) {
+int launch_combine(int64_t Q, const Plan& plan, const WsView& ws, float* sdf, hipStream_t st, float offset) {
   hipLaunchKernelGGL(k_combine, dim3(unsigned((Q + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, ws.part, plan.S,
-                     Q, sdf);
+                     Q, sdf, offset);
   return check_hip(hipGetLastError(), "combine kernel");
 }
 

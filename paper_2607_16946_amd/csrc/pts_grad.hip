@@ -31,7 +31,8 @@ __global__ __launch_bounds__(kBlock) void k_combine_stats(const Header* __restri
                                                           const float* __restrict__ x, const float2* __restrict__ part,
                                                           const float* __restrict__ far2,
                                                           const int32_t* __restrict__ farix, int S, int64_t Q,
-                                                          float* __restrict__ sdf, float* __restrict__ stats) {
+                                                          float* __restrict__ sdf, float* __restrict__ stats,
+                                                          float offset) {
   const int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (q >= Q) return;
   float num = 0.f, den = 0.f;
@@ -43,7 +44,7 @@ __global__ __launch_bounds__(kBlock) void k_combine_stats(const Header* __restri
   const float m2 = far2[q];
   const int32_t slot = farix[q];
   const float phi = num / den;
-  if (sdf) sdf[q] = phi;
+  if (sdf) sdf[q] = phi - offset;   // the statistics keep phi itself
   const float M = sqrtf(fmaxf(m2, 0.f));
   float e[3] = {0.f, 0.f, 0.f};
   if (slot >= 0 && M > 0.f) {
@@ -204,12 +205,12 @@ int launch_far_arg(const void* rec, int64_t N, const float* x, int64_t Q, const 
 }
 
 int launch_combine_stats(const void* rec, int64_t N, const float* x, int64_t Q, const Plan& plan, const WsView& ws,
-                         float* sdf, float* stats, hipStream_t st) {
+                         float* sdf, float* stats, hipStream_t st, float offset) {
   const Layout L(N);
   const char* base = static_cast<const char*>(rec);
   hipLaunchKernelGGL(k_combine_stats, dim3(unsigned((Q + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
                      reinterpret_cast<const Header*>(base), reinterpret_cast<const float4*>(base + L.pos), x,
-                     ws.part, ws.far2, ws.farix, plan.S, Q, sdf, stats);
+                     ws.part, ws.far2, ws.farix, plan.S, Q, sdf, stats, offset);
   return check_hip(hipGetLastError(), "combine (stats) kernel");
 }
 

@@ -143,13 +143,15 @@ int launch_radix_sort(uint32_t* key[2], int32_t* idx[2], int64_t n, int passes, 
 Plan bounded_plan(int64_t N, int64_t Q);
 size_t bounded_ws_bytes(const Plan& plan, int64_t Q);
 int launch_bounded(const void* rec, int64_t N, const float* x, int64_t Q, float eps, float C, const Plan& plan,
-                   void* ws, float* sdf, float* bound, int32_t* kept, hipStream_t st);
+                   void* ws, float* sdf, float* bound, int32_t* kept, hipStream_t st, float offset = 0.f);
 
 // Baseline evaluators (pts_baseline.hip): smoothed signed planar distance and
 // signed Hopf-Cole distance over the record's base section.
 int launch_set_areas(void* rec, int64_t N, const float* area, hipStream_t st);
 int launch_baseline(const void* rec, int64_t N, const float* x, int64_t Q, int kind, float C, const Plan& plan,
-                    const WsView& ws, float* sdf, hipStream_t st);
+                    const WsView& ws, float* sdf, hipStream_t st, float offset = 0.f);
+// Elementwise compositions of signed distances (pts_compose.hip).
+int launch_compose(const float* a, const float* b, int64_t n, int op, float c, float* out, hipStream_t st);
 // Radius-limited evaluation (pts_radius.hip).
 int launch_blocks(void* rec, int64_t N, hipStream_t st);
 int launch_radius_prepare(void* rec, int64_t N, float C, hipStream_t st);
@@ -163,11 +165,12 @@ int launch_far(const void* rec, int64_t N, const float* x, int64_t Q, const Plan
                hipStream_t st);
 int launch_blend(const void* rec, int64_t N, const float* x, int64_t Q, float C, const Plan& plan,
                  const WsView& ws, hipStream_t st);
-int launch_combine(int64_t Q, const Plan& plan, const WsView& ws, float* sdf, hipStream_t st);
+// sdf = num / den - offset (the offset surface phi = offset; 0 leaves phi bitwise unchanged)
+int launch_combine(int64_t Q, const Plan& plan, const WsView& ws, float* sdf, hipStream_t st, float offset = 0.f);
 int launch_far_arg(const void* rec, int64_t N, const float* x, int64_t Q, const Plan& plan, const WsView& ws,
                    hipStream_t st);
 int launch_combine_stats(const void* rec, int64_t N, const float* x, int64_t Q, const Plan& plan,
-                         const WsView& ws, float* sdf, float* stats, hipStream_t st);
+                         const WsView& ws, float* sdf, float* stats, hipStream_t st, float offset = 0.f);
 int launch_grad(const void* rec, int64_t N, const float* x, int64_t Q, const float* stats, const float* gout,
                 float* gx, float C, const Plan& plan, const WsView& ws, hipStream_t st);
 

@@ -240,7 +240,7 @@ class Server {
     P_.C = cfg_.C > 0 ? cfg_.C : 64.0f;
     P_.kfloor_rel = cfg_.kfloor_rel > 0 ? cfg_.kfloor_rel : 1e-6f;
     P_.splits = 0;
-    P_.reserved = 0;
+    P_.offset = 0.0f;
     max_work_ = cfg_.max_batch_work;
     max_comb_ = cfg_.max_batch_work;
     if (!cfg_.mock) {

@@ -249,7 +249,7 @@ int launch_trace(const void* rec, int64_t N, const float* org, const float* dir,
     hipLaunchKernelGGL(k_positions, dim3(nblk(na)), dim3(kBlock), 0, st, act, na, org, dir, t, v.xq);
     if (int rc = launch_far(rec, N, v.xq, na, plan, wv, st)) return rc;
     if (int rc = launch_blend(rec, N, v.xq, na, P.C, plan, wv, st)) return rc;
-    if (int rc = launch_combine(na, plan, wv, v.phi, st)) return rc;
+    if (int rc = launch_combine(na, plan, wv, v.phi, st, P.offset)) return rc;
     hipLaunchKernelGGL(k_advance, dim3(nblk(na)), dim3(kBlock), 0, st, act, na, v.phi, eps, tmax, k, t, hit, nsteps,
                        v.keep);
     int64_t nn = 0;
@@ -270,7 +270,7 @@ int launch_trace(const void* rec, int64_t N, const float* org, const float* dir,
   hipLaunchKernelGGL(k_positions, dim3(nblk(nh)), dim3(kBlock), 0, st, act, nh, org, dir, t, v.xq);
   if (int rc = launch_far_arg(rec, N, v.xq, nh, plan, wv, st)) return rc;
   if (int rc = launch_blend(rec, N, v.xq, nh, P.C, plan, wv, st)) return rc;
-  if (int rc = launch_combine_stats(rec, N, v.xq, nh, plan, wv, v.phi, wv.stats, st)) return rc;
+  if (int rc = launch_combine_stats(rec, N, v.xq, nh, plan, wv, v.phi, wv.stats, st, P.offset)) return rc;
   if (int rc = launch_grad(rec, N, v.xq, nh, wv.stats, nullptr, v.g, P.C, plan, wv, st)) return rc;
   hipLaunchKernelGGL(k_normals, dim3(nblk(nh)), dim3(kBlock), 0, st, act, nh, v.g, nrm);
   return check_hip(hipGetLastError(), "trace normals");

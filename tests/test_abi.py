@@ -57,6 +57,13 @@ def test_host_side_errors(L):
     bad = binding.make_params(splits=3)
     assert L.pts_eval_ws_bytes(10, 10, ctypes.byref(bad), ctypes.byref(out)) == binding.PTS_EINVAL
     assert L.pts_cloud_build(None, None, None, 10, None, None, 0, None) == binding.PTS_EINVAL
+    # compositions: unknown op, a two-operand op without b, n < 0
+    assert L.pts_compose(None, None, 4, 9, 0.0, None, None) == binding.PTS_EINVAL
+    assert L.pts_compose(ctypes.c_void_p(16), None, 4, 1, 0.0, ctypes.c_void_p(16), None) == binding.PTS_EINVAL
+    assert L.pts_compose(None, None, 0, 1, 0.0, None, None) == binding.PTS_OK
+    # a non-finite offset is refused before any device work
+    bad = binding.make_params(offset=float("nan"))
+    assert L.pts_eval_ws_bytes(10, 10, ctypes.byref(bad), ctypes.byref(out)) == binding.PTS_EINVAL
     # the point backward needs at least one output, and its workspace covers every combination
     assert L.pts_backward_points(None, 10, None, None, None, None, 5, None, None, None, None, None,
                                  ctypes.byref(prm), None, 0, None) == binding.PTS_EINVAL
