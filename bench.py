@@ -461,6 +461,8 @@ def main():
                     help="oracle sample (queries); about 10 s on 16 host threads at the default size")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation workload")
     ap.add_argument("--no-baselines", action="store_true", help="skip the two baselines of the accuracy comparison")
+    ap.add_argument("--no-radius", action="store_true", help="skip the radius-limited evaluation")
+    ap.add_argument("--no-bounded", action="store_true", help="skip the error-bounded evaluation")
     ap.add_argument("--no-large", action="store_true", help="skip the large (2^20 x 2^20) workload")
     ap.add_argument("--large-trace", action="store_true", help="also run the 1024^2 x 64-step trace of it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -584,10 +586,12 @@ def main():
         "stages_ms": stage,
         "roofline": roofline,
     }
-    out["radius_limited"] = radius_bench("mid", cl, x)
+    if not args.no_radius:
+        out["radius_limited"] = radius_bench("mid", cl, x)
     if not args.no_baselines:
         out["baselines"] = baseline_bench(cl, x)
-    out["bounded"] = bounded_bench(cl, x)
+    if not args.no_bounded:
+        out["bounded"] = bounded_bench(cl, x)
     if not args.no_diff:
         out["diff"] = diff_bench(5)
     if not args.no_large:
