@@ -132,6 +132,53 @@ def cpu_baseline(cl, x, sample: int):
             "one_core": {"value": x1.shape[0] * cl.N / (t4 - t3), "queries": x1.shape[0], "seconds": t4 - t3}}
 
 
+def configs_bench(threads: int):
+    """Each configuration's plain evaluation on the GPU beside the FP64 oracle:
+    GPU pairs/s (HIP events, median of 5 after a warm-up), the oracle's pairs/s
+    on the timed sets (all 4096 queries of the tiny cloud, a seeded 8192-query
+    subset of the others; all host threads, then one thread on a sixteenth of
+    the set), and max |phi_gpu - phi_oracle| / D over the oracle's queries."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_2607_16946_amd import binding, synth
+    cases = [("1 tiny", lambda: synth.tiny()), ("2 mid", lambda: synth.mid()),
+             ("3 diff", lambda: synth.diff_workload()[:2]), ("5 large", lambda: synth.large())]
+    out = {}
+    for name, make in cases:
+        cl, x = make()
+        N, Q = cl.N, x.shape[0]
+        p, n, a, xd = (torch.from_numpy(v).cuda() for v in (cl.p, cl.n, cl.a, x))
+        prm = binding.make_params()
+        rec = binding.cloud_build(p, n, a, prm)
+        ws = torch.empty(max(binding.eval_ws_bytes(N, Q, prm), 256), dtype=torch.uint8, device="cuda")
+        sdf = torch.empty(Q, dtype=torch.float32, device="cuda")
+        ms = _timed(lambda: binding.eval(rec, N, xd, prm, ws=ws, out=sdf), 5)
+        phi = sdf.cpu().numpy().astype(np.float64)
+        idx = np.arange(Q) if Q <= 4096 else np.sort(np.random.default_rng(8192).choice(Q, 8192, replace=False))
+        t0 = time.perf_counter()
+        tor = oracle.fit(cl.p, cl.n, cl.a)
+        t1 = time.perf_counter()
+        ref = oracle.eval_sdf(cl.p, tor, x[idx], nthreads=threads)
+        t2 = time.perf_counter()
+        one = idx[:max(1, len(idx) // 16)]
+        oracle.eval_sdf(cl.p, tor, x[one], nthreads=1)
+        t3 = time.perf_counter()
+        D = max(oracle.bbox_diag(cl.p), 1.0)
+        err = np.abs(phi[idx] - ref)
+        out[name] = {"N": N, "Q": Q, "gpu_ms": ms, "gpu_pairs_per_s": float(N) * Q / (ms * 1e-3),
+                     "oracle_queries": int(len(idx)), "oracle_pairs_per_s": len(idx) * N / (t2 - t1),
+                     "oracle_threads": threads, "oracle_one_thread_pairs_per_s": len(one) * N / (t3 - t2),
+                     "oracle_fit_s": t1 - t0, "max_abs_err_over_D": float(err.max() / D),
+                     "p99_abs_err_over_D": float(np.quantile(err, 0.99) / D)}
+        log(f"config {name}: GPU {out[name]['gpu_pairs_per_s']:.3g} pairs/s; oracle "
+            f"{out[name]['oracle_pairs_per_s']:.3g} ({threads} threads), {out[name]['oracle_one_thread_pairs_per_s']:.3g} "
+            f"(1 thread); max |err|/D {out[name]['max_abs_err_over_D']:.2e}")
+        del rec, ws, sdf, xd, p, n, a
+        torch.cuda.empty_cache()
+    return out
+
+
 def _timed(fn, reps: int, warm: int = 1) -> float:
     """Median milliseconds of fn() over reps runs, bracketed by events on the current stream."""
     import numpy as np
@@ -453,8 +500,8 @@ def serving_bench(n_requests: int, n_warmup: int, loads, n_clouds: int = 64, bud
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--grid", type=int, default=128, help="query lattice resolution (default 128)")
     ap.add_argument("--points", type=int, default=131072)
     ap.add_argument("--cpu-sample", type=int, default=98304,
@@ -471,7 +518,7 @@ def main():
     ap.add_argument("--serving-only", action="store_true", help="only the serving-mode measurement")
     ap.add_argument("--diff-only", action="store_true", help="only the differentiation workload")
     ap.add_argument("--bounded-only", action="store_true", help="only the error-bounded evaluation")
-    ap.add_argument("--serve-requests", type=int, default=600, help="measured requests per load level")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per load level")
     ap.add_argument("--serve-warmup", type=int, default=50)
     ap.add_argument("--serve-loads", default="0.5,0.9", help="arrival rates as fractions of capacity")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -602,6 +649,7 @@ def main():
         log("bench: timing the FP64 oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(cl, x, args.cpu_sample)
         log(f"bench: oracle {out['cpu_baseline']['value']:.3g} pairs/s on {out['cpu_baseline']['cores']} threads")
+        out["configs"] = configs_bench(out["cpu_baseline"]["cores"])
     print(json.dumps(out))
 
 
