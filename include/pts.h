@@ -353,9 +353,9 @@ int pts_trace_ws_bytes(int64_t N, int64_t R, const pts_params* prm, size_t* out_
  * budget ran out), normal_out [R,3] float32 or NULL (grad phi / |grad phi| at
  * hits, 0 elsewhere).  Each step evaluates the active rays with the pts_eval
  * kernels.  The point splits depend on N only -- the march uses the largest
- * power of two <= 64 that leaves every split two 512-point tiles, the normals
- * at most 8 of them; pts_params.splits > 0 sets both -- so a ray's result does
- * not depend on the other rays.  Blocks: it reads back the active-ray count after
+ * power of two <= 16 that leaves every split two 512-point tiles
+ * (pts_params.splits > 0 sets it), the normals at most 8 of them -- so a ray's
+ * result does not depend on the other rays.  Blocks: it reads back the active-ray count after
  * every step.  phi overestimates |distance| away from the surface for finite
  * C (Sec. 6), so rays can overshoot thin features. */
 int pts_trace(const void* rec, int64_t N, const float* origin, const float* dir, int64_t R, int steps,
@@ -415,9 +415,9 @@ int pts_eval_radius(const void* rec, int64_t N, const float* x, int64_t Q, float
  *
  * A request on a cloud of N points is evaluated with the point split
  * pts_server_cloud_plan reports, a function of N only (the march split of
- * pts_trace): its results are bitwise the same alone or in any mix; query
- * results equal pts_eval called with pts_params.splits set to that split, and
- * trace results equal pts_trace with default splits (same C, kfloor_rel).
+ * pts_trace, capped at 64 splits instead of 16): its results are bitwise the
+ * same alone or in any mix, and equal pts_eval / pts_trace called with
+ * pts_params.splits set to that split (same C, kfloor_rel).
  *
  * All device memory (records, request buffers, launch descriptors) comes from
  * one allocation of hbm_budget_bytes made at creation; that is the budget

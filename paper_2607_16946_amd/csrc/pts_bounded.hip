@@ -333,7 +333,8 @@ struct BoundedWs {
 
 }  // namespace
 
-// The bounded path's plan: QPL = 2 queries per lane, one wavefront per
+// The bounded path's plan: one query per lane (a wave votes for 64 queries;
+// measured slightly faster than two per lane), one wavefront per
 // workgroup, one point range per query block unless that leaves fewer than
 // 8192 workgroups, then up to 64 ranges (multiples of a 64-point unit, at
 // least 512 points each).

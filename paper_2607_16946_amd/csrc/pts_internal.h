@@ -209,10 +209,16 @@ int launch_backward(const void* rec, int64_t N, const float* p, const float* n, 
                     const Plan& plan, void* ws, hipStream_t st);
 
 // Sphere tracing (point splits fixed by N so that rays do not affect each other).
-int march_splits(int64_t N);
-Plan march_plan(int64_t N, int64_t Q, const pts_params& P);
+// The march's split: the largest power of two <= cap leaving each split two
+// 512-point tiles.  The server uses cap 64 (many small packed requests need
+// the parallelism); pts_trace uses 16 (a large ray set sweeps fastest with few
+// long splits: 16 splits cost the 2^20-point sweep 3%, 64 cost it 10%).
+constexpr int kServerSplitCap = 64;
+constexpr int kTraceSplitCap = 16;
+int march_splits(int64_t N, int cap);
+Plan march_plan(int64_t N, int64_t Q, const pts_params& P, int cap);
 Plan normal_plan(int64_t N, int64_t Q, const pts_params& P);
-size_t trace_eval_ws_bytes(int64_t N, int64_t R, const pts_params& P);  // evaluation part of the workspace
+size_t trace_eval_ws_bytes(int64_t N, int64_t R, const pts_params& P, int cap);  // evaluation part of the workspace
 size_t trace_ws_bytes(int64_t N, int64_t R, const pts_params& P);
 int launch_trace(const void* rec, int64_t N, const float* org, const float* dir, int64_t R, int steps, float eps,
                  float tmax, float* t, float* nrm, int32_t* hit, int32_t* nsteps, const pts_params& P, void* ws,

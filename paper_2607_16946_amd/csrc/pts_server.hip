@@ -154,7 +154,7 @@ ReqLayout req_layout(int kind, int64_t n, const Plan& plan, const pts_params& P,
     L.xq = take(size_t(n) * 12);
     L.phi = take(size_t(n) * 4);
     L.g = take(size_t(n) * 12);
-    L.nws = take(trace_eval_ws_bytes(N, n, P));
+    L.nws = take(trace_eval_ws_bytes(N, n, P, kServerSplitCap));
   }
   L.total = w;
   return L;
@@ -332,7 +332,7 @@ class Server {
     auto it = clouds_.find(id);
     if (it == clouds_.end()) return fail(PTS_ENOTFOUND, "unknown cloud");
     if (N) *N = it->second.N;
-    if (splits) *splits = march_splits(it->second.N);
+    if (splits) *splits = march_splits(it->second.N, kServerSplitCap);
     return PTS_OK;
   }
 
@@ -372,7 +372,7 @@ class Server {
     q->N = c.N;
     const int64_t n = r->count;
     if (n > 0) {
-      q->plan = march_plan(c.N, n, P_);
+      q->plan = march_plan(c.N, n, P_, kServerSplitCap);
       q->nplan = normal_plan(c.N, n, P_);
       if (work_descs(n, q->plan.S) > max_work_ || comb_descs(n) > max_comb_) {
         std::lock_guard<std::mutex> lk(mu_);

@@ -205,33 +205,33 @@ int compact(const int32_t* keep, const int32_t* act_in, int64_t n, int32_t* act_
 // Point split of the march: the largest power of two <= 64 that leaves every
 // split at least two farthest-point tiles.  A function of N only, so a ray's
 // phi does not depend on which other rays are still active.
-int march_splits(int64_t N) {
+int march_splits(int64_t N, int cap) {
   const int64_t tiles = (N + kTile1 - 1) / kTile1;
   int S = 1;
-  while (S < 64 && tiles >= int64_t(4) * S) S *= 2;
+  while (S < cap && tiles >= int64_t(4) * S) S *= 2;
   return S;
 }
 
-Plan march_plan(int64_t N, int64_t Q, const pts_params& P) {
+Plan march_plan(int64_t N, int64_t Q, const pts_params& P, int cap) {
   pts_params F = P;
-  if (F.splits == 0) F.splits = march_splits(N);
+  if (F.splits == 0) F.splits = march_splits(N, cap);
   return make_plan(N, Q, &F);
 }
 
-// The normals' gradient sweep keeps at most 8 splits (its workspace grows by
-// 32 bytes per ray and split); also a function of N only.
+// The normals' gradient sweep keeps at most 8 of the march's splits (its
+// workspace grows by 32 bytes per ray and split); also a function of N only.
 Plan normal_plan(int64_t N, int64_t Q, const pts_params& P) {
   pts_params F = P;
-  if (F.splits == 0) F.splits = std::min(march_splits(N), 8);
+  F.splits = std::min(F.splits > 0 ? F.splits : march_splits(N, kServerSplitCap), 8);
   return make_plan(N, Q, &F);
 }
 
-size_t trace_eval_ws_bytes(int64_t N, int64_t R, const pts_params& P) {
-  return std::max(eval_ws_bytes(march_plan(N, R, P), R), grad_ws_bytes(normal_plan(N, R, P), R));
+size_t trace_eval_ws_bytes(int64_t N, int64_t R, const pts_params& P, int cap) {
+  return std::max(eval_ws_bytes(march_plan(N, R, P, cap), R), grad_ws_bytes(normal_plan(N, R, P), R));
 }
 
 size_t trace_ws_bytes(int64_t N, int64_t R, const pts_params& P) {
-  return trace_fixed_bytes(R) + trace_eval_ws_bytes(N, R, P);
+  return trace_fixed_bytes(R) + trace_eval_ws_bytes(N, R, P, kTraceSplitCap);
 }
 
 int launch_trace(const void* rec, int64_t N, const float* org, const float* dir, int64_t R, int steps, float eps,
@@ -244,7 +244,7 @@ int launch_trace(const void* rec, int64_t N, const float* org, const float* dir,
   int32_t* nxt = v.act1;
   int64_t na = R;
   for (int k = 0; k < steps && na > 0; ++k) {
-    const Plan plan = march_plan(N, na, P);
+    const Plan plan = march_plan(N, na, P, kTraceSplitCap);
     const WsView wv = ws_view(plan, na, v.eval);
     hipLaunchKernelGGL(k_positions, dim3(nblk(na)), dim3(kBlock), 0, st, act, na, org, dir, t, v.xq);
     if (int rc = launch_far(rec, N, v.xq, na, plan, wv, st)) return rc;

@@ -140,7 +140,7 @@ def test_server_equals_direct_calls_and_oracle():
             assert err <= TOL
             o, d = _rays(32, 20 + k)
             r = S.wait(S.submit_trace(cid, o, d, steps=24, eps=1e-4, tmax=6.0, normals=True))
-            t, hit, ns, nrm = binding.trace(c.rec, c.N, _dev(o), _dev(d), steps=24, eps=1e-4, tmax=6.0)
+            t, hit, ns, nrm = binding.trace(c.rec, c.N, _dev(o), _dev(d), steps=24, eps=1e-4, tmax=6.0, params=prm)
             assert np.array_equal(r["t"], t.cpu().numpy())
             assert np.array_equal(r["hit"], hit.cpu().numpy().astype(np.int32))
             assert np.array_equal(r["steps"], ns.cpu().numpy())
