@@ -1,0 +1,126 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times, on outputs the oracle can compute one by one.
+
+Evaluations run over every query of the workload; the oracle evaluates a
+seeded sample of them.  Backward passes run over every query with the upstream
+gradient nonzero only on a seeded sample, so the oracle's sum over that sample
+is the exact reference for the full-size launch.  Tolerances as in the
+per-feature parity tests (phi 1e-5 D; gradients 1e-4; Laplacian per query
+2e-4 max(1, |Lap|) + 4e-7 lambda / d_min).  Queries whose farthest point FP32
+cannot decide are left out of the derivative checks, as there.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2607_16946_amd import binding, synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+GTOL = 1e-4
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    binding.lib()
+
+
+def _decided(p, x):
+    d = np.linalg.norm(x.astype(np.float64)[:, None, :] - p.astype(np.float64)[None], axis=2)
+    top = np.sort(d, axis=1)[:, -2:]
+    return top[:, 1] - top[:, 0] > 1e-5 * top[:, 1]
+
+
+@pytest.fixture(scope="module")
+def diff_case():
+    cl, x, mask = synth.diff_workload()
+    c = binding.Cloud(_dev(cl.p), _dev(cl.n), _dev(cl.a))
+    xs = _dev(x)
+    phi, st = c(xs, stats=True)
+    rng = np.random.default_rng(77)
+    cand = rng.choice(x.shape[0], 1200, replace=False)
+    keep = cand[_decided(cl.p, x[cand])][:400]
+    return cl, x, c, xs, phi, st, np.sort(keep)
+
+
+def test_large_full_size_sampled():
+    cl, x = synth.large()
+    c = binding.Cloud(_dev(cl.p), _dev(cl.n), _dev(cl.a))
+    phi = c(_dev(x)).cpu().numpy().astype(np.float64)
+    idx = np.sort(np.random.default_rng(78).choice(x.shape[0], 256, replace=False))
+    ref = oracle.sdf(cl.p, cl.n, cl.a, x[idx])
+    D = oracle.bbox_diag(cl.p)
+    err = np.abs(phi[idx] - ref).max()
+    print(f"large 2^20 x 2^20: max |phi - oracle| over 256 sampled queries {err:.3e} (tol {TOL * D:.3e})", flush=True)
+    assert err <= TOL * D and np.isfinite(phi).all()
+
+
+def test_diff_full_size_backward_sampled(diff_case):
+    cl, x, c, xs, phi, st, keep = diff_case
+    gout = np.zeros(x.shape[0], np.float32)
+    gout[keep] = np.random.default_rng(79).normal(size=len(keep)).astype(np.float32)
+    ga, gp, gn = binding.backward_points(c.rec, c.p, c.n, c.a, xs, st, _dev(gout), c.params)
+    refs = oracle.grad_points(cl.p, cl.n, cl.a, x[keep], gout[keep])
+    for what, g, ref in zip("apn", (ga, gp, gn), refs):
+        err = np.abs(g.cpu().numpy().astype(np.float64) - ref).max()
+        print(f"diff full size: dL/d{what} max err {err:.3e}, scale {np.abs(ref).max():.3e}", flush=True)
+        assert err <= 1e-4 * np.abs(ref).max(), what
+    gx = binding.grad_x(c.rec, c.N, xs, st, _dev(gout), c.params).cpu().numpy()
+    _, gref = oracle.sdf(cl.p, cl.n, cl.a, x[keep], grad=True)
+    gx_err = np.abs(gx[keep] - gout[keep, None] * gref).max()
+    print(f"diff full size: d/dx max err {gx_err:.3e}", flush=True)
+    assert gx_err <= GTOL * max(1.0, np.abs(gout).max())
+    others = np.setdiff1d(np.arange(x.shape[0]), keep)
+    assert not np.any(gx[others])
+
+
+def test_diff_full_size_laplacian_sampled(diff_case):
+    cl, x, c, xs, phi, st, keep = diff_case
+    lap, g, eik = binding.laplacian(c.rec, c.N, xs, st, c.params)
+    k = keep[:200]
+    tor = oracle.fit(cl.p, cl.n, cl.a)
+    lref = oracle.laplacian(cl.p, tor, x[k])
+    d = np.linalg.norm(x[k].astype(np.float64)[:, None, :] - cl.p.astype(np.float64)[None], axis=2)
+    tol = 2e-4 * np.maximum(1.0, np.abs(lref)) + 4e-7 * (128.0 / d.max(axis=1)) / d.min(axis=1)
+    err = np.abs(lap.cpu().numpy()[k] - lref)
+    print(f"diff full size: Laplacian largest err/tol {(err / tol).max():.3f}", flush=True)
+    assert np.all(err <= tol)
+    assert torch.isfinite(eik).all()
+
+
+def test_mid_full_size_baselines_and_bounded_sampled():
+    cl, x = synth.mid()
+    c = binding.Cloud(_dev(cl.p), _dev(cl.n), _dev(cl.a))
+    xs = _dev(x)
+    D = oracle.bbox_diag(cl.p)
+    idx = np.sort(np.random.default_rng(80).choice(x.shape[0], 300, replace=False))
+    for kind in ("sspd", "shc"):
+        got = binding.eval_baseline(c.rec, c.N, xs, kind, c.params).cpu().numpy().astype(np.float64)
+        ref, s, sabs = oracle.eval_baseline(cl.p, cl.n, x[idx], kind, raw=True)
+        if kind == "sspd":
+            ok, tol = np.ones(len(idx), bool), np.full(len(idx), TOL * D)
+        else:
+            M = np.linalg.norm(x[idx].astype(np.float64)[:, None, :] - cl.p.astype(np.float64)[None], axis=2).max(1)
+            ok = np.abs(s) > 1e-4 * sabs
+            tol = TOL * D + 64 * 2.0 ** -24 * sabs / (np.abs(s) * (128.0 / M))
+        err = np.abs(got[idx] - ref)
+        print(f"mid full size {kind}: {ok.sum()} compared, largest err/tol {(err[ok] / tol[ok]).max():.3f}", flush=True)
+        assert ok.sum() > 250 and np.all(err[ok] <= tol[ok])
+    eps = 1e-6 * D
+    phi, bd, kept = binding.eval_bounded(c.rec, c.N, xs, eps, c.params, bound=True, kept=True)
+    phi = phi.cpu().numpy().astype(np.float64)
+    ref = oracle.sdf(cl.p, cl.n, cl.a, x[idx])
+    err = np.abs(phi[idx] - ref).max()
+    frac = kept.double().mean().item() / c.N
+    print(f"mid full size bounded (eps 1e-6 D): max err {err:.3e}, {100 * frac:.1f}% of pairs evaluated", flush=True)
+    assert err <= eps + TOL * D and float(bd.max().item()) <= eps * (1 + 1e-3)
+    assert frac < 0.5
