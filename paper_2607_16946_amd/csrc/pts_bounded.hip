@@ -38,11 +38,12 @@
 //
 //   k_qkeys    Morton key (3 x 8 bits over the cloud's bbox) of every query
 //   (radix sort of the keys, pts_build.hip)
-//   k_bwork    per query block: a work estimate (units whose sphere comes
-//              within 25 / lambda of the nearest one, seen from the block's
-//              first query), sorted so that heavy blocks launch first and the
-//              tail of the launch is light (ordering only: a block's result
-//              does not depend on when it runs)
+//   k_bwork    per query block: a work estimate (seen from the block's first
+//              query, the units whose skip bound exceeds a 1/(10 U) share of
+//              the budget eps W, W summed from the unit centres), sorted so
+//              that heavy blocks launch first and the tail of the launch is
+//              light (ordering only: a block's result does not depend on
+//              when it runs)
 //   k_bounded  the sweep: a wave votes per block of 64 units (4096 points)
 //              and, in blocks it keeps, per 64-point unit; kept units are
 //              staged and run the blend's pair arithmetic
@@ -122,28 +123,40 @@ __device__ int64_t nearest_unit(const float4* __restrict__ ub, int64_t u0, int64
   return red_i[0];
 }
 
-__global__ __launch_bounds__(kBlock) void k_bwork(const Header* __restrict__ h, const float4* __restrict__ ub,
-                                                  const float* __restrict__ x, const int32_t* __restrict__ order,
-                                                  int64_t Q, int64_t nqb, int qpl, const float* __restrict__ far2,
-                                                  float C, uint32_t* __restrict__ key, int32_t* __restrict__ idx) {
-  const int64_t b = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+// Threads per workgroup of k_bwork: small, so its few thousand threads spread
+// over every compute unit.
+constexpr int kWorkBlock = 64;
+
+__global__ __launch_bounds__(kWorkBlock) void k_bwork(const Header* __restrict__ h, const float4* __restrict__ ub,
+                                                      const float* __restrict__ x, const int32_t* __restrict__ order,
+                                                      int64_t Q, int64_t nqb, int qpl, const float* __restrict__ far2,
+                                                      float C2, float eps, uint32_t* __restrict__ key,
+                                                      int32_t* __restrict__ idx) {
+  const int64_t b = int64_t(blockIdx.x) * kWorkBlock + threadIdx.x;
   if (b >= nqb) return;
   const int64_t q = order[b * kBW * qpl];
   const QueryIn r = load_query(x, q, Q, h);
-  const float M = sqrtf(fmaxf(far2[q], 0.f));
+  float M = 0.f, nl = 0.f;
+  far_of(far2, 1, Q, q, C2, M, nl);
+  const float A = __uint_as_float(h->a00max_bits);
   const int64_t nunit = (h->N + kUnit - 1) / kUnit;
-  float lo = 3.0e38f;
+  // W from the unit centres, then the units whose skip bound (as the vote
+  // prices it) exceeds a share eps W / (10 U) of the budget: those the sweep
+  // must evaluate, about
+  float W = 0.f;
   for (int64_t u = 0; u < nunit; ++u) {
     const float4 cb = ub[2 * u];
     const float ex = r.x - cb.x, ey = r.y - cb.y, ez = r.z - cb.z;
-    lo = fminf(lo, sqrtf(fmaf(ez, ez, fmaf(ey, ey, ex * ex))) - cb.w);
+    W += hw_exp2(fmaf(hw_sqrt(fmaf(ez, ez, fmaf(ey, ey, ex * ex))), nl, C2));
   }
-  const float cut = lo + 25.f * M / (2.f * C);
+  const float thr = eps * W / (10.f * float(nunit));
   uint32_t cnt = 0;
   for (int64_t u = 0; u < nunit; ++u) {
     const float4 cb = ub[2 * u];
     const float ex = r.x - cb.x, ey = r.y - cb.y, ez = r.z - cb.z;
-    cnt += (sqrtf(fmaf(ez, ez, fmaf(ey, ey, ex * ex))) - cb.w <= cut) ? 1u : 0u;
+    const float s = hw_sqrt(fmaf(ez, ez, fmaf(ey, ey, ex * ex)));
+    const float du = hw_exp2(fmaf(fmaxf(s - cb.w, 0.f), nl, C2));
+    cnt += du * (s + cb.w + M + 2.f * A) > thr ? 1u : 0u;
   }
   key[b] = 0xffffffu - (cnt < 0xffffffu ? cnt : 0xffffffu);   // ascending sort = heaviest first
   idx[b] = int32_t(b);
@@ -184,9 +197,12 @@ __global__ __launch_bounds__(kBW) void k_bounded(const Header* __restrict__ h, c
                                                  int64_t Q, int S, int64_t per_split,
                                                  const float* __restrict__ far2, float C2, float eps_total,
                                                  float4* __restrict__ part, int32_t* __restrict__ kpart) {
+  // 5 KB of LDS per wave (8 waves per SIMD); the seed searches' reductions
+  // use the unit tile, which holds nothing yet (every tile write is preceded
+  // by a barrier that also orders the reductions' reads)
   __shared__ float4 tile[kUnit * kRecF4];
-  __shared__ float red_v[kBW];
-  __shared__ int32_t red_i[kBW];
+  float* red_v = reinterpret_cast<float*>(tile);
+  int32_t* red_i = reinterpret_cast<int32_t*>(tile) + kBW;
   const int split = int(blockIdx.x % unsigned(S));
   const int64_t qb = border[blockIdx.x / unsigned(S)];
   const int64_t N = h->N;
@@ -392,12 +408,12 @@ int launch_bounded(const void* rec, int64_t N, const float* x, int64_t Q, float 
   const int32_t* order = v.idx[cur];
   if (int rc = launch_far_cull(rec, N, x, Q, plan.qpl, v.far2, nullptr, st)) return rc;
   // heavy query blocks first
-  hipLaunchKernelGGL(k_bwork, dim3(unsigned((plan.nqb + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, h, ub, x, order,
-                     Q, plan.nqb, plan.qpl, v.far2, C, v.bkey[0], v.bidx[0]);
+  const float C2 = C * kLog2e;
+  hipLaunchKernelGGL(k_bwork, dim3(unsigned((plan.nqb + kWorkBlock - 1) / kWorkBlock)), dim3(kWorkBlock), 0, st, h, ub,
+                     x, order, Q, plan.nqb, plan.qpl, v.far2, C2, eps, v.bkey[0], v.bidx[0]);
   int bcur = 0;
   if (int rc = launch_radix_sort(v.bkey, v.bidx, plan.nqb, 6, v.rhist, st, &bcur)) return rc;
   const int32_t* border = v.bidx[bcur];
-  const float C2 = C * kLog2e;
   switch (plan.qpl) {
     case 1: launch_bounded_q<1>(h, recs, ub, bb, x, order, border, Q, plan, v.far2, C2, eps, v.part, v.kpart, st); break;
     case 2: launch_bounded_q<2>(h, recs, ub, bb, x, order, border, Q, plan, v.far2, C2, eps, v.part, v.kpart, st); break;
