@@ -26,6 +26,12 @@
  *  - Every call returns a status (PTS_OK = 0 on success).  On failure nothing
  *    has been enqueued, and pts_last_error() returns a message for the calling
  *    thread.  No C++ exception crosses this boundary.
+ *  - A call that takes a record `rec` and a point count N requires N to be the
+ *    count the record was built with.  The record lives in device memory and
+ *    is not read back on the host to check this (that would block every
+ *    call), so a different N is undefined behaviour: kernels would locate the
+ *    record's sections for the wrong size.  pts_cloud_info_get returns the
+ *    record's N.
  *  - No entry point allocates device memory except the server (pts_server_*),
  *    which allocates from its own budget; scratch memory is passed in by the
  *    caller, sized by the matching *_ws_bytes call.
