@@ -231,8 +231,10 @@ int trace_step_pre(const int32_t* act, int64_t na, const float* org, const float
 int trace_step_post(const int32_t* act, int64_t na, const float* phi, float eps, float tmax, int step, float* t,
                     int32_t* hit, int32_t* nsteps, int32_t* keep, int32_t* act_out, int32_t* blk, int32_t* off,
                     int32_t* count, hipStream_t st);
-int trace_normals_all(const void* rec, int64_t N, const float* org, const float* dir, const float* t,
-                      const int32_t* hit, int64_t R, int32_t* iota, float* xq, float* phi, float* g, float* nrm,
-                      const Plan& plan, float C, void* ws, hipStream_t st);
+int trace_hits(const int32_t* hit, int64_t R, int32_t* iota, int32_t* act_out, int32_t* blk, int32_t* off,
+               int32_t* count, hipStream_t st);
+int trace_normals_hits(const void* rec, int64_t N, const float* org, const float* dir, const float* t,
+                       const int32_t* act, int64_t nh, float* xq, float* phi, float* g, float* nrm, const Plan& plan,
+                       float C, void* ws, hipStream_t st);
 
 }  // namespace pts

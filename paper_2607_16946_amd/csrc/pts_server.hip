@@ -18,8 +18,10 @@
 // second launch runs while the first is still on the device.  When a launch's
 // end event has fired: query requests copy their results out and finish;
 // trace requests take their new active-ray count and are packed again, or,
-// once every ray has stopped or the step budget is spent, compute normals and
-// copy back on the finishing stream.
+// once every ray has stopped or the step budget is spent, finish on the
+// finishing stream: with normals, the hit rays are compacted and counted
+// first (one more event), and the normals are evaluated at those rays only;
+// then the results are copied back.
 //
 // Memory.  One device allocation of hbm_budget_bytes holds everything: cloud
 // records, request buffers and the launch descriptors (reserved at creation).
@@ -188,7 +190,6 @@ struct Req {
   size_t cloud_off = 0;
   int64_t N = 0;
   Plan plan{};   // split of query requests and of trace steps
-  Plan nplan{};  // split of a trace request's normals
   ReqLayout lay;
   size_t dev_off = 0;
   bool admitted = false;
@@ -198,6 +199,7 @@ struct Req {
   int64_t n_active = 0;
   int step = 0;
   bool finalizing = false;
+  bool fin_hits = false;  // normals asked for: the hit count is on its way to the host
   int final_rc = PTS_OK;
   hipEvent_t fin_ev = nullptr;
   int32_t *act = nullptr, *nxt = nullptr;
@@ -373,7 +375,6 @@ class Server {
     const int64_t n = r->count;
     if (n > 0) {
       q->plan = march_plan(c.N, n, P_, kServerSplitCap);
-      q->nplan = normal_plan(c.N, n, P_);
       if (work_descs(n, q->plan.S) > max_work_ || comb_descs(n) > max_comb_) {
         std::lock_guard<std::mutex> lk(mu_);
         ++rejected_;
@@ -774,8 +775,10 @@ class Server {
     return any;
   }
 
-  // Normals (if asked for) and the copy back of a finished march (mu_ held;
-  // the request's last launch has completed).
+  // The end of a finished march (mu_ held; the request's last launch has
+  // completed).  With normals, the hit rays are first compacted on the device
+  // and their count copied to the host (complete_finals then evaluates the
+  // normals at those rays only); otherwise the results are copied back.
   void start_final_locked(Req* q) {
     q->finalizing = true;
     finals_.push_back(q);
@@ -783,11 +786,39 @@ class Server {
     const int64_t n = q->r.count;
     hipStream_t st = fin_stream_;
     int rc = PTS_OK;
-    if (q->r.out_normal)
-      rc = trace_normals_all(base_ + q->cloud_off, q->N, dev<float>(q, q->lay.org), dev<float>(q, q->lay.dir),
-                             dev<float>(q, q->lay.t), dev<int32_t>(q, q->lay.hit), n, dev<int32_t>(q, q->lay.keep),
-                             dev<float>(q, q->lay.xq), dev<float>(q, q->lay.phi), dev<float>(q, q->lay.g),
-                             dev<float>(q, q->lay.nrm), q->nplan, P_.C, dev<void>(q, q->lay.nws), st);
+    if (q->r.out_normal) {
+      rc = trace_hits(dev<int32_t>(q, q->lay.hit), n, dev<int32_t>(q, q->lay.keep), dev<int32_t>(q, q->lay.act),
+                      dev<int32_t>(q, q->lay.blk), dev<int32_t>(q, q->lay.off), dev<int32_t>(q, q->lay.cnt), st);
+      // the staged inputs were uploaded before the march: their first bytes take the count
+      if (!rc)
+        rc = check_hip(hipMemcpyAsync(q->stage, dev<int32_t>(q, q->lay.cnt), sizeof(int32_t), hipMemcpyDeviceToHost,
+                                      st),
+                       "copy hit count");
+      if (!rc) rc = check_hip(hipEventCreateWithFlags(&q->fin_ev, hipEventDisableTiming), "final event");
+      if (!rc) rc = check_hip(hipEventRecord(q->fin_ev, st), "final event");
+      q->fin_hits = true;
+      q->final_rc = rc;
+      return;
+    }
+    q->final_rc = enqueue_results_locked(q, false);
+  }
+
+  // Normals at the hit rays (their count is in the first bytes of the stage)
+  // if `normals`, then the copy back of the results and an event after it.
+  int enqueue_results_locked(Req* q, bool normals) {
+    const int64_t n = q->r.count;
+    hipStream_t st = fin_stream_;
+    int rc = PTS_OK;
+    if (normals) {
+      int32_t nh = 0;
+      std::memcpy(&nh, q->stage, sizeof(nh));
+      if (nh < 0 || nh > n) return fail(PTS_EHIP, "hit count out of range");
+      const Plan plan = normal_plan(q->N, nh, P_);
+      rc = trace_normals_hits(base_ + q->cloud_off, q->N, dev<float>(q, q->lay.org), dev<float>(q, q->lay.dir),
+                              dev<float>(q, q->lay.t), dev<int32_t>(q, q->lay.act), nh, dev<float>(q, q->lay.xq),
+                              dev<float>(q, q->lay.phi), dev<float>(q, q->lay.g), dev<float>(q, q->lay.nrm), plan,
+                              P_.C, dev<void>(q, q->lay.nws), st);
+    }
     char* s = q->stage + size_t(n) * 24;
     if (!rc)
       rc = check_hip(hipMemcpyAsync(s, dev<float>(q, q->lay.t), size_t(n) * 4, hipMemcpyDeviceToHost, st), "copy t");
@@ -805,7 +836,7 @@ class Server {
                      "copy normals");
     if (!rc) rc = check_hip(hipEventCreateWithFlags(&q->fin_ev, hipEventDisableTiming), "final event");
     if (!rc) rc = check_hip(hipEventRecord(q->fin_ev, st), "final event");
-    q->final_rc = rc;
+    return rc;
   }
 
   bool complete_finals() {
@@ -827,6 +858,16 @@ class Server {
         }
         if (q->fin_ev) (void)hipEventDestroy(q->fin_ev);
         q->fin_ev = nullptr;
+        if (!rc && q->fin_hits && !q->cancel) {  // the hit count has arrived
+          q->fin_hits = false;
+          rc = enqueue_results_locked(q, true);
+          q->final_rc = rc;
+          if (!rc) {
+            ++i;
+            continue;
+          }
+          (void)hipStreamSynchronize(fin_stream_);  // drain what was enqueued before the error
+        }
       }
       any = true;
       const int64_t n = q->r.count;

@@ -132,19 +132,6 @@ __global__ __launch_bounds__(kBlock) void k_normals(const int32_t* __restrict__ 
   nrm[3 * r + 2] = gz * il;
 }
 
-// Normals of all R rays evaluated in ray order, written only where hit.
-__global__ __launch_bounds__(kBlock) void k_normals_masked(const int32_t* __restrict__ hit, int64_t R,
-                                                           const float* __restrict__ g, float* __restrict__ nrm) {
-  const int64_t r = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (r >= R || !hit[r]) return;
-  const float gx = g[3 * r], gy = g[3 * r + 1], gz = g[3 * r + 2];
-  const float l = sqrtf(gx * gx + gy * gy + gz * gz);
-  const float il = l > 0.f ? 1.f / l : 0.f;
-  nrm[3 * r] = gx * il;
-  nrm[3 * r + 1] = gy * il;
-  nrm[3 * r + 2] = gz * il;
-}
-
 __global__ __launch_bounds__(kBlock) void k_iota(int32_t* __restrict__ out, int64_t n) {
   const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (i < n) out[i] = int32_t(i);
@@ -303,20 +290,33 @@ int trace_step_post(const int32_t* act, int64_t na, const float* phi, float eps,
   return check_hip(hipGetLastError(), "trace advance");
 }
 
-// Normals of every ray at its final position (kept only where it hit); the
-// gradient of a ray does not depend on the other rays, so this gives the same
-// normals as evaluating the hit rays alone.  `iota` is scratch of R int32.
-int trace_normals_all(const void* rec, int64_t N, const float* org, const float* dir, const float* t,
-                      const int32_t* hit, int64_t R, int32_t* iota, float* xq, float* phi, float* g, float* nrm,
-                      const Plan& plan, float C, void* ws, hipStream_t st) {
-  const WsView wv = ws_view(plan, R, ws);
-  hipLaunchKernelGGL(k_iota, dim3(nblk(R)), dim3(kBlock), 0, st, iota, R);
-  hipLaunchKernelGGL(k_positions, dim3(nblk(R)), dim3(kBlock), 0, st, iota, R, org, dir, t, xq);
-  if (int rc = launch_far_arg(rec, N, xq, R, plan, wv, st)) return rc;
-  if (int rc = launch_blend(rec, N, xq, R, C, plan, wv, st)) return rc;
-  if (int rc = launch_combine_stats(rec, N, xq, R, plan, wv, phi, wv.stats, st)) return rc;
-  if (int rc = launch_grad(rec, N, xq, R, wv.stats, nullptr, g, C, plan, wv, st)) return rc;
-  hipLaunchKernelGGL(k_normals_masked, dim3(nblk(R)), dim3(kBlock), 0, st, hit, R, g, nrm);
+// Hit rays of a finished march, compacted on the device in ray order into
+// act_out [0, *count); `iota` is scratch of R int32.  Nothing is read back.
+int trace_hits(const int32_t* hit, int64_t R, int32_t* iota, int32_t* act_out, int32_t* blk, int32_t* off,
+               int32_t* count, hipStream_t st) {
+  const unsigned nb = nblk(R);
+  hipLaunchKernelGGL(k_iota, dim3(nb), dim3(kBlock), 0, st, iota, R);
+  hipLaunchKernelGGL(k_count, dim3(nb), dim3(kBlock), 0, st, hit, R, blk);
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, blk, int64_t(nb), off, count);
+  hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, st, hit, iota, R, off, act_out);
+  return check_hip(hipGetLastError(), "trace hit compaction");
+}
+
+// Normals at the nh hit rays act [0, nh) (from trace_hits), written to nrm at
+// their ray index; the other rays' entries are left as they are (0 from
+// trace_init).  plan = normal_plan(N, nh, ...): its splits depend on N only,
+// so the normals are bitwise those pts_trace computes.
+int trace_normals_hits(const void* rec, int64_t N, const float* org, const float* dir, const float* t,
+                       const int32_t* act, int64_t nh, float* xq, float* phi, float* g, float* nrm, const Plan& plan,
+                       float C, void* ws, hipStream_t st) {
+  if (nh == 0) return PTS_OK;
+  const WsView wv = ws_view(plan, nh, ws);
+  hipLaunchKernelGGL(k_positions, dim3(nblk(nh)), dim3(kBlock), 0, st, act, nh, org, dir, t, xq);
+  if (int rc = launch_far_arg(rec, N, xq, nh, plan, wv, st)) return rc;
+  if (int rc = launch_blend(rec, N, xq, nh, C, plan, wv, st)) return rc;
+  if (int rc = launch_combine_stats(rec, N, xq, nh, plan, wv, phi, wv.stats, st)) return rc;
+  if (int rc = launch_grad(rec, N, xq, nh, wv.stats, nullptr, g, C, plan, wv, st)) return rc;
+  hipLaunchKernelGGL(k_normals, dim3(nblk(nh)), dim3(kBlock), 0, st, act, nh, g, nrm);
   return check_hip(hipGetLastError(), "trace normals");
 }
 
