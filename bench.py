@@ -28,6 +28,15 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# The serving leg's server overlaps consecutive packed launches on two HIP
+# streams, which only overlap on the device if HIP maps them to different
+# hardware queues.  With HIP's default of 4 queues per process that depends on
+# how many streams the process created before the server (measured: one
+# earlier stream put both launch streams on one queue, device busy 0.9 instead
+# of 1.7 of wall time and p50 latency 3.5 instead of 2.0 ms at 90% load); with
+# 8 it does not.  Must be set before HIP initialises; a caller's setting wins.
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+
 METRIC = "query×point SDF evals/sec (FP32, % of VALU peak); p50/p99 latency in serving mode"
 
 # Algorithmic work per (query, point) pair, counted from the definition

@@ -417,7 +417,13 @@ int pts_eval_radius(const void* rec, int64_t N, const float* x, int64_t Q, float
  * up to two such launches in flight on two streams, so requests that arrive
  * while the device is busy are admitted and start as soon as memory and a
  * launch slot free up.  Trace requests advance one step per launch and are
- * repacked until every ray has stopped; then normals are computed.
+ * repacked until every ray has stopped; then normals are computed at the hit
+ * rays.  The two launches overlap on the device only if HIP maps the two
+ * streams to different hardware queues; with HIP's default of 4 queues per
+ * process that depends on how many streams the process created earlier, so
+ * a process that runs a server beside other GPU work should start with
+ * GPU_MAX_HW_QUEUES=8 or more in its environment (results do not depend on
+ * it, latency does).
  *
  * A request on a cloud of N points is evaluated with the point split
  * pts_server_cloud_plan reports, a function of N only (the march split of

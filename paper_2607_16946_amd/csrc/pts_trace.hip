@@ -74,31 +74,26 @@ __global__ __launch_bounds__(kBlock) void k_count(const int32_t* __restrict__ ke
   if (threadIdx.x == 0) blk[blockIdx.x] = c;
 }
 
-// Compaction, pass 2: exclusive scan of the block counts (one workgroup);
-// total written to *count.
-__global__ __launch_bounds__(1024) void k_scan_counts(int32_t* __restrict__ blk, int64_t nb,
-                                                      int32_t* __restrict__ off, int32_t* __restrict__ count) {
-  __shared__ int32_t s[1024];
-  __shared__ int32_t carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (int64_t base = 0; base < nb; base += 1024) {
-    const int64_t i = base + threadIdx.x;
+// Compaction, pass 2: exclusive scan of the block counts by one wavefront
+// (a 64-lane shuffle scan per 64 counts, carried in a register), total
+// written to *count.  One wave and no LDS, so it finds a slot at once beside
+// large concurrent launches.
+__global__ __launch_bounds__(64) void k_scan_counts(const int32_t* __restrict__ blk, int64_t nb,
+                                                    int32_t* __restrict__ off, int32_t* __restrict__ count) {
+  const int lane = int(threadIdx.x);
+  int32_t carry = 0;
+  for (int64_t base = 0; base < nb; base += 64) {
+    const int64_t i = base + lane;
     const int32_t v = i < nb ? blk[i] : 0;
-    s[threadIdx.x] = v;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-      const int32_t a = threadIdx.x >= unsigned(o) ? s[threadIdx.x - o] : 0;
-      __syncthreads();
-      s[threadIdx.x] += a;
-      __syncthreads();
+    int32_t incl = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int32_t t = __shfl_up(incl, o);
+      if (lane >= o) incl += t;
     }
-    if (i < nb) off[i] = carry + s[threadIdx.x] - v;
-    __syncthreads();
-    if (threadIdx.x == 1023) carry += s[1023];
-    __syncthreads();
+    if (i < nb) off[i] = carry + incl - v;
+    carry += __shfl(incl, 63);
   }
-  if (threadIdx.x == 0) *count = carry;
+  if (lane == 0) *count = carry;
 }
 
 // Compaction, pass 3: stable scatter of the kept entries.
@@ -178,7 +173,7 @@ int compact(const int32_t* keep, const int32_t* act_in, int64_t n, int32_t* act_
             hipStream_t st) {
   const unsigned nb = nblk(n);
   hipLaunchKernelGGL(k_count, dim3(nb), dim3(kBlock), 0, st, keep, n, v.blk);
-  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, v.blk, int64_t(nb), v.off, v.count);
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(64), 0, st, v.blk, int64_t(nb), v.off, v.count);
   hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, st, keep, act_in, n, v.off, act_out);
   int32_t c = 0;
   if (int rc = check_hip(hipMemcpyAsync(&c, v.count, sizeof(c), hipMemcpyDeviceToHost, st), "read count")) return rc;
@@ -285,7 +280,7 @@ int trace_step_post(const int32_t* act, int64_t na, const float* phi, float eps,
   const unsigned nb = nblk(na);
   hipLaunchKernelGGL(k_advance, dim3(nb), dim3(kBlock), 0, st, act, na, phi, eps, tmax, step, t, hit, nsteps, keep);
   hipLaunchKernelGGL(k_count, dim3(nb), dim3(kBlock), 0, st, keep, na, blk);
-  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, blk, int64_t(nb), off, count);
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(64), 0, st, blk, int64_t(nb), off, count);
   hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, st, keep, act, na, off, act_out);
   return check_hip(hipGetLastError(), "trace advance");
 }
@@ -297,7 +292,7 @@ int trace_hits(const int32_t* hit, int64_t R, int32_t* iota, int32_t* act_out, i
   const unsigned nb = nblk(R);
   hipLaunchKernelGGL(k_iota, dim3(nb), dim3(kBlock), 0, st, iota, R);
   hipLaunchKernelGGL(k_count, dim3(nb), dim3(kBlock), 0, st, hit, R, blk);
-  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, blk, int64_t(nb), off, count);
+  hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(64), 0, st, blk, int64_t(nb), off, count);
   hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(kBlock), 0, st, hit, iota, R, off, act_out);
   return check_hip(hipGetLastError(), "trace hit compaction");
 }

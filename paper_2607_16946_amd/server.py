@@ -44,7 +44,10 @@ class Server:
     """Resident-cloud SDF server with continuous batching.
 
     Parameters mirror ``pts_server_cfg``; ``mock=True`` runs the scheduler
-    without a device (a cost model stands in for the kernels).
+    without a device (a cost model stands in for the kernels).  Consecutive
+    packed launches overlap on the device only if HIP gives the server's two
+    launch streams different hardware queues: start the process with
+    ``GPU_MAX_HW_QUEUES=8`` (or more) when it creates other streams too.
     """
 
     def __init__(self, budget_bytes: int = 4 << 30, max_inflight: int = 64, max_queue: int = 0,
