@@ -34,8 +34,14 @@ sys.path.insert(0, ROOT)
 # how many streams the process created before the server (measured: one
 # earlier stream put both launch streams on one queue, device busy 0.9 instead
 # of 1.7 of wall time and p50 latency 3.5 instead of 2.0 ms at 90% load); with
-# 8 it does not.  Must be set before HIP initialises; a caller's setting wins.
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+# 8 it does not.  Must be set before HIP initialises; raised to 8 unless the
+# environment already allows more.
+try:
+    _hwq = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
+except ValueError:
+    _hwq = 4
+if _hwq < 8:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
 
 METRIC = "query×point SDF evals/sec (FP32, % of VALU peak); p50/p99 latency in serving mode"
 
@@ -479,6 +485,7 @@ def serving_bench(n_requests: int, n_warmup: int, loads, n_clouds: int = 64, bud
     out = {"workload": f"{n_clouds} resident clouds (sphere generator, N log-uniform 1024..262144); 90% query "
                        f"requests Q log-uniform 1..65536, 10% 256x256 sphere traces of 48 steps with normals",
            "budget_gib": budget_gib, "clouds": n_clouds, "points_resident": int(Ns.sum()),
+           "gpu_max_hw_queues": os.environ.get("GPU_MAX_HW_QUEUES"),
            "capacity_req_s": cap, "capacity_pairs_s": st["pairs"] / wall, "capacity_requests": len(burst),
            "capacity_launches": st["launches"], "capacity_busy_frac": st["busy_s"] / wall, "loads": []}
     log(f"serving: capacity {cap:.1f} req/s, {st['pairs'] / wall:.3g} pairs/s over {len(burst)} requests "
