@@ -198,6 +198,15 @@ def test_overlapping_launches_and_edge_requests():
         o, d = _rays(8, 1)
         r = S.wait(S.submit_trace(ids[0], o, d, steps=0, eps=1e-4, tmax=6.0))
         assert np.all(r["t"] == 0) and not r["hit"].any() and np.all(r["steps"] == 0) and np.all(r["normal"] == 0)
+        # every ray misses (camera turned away): no hit rays to take normals at
+        r = S.wait(S.submit_trace(ids[0], o, -d, steps=32, eps=1e-4, tmax=6.0))
+        assert not r["hit"].any() and np.all(r["normal"] == 0) and np.all(r["t"] > 0)
+        # a single ray that hits, and one that misses
+        o1 = np.array([[0.0, 0.0, 3.0], [0.0, 0.0, 3.0]], np.float32)
+        d1 = np.array([[0.0, 0.0, -1.0], [0.0, 0.0, 1.0]], np.float32)
+        r = S.wait(S.submit_trace(ids[0], o1, d1, steps=64, eps=1e-4, tmax=6.0))
+        assert r["hit"].tolist() == [1, 0] and np.all(r["normal"][1] == 0)
+        assert abs(float(r["normal"][0][2]) - 1.0) < 1e-2
         S.reset_stats()
         t0 = time.time()
         # a long launch first (about 10^10 pairs), then arrivals while it runs
