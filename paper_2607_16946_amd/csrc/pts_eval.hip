@@ -23,7 +23,7 @@
 // and the sums are accumulated per tile and then per split (two-level), which
 // bounds FP32 accumulation error by ~(tile + N/(S tile)) ulp.
 
-#include "pts_device.h"
+#include "pts_farcull.h"
 
 namespace pts {
 namespace {
@@ -33,28 +33,16 @@ namespace {
 //   |x-p|^2 = |x|^2 + |p|^2 - 2<x,p>; the max is taken over (|p|^2 - 2<x,p>)
 //   (three FMAs and a max per pair) and |x|^2 is added once at the end.
 // Exact culling by units of kUnit consecutive slots (spatially sorted at
-// build time, with bounding spheres (c, r) and extreme points e):
-//   1. LB = max_u |x - e_u| <= M for each query of the workgroup;
-//   2. unit u can hold a point farther than LB (1 - 1e-5) only if
-//      |x - c_u| + r_u >= LB (1 - 1e-5) for some query of the workgroup;
-//   3. only the points of such units are swept, in ascending slot order.
-// A culled unit's points are at least 1e-5 M closer than the farthest point,
-// far beyond FP32 rounding of the swept values, so M^2 (and, with kArg, the
-// first slot attaining it) is exactly what a sweep over every point gives.
+// build time, with bounding spheres and extreme points; pts_farcull.h), the
+// lower bound here from every unit's extreme point, so M^2 (and, with kArg,
+// the first slot attaining it) is exactly what a sweep over every point gives.
 // ---------------------------------------------------------------------------
-constexpr int kChunkU = 256;            // units whose bounds are staged in LDS at once
-constexpr int kBatchU = kTile1 / kUnit;  // units per LDS tile of points
-
 template <int QPL, bool kArg>
 __global__ __launch_bounds__(kBlock) void k_far_cull(const Header* __restrict__ h, const float4* __restrict__ pos4,
                                                      const float4* __restrict__ ub, const float* __restrict__ x,
                                                      int64_t Q, float* __restrict__ far2,
                                                      int32_t* __restrict__ farix) {
-  __shared__ float4 sb[kChunkU];
-  __shared__ uint32_t smask[kChunkU / 32];
-  __shared__ int32_t slist[kChunkU];
-  __shared__ int32_t scount;
-  __shared__ float4 tile[kTile1];
+  __shared__ FarLds L;
   const int64_t N = h->N;
   const int64_t U = (N + kUnit - 1) / kUnit;
   const int64_t qb = blockIdx.x;
@@ -70,95 +58,10 @@ __global__ __launch_bounds__(kBlock) void k_far_cull(const Header* __restrict__ 
     ix[k] = -1;
     lb[k] = -1.f;
   }
-  // 1. lower bound from the units' extreme points
-  for (int64_t c0 = 0; c0 < U; c0 += kChunkU) {
-    const int cnt = int(min<int64_t>(kChunkU, U - c0));
-    __syncthreads();
-    for (int j = threadIdx.x; j < cnt; j += kBlock) sb[j] = ub[2 * (c0 + j) + 1];
-    __syncthreads();
-    for (int j = 0; j < cnt; ++j) {
-      const float4 E = sb[j];
-#pragma unroll
-      for (int k = 0; k < QPL; ++k) {
-        const float dx = qx[k] - E.x, dy = qy[k] - E.y, dz = qz[k] - E.z;
-        lb[k] = fmaxf(lb[k], fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
-      }
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < QPL; ++k) {
-    ok[k] = ok[k] && lb[k] >= 0.f;              // a query with a NaN coordinate needs no unit: M is NaN
-    lb[k] = sqrtf(fmaxf(lb[k], 0.f)) * (1.f - 1e-5f);
-  }
-  // 2./3. per chunk of units: mark the needed ones, list them, sweep their points
-  for (int64_t c0 = 0; c0 < U; c0 += kChunkU) {
-    const int cnt = int(min<int64_t>(kChunkU, U - c0));
-    __syncthreads();
-    for (int j = threadIdx.x; j < cnt; j += kBlock) sb[j] = ub[2 * (c0 + j)];
-    for (int j = threadIdx.x; j < kChunkU / 32; j += kBlock) smask[j] = 0u;
-    __syncthreads();
-    for (int j = 0; j < cnt; ++j) {
-      const float4 C = sb[j];
-      bool need = false;
-#pragma unroll
-      for (int k = 0; k < QPL; ++k) {
-        const float t = lb[k] - C.w;
-        const float dx = qx[k] - C.x, dy = qy[k] - C.y, dz = qz[k] - C.z;
-        const float dc2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        need = need || (ok[k] && (t <= 0.f || !(dc2 < t * t)));
-      }
-      if (__ballot(need) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&smask[j >> 5], 1u << (j & 31));
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {  // ascending list of the needed units (first wave)
-      const int w = int(threadIdx.x);
-      const uint32_t bits = w < kChunkU / 32 ? smask[w] : 0u;
-      const int pc = __popc(bits);
-      int incl = pc;
-      for (int o = 1; o < 64; o <<= 1) {
-        const int t = __shfl_up(incl, o);
-        if (w >= o) incl += t;
-      }
-      int pos = incl - pc;
-      for (uint32_t b = bits; b != 0u; b &= b - 1u) slist[pos++] = int32_t(c0) + w * 32 + (__ffs(b) - 1);
-      if (w == 63) scount = incl;
-    }
-    __syncthreads();
-    const int nlist = scount;
-    for (int b0 = 0; b0 < nlist; b0 += kBatchU) {
-      const int nbu = min(kBatchU, nlist - b0);
-      const int cntp = nbu * kUnit;
-      __syncthreads();
-      for (int t = threadIdx.x; t < cntp; t += kBlock) {
-        const int64_t sl = int64_t(slist[b0 + t / kUnit]) * kUnit + (t % kUnit);
-        tile[t] = sl < N ? pos4[sl] : make_float4(0.f, 0.f, 0.f, -3.0e38f);
-      }
-      __syncthreads();
-      if (kArg) {
-        for (int u = 0; u < nbu; ++u) {
-          const int32_t base = slist[b0 + u] * kUnit;
-          for (int j = 0; j < kUnit; ++j) {
-            const float4 P = tile[u * kUnit + j];
-#pragma unroll
-            for (int k = 0; k < QPL; ++k) {
-              const float a = fmaf(qz[k], P.z, fmaf(qy[k], P.y, fmaf(qx[k], P.x, P.w)));
-              if (a > acc[k]) { acc[k] = a; ix[k] = base + j; }
-            }
-          }
-        }
-      } else {
-        for (int j = 0; j < cntp; j += 2) {
-          const float4 P0 = tile[j], P1 = tile[j + 1];
-#pragma unroll
-          for (int k = 0; k < QPL; ++k) {
-            const float a0 = fmaf(qz[k], P0.z, fmaf(qy[k], P0.y, fmaf(qx[k], P0.x, P0.w)));
-            const float a1 = fmaf(qz[k], P1.z, fmaf(qy[k], P1.y, fmaf(qx[k], P1.x, P1.w)));
-            acc[k] = fmaxf(acc[k], fmaxf(a0, a1));
-          }
-        }
-      }
-    }
-  }
+  // 1. lower bound from every unit's extreme point; 2./3. the units that can reach it
+  far_bound<QPL>(ub, U, [](int64_t i) { return i; }, qx, qy, qz, lb, L);
+  far_threshold<QPL>(lb, ok);
+  far_sweep<QPL, kArg>(pos4, ub, 0, U, N, qx, qy, qz, ok, lb, acc, ix, L);
 #pragma unroll
   for (int k = 0; k < QPL; ++k) {
     const int64_t q = qb * (kBlock * QPL) + k * kBlock + threadIdx.x;

@@ -1,0 +1,144 @@
+// pts_farcull.h -- exact culling of the farthest-point sweep (the maximum of
+// Eq. RelationshipBetweenLambdaAndRadius), shared by the single-request sweep
+// (pts_eval.hip) and the packed serving sweep (pts_multi.hip).
+//
+// With LB <= M the largest distance from a query to some actual points (the
+// extreme points e_u of chosen 64-slot units), a unit whose bounding sphere
+// (c, r) has |x - c| + r < LB (1 - 1e-5) for every query of the workgroup
+// cannot hold the farthest point: its points are at least 1e-5 M nearer than
+// M, far above FP32 rounding of the swept values.  Only the other units are
+// swept, in ascending slot order, so the maximum (and, with kArg, the first
+// slot attaining it) is exactly that of a full sweep over the same points.
+#pragma once
+
+#include "pts_device.h"
+
+namespace pts {
+
+constexpr int kChunkU = 256;             // units whose bounds are staged in LDS at once
+constexpr int kBatchU = kTile1 / kUnit;  // units per LDS tile of points
+
+// LDS of one workgroup's culled sweep.
+struct FarLds {
+  float4 sb[kChunkU];
+  uint32_t smask[kChunkU / 32];
+  int32_t slist[kChunkU];
+  int32_t scount;
+  float4 tile[kTile1];
+};
+
+// lb[k] = max(lb[k], largest squared distance from query k to the extreme
+// points of the units unit_of(i), i in [0, n)).
+template <int QPL, class UnitOf>
+__device__ __forceinline__ void far_bound(const float4* __restrict__ ub, int64_t n, UnitOf unit_of,
+                                          const float (&qx)[QPL], const float (&qy)[QPL], const float (&qz)[QPL],
+                                          float (&lb)[QPL], FarLds& L) {
+  for (int64_t c0 = 0; c0 < n; c0 += kChunkU) {
+    const int cnt = int(min<int64_t>(kChunkU, n - c0));
+    __syncthreads();
+    for (int j = threadIdx.x; j < cnt; j += kBlock) L.sb[j] = ub[2 * unit_of(c0 + j) + 1];
+    __syncthreads();
+    for (int j = 0; j < cnt; ++j) {
+      const float4 E = L.sb[j];
+#pragma unroll
+      for (int k = 0; k < QPL; ++k) {
+        const float dx = qx[k] - E.x, dy = qy[k] - E.y, dz = qz[k] - E.z;
+        lb[k] = fmaxf(lb[k], fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+      }
+    }
+  }
+}
+
+// The squared bound becomes the cull threshold LB (1 - 1e-5); a query with a
+// NaN coordinate needs no unit (its M is NaN whatever is swept).
+template <int QPL>
+__device__ __forceinline__ void far_threshold(float (&lb)[QPL], bool (&ok)[QPL]) {
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) {
+    ok[k] = ok[k] && lb[k] >= 0.f;
+    lb[k] = sqrtf(fmaxf(lb[k], 0.f)) * (1.f - 1e-5f);
+  }
+}
+
+// Sweep the units of [u_lo, u_hi) that some query of the workgroup needs:
+// acc[k] = max over their points of |p|^2 - 2<x,p> (slots >= slot_end are
+// padding), and with kArg ix[k] the first slot attaining it.
+template <int QPL, bool kArg>
+__device__ __forceinline__ void far_sweep(const float4* __restrict__ pos4, const float4* __restrict__ ub,
+                                          int64_t u_lo, int64_t u_hi, int64_t slot_end, const float (&qx)[QPL],
+                                          const float (&qy)[QPL], const float (&qz)[QPL], const bool (&ok)[QPL],
+                                          const float (&lb)[QPL], float (&acc)[QPL], int32_t (&ix)[QPL],
+                                          FarLds& L) {
+  for (int64_t c0 = u_lo; c0 < u_hi; c0 += kChunkU) {
+    const int cnt = int(min<int64_t>(kChunkU, u_hi - c0));
+    __syncthreads();
+    for (int j = threadIdx.x; j < cnt; j += kBlock) L.sb[j] = ub[2 * (c0 + j)];
+    for (int j = threadIdx.x; j < kChunkU / 32; j += kBlock) L.smask[j] = 0u;
+    __syncthreads();
+    // mark the needed units
+    for (int j = 0; j < cnt; ++j) {
+      const float4 C = L.sb[j];
+      bool need = false;
+#pragma unroll
+      for (int k = 0; k < QPL; ++k) {
+        const float t = lb[k] - C.w;
+        const float dx = qx[k] - C.x, dy = qy[k] - C.y, dz = qz[k] - C.z;
+        const float dc2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        need = need || (ok[k] && (t <= 0.f || !(dc2 < t * t)));
+      }
+      if (__ballot(need) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&L.smask[j >> 5], 1u << (j & 31));
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {  // ascending list of the needed units (first wave)
+      const int w = int(threadIdx.x);
+      const uint32_t bits = w < kChunkU / 32 ? L.smask[w] : 0u;
+      const int pc = __popc(bits);
+      int incl = pc;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o);
+        if (w >= o) incl += t;
+      }
+      int pos = incl - pc;
+      for (uint32_t b = bits; b != 0u; b &= b - 1u) L.slist[pos++] = int32_t(c0) + w * 32 + (__ffs(b) - 1);
+      if (w == 63) L.scount = incl;
+    }
+    __syncthreads();
+    // sweep their points, a tile of kBatchU units at a time
+    const int nlist = L.scount;
+    for (int b0 = 0; b0 < nlist; b0 += kBatchU) {
+      const int nbu = min(kBatchU, nlist - b0);
+      const int cntp = nbu * kUnit;
+      __syncthreads();
+      for (int t = threadIdx.x; t < cntp; t += kBlock) {
+        const int64_t sl = int64_t(L.slist[b0 + t / kUnit]) * kUnit + (t % kUnit);
+        L.tile[t] = sl < slot_end ? pos4[sl] : make_float4(0.f, 0.f, 0.f, -3.0e38f);
+      }
+      __syncthreads();
+      if (kArg) {
+        for (int u = 0; u < nbu; ++u) {
+          const int32_t base = L.slist[b0 + u] * kUnit;
+          for (int j = 0; j < kUnit; ++j) {
+            const float4 P = L.tile[u * kUnit + j];
+#pragma unroll
+            for (int k = 0; k < QPL; ++k) {
+              const float a = fmaf(qz[k], P.z, fmaf(qy[k], P.y, fmaf(qx[k], P.x, P.w)));
+              if (a > acc[k]) { acc[k] = a; ix[k] = base + j; }
+            }
+          }
+        }
+      } else {
+        for (int j = 0; j < cntp; j += 2) {
+          const float4 P0 = L.tile[j], P1 = L.tile[j + 1];
+#pragma unroll
+          for (int k = 0; k < QPL; ++k) {
+            const float a0 = fmaf(qz[k], P0.z, fmaf(qy[k], P0.y, fmaf(qx[k], P0.x, P0.w)));
+            const float a1 = fmaf(qz[k], P1.z, fmaf(qy[k], P1.y, fmaf(qx[k], P1.x, P1.w)));
+            acc[k] = fmaxf(acc[k], fmaxf(a0, a1));
+          }
+        }
+      }
+    }
+  }
+}
+
+}  // namespace pts

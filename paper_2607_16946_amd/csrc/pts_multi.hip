@@ -6,40 +6,33 @@
 // split count is a function of its cloud's N only, and a query's sums depend
 // only on the split and tile boundaries, so a request gets bit-identical
 // results whether it is launched alone or packed with others.
-#include "pts_device.h"
+#include "pts_farcull.h"
 #include "pts_multi.h"
 
 namespace pts {
 namespace {
 
 constexpr int kQpl = 2;
-constexpr int kChunkU = 256;              // units whose bounds are staged in LDS at once
-constexpr int kBatchU = kTile1 / kUnit;   // units per LDS tile of points
 constexpr int kSampleU = 64;              // units of the whole cloud that seed the lower bound
 
-// Farthest point per query and point split, culled exactly as the
-// single-request sweep but within the split: with LB <= M the largest
-// distance from the query to the extreme points of a fixed sample of the
-// cloud's units and of this split's units, only the split's units whose
-// bounding sphere can reach LB (1 - 1e-5) for some query of the workgroup are
-// swept.  A split may then miss its own maximum, but never the cloud's: the
-// unit holding the farthest point is always swept, with the same arithmetic as
-// a full sweep, and the blend reads only the maximum over splits, so M is
-// bitwise that of a full sweep.
+// Farthest point per query and point split, culled (pts_farcull.h) within
+// the split: the lower bound comes from the extreme points of a fixed sample
+// of the cloud's units and of the split's own units, and only the split's
+// units that can reach it are swept.  A split may then miss its own maximum,
+// but never the cloud's: the unit holding the farthest point is always swept,
+// with the same arithmetic as a full sweep, and the blend reads only the
+// maximum over splits, so M is bitwise that of a full sweep.
 __global__ __launch_bounds__(kBlock) void k_far_multi(const WorkDesc* __restrict__ descs) {
-  __shared__ float4 sb[kChunkU];
-  __shared__ uint32_t smask[kChunkU / 32];
-  __shared__ int32_t slist[kChunkU];
-  __shared__ int32_t scount;
-  __shared__ float4 tile[kTile1];
+  __shared__ FarLds L;
   const WorkDesc d = descs[blockIdx.x];
   const Header* h = reinterpret_cast<const Header*>(d.rec);
   const int64_t N = h->N, Q = d.Q;
-  const Layout L(N);
+  const Layout lay(N);
   const float4* pos4 = reinterpret_cast<const float4*>(d.rec + d.pos_off);
-  const float4* ub = reinterpret_cast<const float4*>(d.rec + L.ub);
-  const int64_t U = L.nunit;
+  const float4* ub = reinterpret_cast<const float4*>(d.rec + lay.ub);
+  const int64_t U = lay.nunit;
   float qx[kQpl], qy[kQpl], qz[kQpl], acc[kQpl], lb[kQpl];
+  int32_t ix[kQpl];
   bool ok[kQpl];
 #pragma unroll
   for (int k = 0; k < kQpl; ++k) {
@@ -47,6 +40,7 @@ __global__ __launch_bounds__(kBlock) void k_far_multi(const WorkDesc* __restrict
     qx[k] = qi.x; qy[k] = qi.y; qz[k] = qi.z;
     ok[k] = qi.valid;
     acc[k] = -3.0e38f;
+    ix[k] = -1;
     lb[k] = -1.f;
   }
   const int64_t beg = int64_t(d.split) * d.per_split;
@@ -55,84 +49,11 @@ __global__ __launch_bounds__(kBlock) void k_far_multi(const WorkDesc* __restrict
   // 1. lower bound: extreme points of every stride-th unit, then of the split's units
   const int64_t stride = (U + kSampleU - 1) / kSampleU;
   const int64_t n_samp = (U + stride - 1) / stride;
-  const int64_t n_lb = n_samp + (u_hi - u_lo);
-  for (int64_t c0 = 0; c0 < n_lb; c0 += kChunkU) {
-    const int cnt = int(min<int64_t>(kChunkU, n_lb - c0));
-    __syncthreads();
-    for (int j = threadIdx.x; j < cnt; j += kBlock) {
-      const int64_t i = c0 + j;
-      sb[j] = ub[2 * (i < n_samp ? i * stride : u_lo + (i - n_samp)) + 1];
-    }
-    __syncthreads();
-    for (int j = 0; j < cnt; ++j) {
-      const float4 E = sb[j];
-#pragma unroll
-      for (int k = 0; k < kQpl; ++k) {
-        const float dx = qx[k] - E.x, dy = qy[k] - E.y, dz = qz[k] - E.z;
-        lb[k] = fmaxf(lb[k], fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
-      }
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < kQpl; ++k) {
-    ok[k] = ok[k] && lb[k] >= 0.f;              // a query with a NaN coordinate needs no unit: M is NaN
-    lb[k] = sqrtf(fmaxf(lb[k], 0.f)) * (1.f - 1e-5f);
-  }
-  // 2./3. per chunk of the split's units: mark the needed ones, list them, sweep their points
-  for (int64_t c0 = u_lo; c0 < u_hi; c0 += kChunkU) {
-    const int cnt = int(min<int64_t>(kChunkU, u_hi - c0));
-    __syncthreads();
-    for (int j = threadIdx.x; j < cnt; j += kBlock) sb[j] = ub[2 * (c0 + j)];
-    for (int j = threadIdx.x; j < kChunkU / 32; j += kBlock) smask[j] = 0u;
-    __syncthreads();
-    for (int j = 0; j < cnt; ++j) {
-      const float4 C = sb[j];
-      bool need = false;
-#pragma unroll
-      for (int k = 0; k < kQpl; ++k) {
-        const float t = lb[k] - C.w;
-        const float dx = qx[k] - C.x, dy = qy[k] - C.y, dz = qz[k] - C.z;
-        const float dc2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        need = need || (ok[k] && (t <= 0.f || !(dc2 < t * t)));
-      }
-      if (__ballot(need) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&smask[j >> 5], 1u << (j & 31));
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {  // ascending list of the needed units (first wave)
-      const int w = int(threadIdx.x);
-      const uint32_t bits = w < kChunkU / 32 ? smask[w] : 0u;
-      const int pc = __popc(bits);
-      int incl = pc;
-      for (int o = 1; o < 64; o <<= 1) {
-        const int t = __shfl_up(incl, o);
-        if (w >= o) incl += t;
-      }
-      int pos = incl - pc;
-      for (uint32_t b = bits; b != 0u; b &= b - 1u) slist[pos++] = int32_t(c0) + w * 32 + (__ffs(b) - 1);
-      if (w == 63) scount = incl;
-    }
-    __syncthreads();
-    const int nlist = scount;
-    for (int b0 = 0; b0 < nlist; b0 += kBatchU) {
-      const int nbu = min(kBatchU, nlist - b0);
-      const int cntp = nbu * kUnit;
-      __syncthreads();
-      for (int t = threadIdx.x; t < cntp; t += kBlock) {
-        const int64_t sl = int64_t(slist[b0 + t / kUnit]) * kUnit + (t % kUnit);
-        tile[t] = sl < end ? pos4[sl] : make_float4(0.f, 0.f, 0.f, -3.0e38f);
-      }
-      __syncthreads();
-      for (int j = 0; j < cntp; j += 2) {
-        const float4 P0 = tile[j], P1 = tile[j + 1];
-#pragma unroll
-        for (int k = 0; k < kQpl; ++k) {
-          const float a0 = fmaf(qz[k], P0.z, fmaf(qy[k], P0.y, fmaf(qx[k], P0.x, P0.w)));
-          const float a1 = fmaf(qz[k], P1.z, fmaf(qy[k], P1.y, fmaf(qx[k], P1.x, P1.w)));
-          acc[k] = fmaxf(acc[k], fmaxf(a0, a1));
-        }
-      }
-    }
-  }
+  far_bound<kQpl>(ub, n_samp + (u_hi - u_lo),
+                  [=](int64_t i) { return i < n_samp ? i * stride : u_lo + (i - n_samp); }, qx, qy, qz, lb, L);
+  far_threshold<kQpl>(lb, ok);
+  // 2./3. the split's units that can reach it
+  far_sweep<kQpl, false>(pos4, ub, u_lo, u_hi, end, qx, qy, qz, ok, lb, acc, ix, L);
 #pragma unroll
   for (int k = 0; k < kQpl; ++k) {
     const int64_t q = int64_t(d.qb) * (kBlock * kQpl) + k * kBlock + threadIdx.x;
