@@ -72,6 +72,69 @@ __global__ __launch_bounds__(kBlock) void k_far_cull(const Header* __restrict__ 
   }
 }
 
+// The same sweep for calls with few query blocks, over the blend's point
+// splits as well: workgroup b covers split b % S of query block b / S, with
+// the bound of pts_farcull.h's far_bound_split, and writes row `split` of
+// far2 (and farix).  A split may miss its own maximum but never the cloud's;
+// k_far_fold keeps the largest row and, among equal ones, the first split
+// (the lowest slots), so row 0 ends up bitwise what k_far_cull writes.
+template <int QPL, bool kArg>
+__global__ __launch_bounds__(kBlock) void k_far_split(const Header* __restrict__ h, const float4* __restrict__ pos4,
+                                                      const float4* __restrict__ ub, const float* __restrict__ x,
+                                                      int64_t Q, int S, int64_t per_split, float* __restrict__ far2,
+                                                      int32_t* __restrict__ farix) {
+  __shared__ FarLds L;
+  const int split = int(blockIdx.x % unsigned(S));
+  const int64_t qb = blockIdx.x / unsigned(S);
+  const int64_t N = h->N;
+  const int64_t U = (N + kUnit - 1) / kUnit;
+  float qx[QPL], qy[QPL], qz[QPL], acc[QPL], lb[QPL];
+  int32_t ix[QPL];
+  bool ok[QPL];
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) {
+    const QueryIn qi = load_query(x, qb * (kBlock * QPL) + k * kBlock + threadIdx.x, Q, h);
+    qx[k] = qi.x; qy[k] = qi.y; qz[k] = qi.z;
+    ok[k] = qi.valid;
+    acc[k] = -3.0e38f;
+    ix[k] = -1;
+    lb[k] = -1.f;
+  }
+  const int64_t beg = int64_t(split) * per_split;
+  const int64_t end = min(N, beg + per_split);
+  const int64_t u_lo = beg / kUnit, u_hi = max(u_lo, (end + kUnit - 1) / kUnit);
+  far_bound_split<QPL>(ub, U, u_lo, u_hi, qx, qy, qz, lb, L);
+  far_threshold<QPL>(lb, ok);
+  far_sweep<QPL, kArg>(pos4, ub, u_lo, u_hi, end, qx, qy, qz, ok, lb, acc, ix, L);
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) {
+    const int64_t q = qb * (kBlock * QPL) + k * kBlock + threadIdx.x;
+    if (q < Q) {
+      far2[int64_t(split) * Q + q] = acc[k] + fmaf(qz[k], qz[k], fmaf(qy[k], qy[k], qx[k] * qx[k]));
+      if (kArg) farix[int64_t(split) * Q + q] = ix[k];
+    }
+  }
+}
+
+// Rows 1..S-1 of far2 (and farix) folded into row 0: the largest value, the
+// first row among equal ones (a NaN row 0 stays).
+__global__ __launch_bounds__(kBlock) void k_far_fold(float* __restrict__ far2, int32_t* __restrict__ farix, int S,
+                                                     int64_t Q) {
+  const int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (q >= Q) return;
+  float m = far2[q];
+  int32_t ix = farix ? farix[q] : -1;
+  for (int s = 1; s < S; ++s) {
+    const float v = far2[int64_t(s) * Q + q];
+    if (v > m) {
+      m = v;
+      if (farix) ix = farix[int64_t(s) * Q + q];
+    }
+  }
+  far2[q] = m;
+  if (farix) farix[q] = ix;
+}
+
 // ---------------------------------------------------------------------------
 // Sweep 2: partial (sum w g, sum w) per split.
 // ---------------------------------------------------------------------------
@@ -161,9 +224,15 @@ __global__ __launch_bounds__(kBlock) void k_combine(const float2* __restrict__ p
 
 template <int QPL, bool kArg>
 void launch_far_q(const Header* h, const float4* pos4, const float4* ub, const float* x, int64_t Q, int64_t nqb,
-                  float* far2, int32_t* farix, hipStream_t st) {
-  hipLaunchKernelGGL((k_far_cull<QPL, kArg>), dim3(unsigned(nqb)), dim3(kBlock), 0, st, h, pos4, ub, x, Q, far2,
-                     farix);
+                  int S, int64_t per_split, float* far2, int32_t* farix, hipStream_t st) {
+  if (S > 1) {
+    hipLaunchKernelGGL((k_far_split<QPL, kArg>), dim3(unsigned(nqb * S)), dim3(kBlock), 0, st, h, pos4, ub, x, Q, S,
+                       per_split, far2, farix);
+    hipLaunchKernelGGL(k_far_fold, dim3(unsigned((Q + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, far2, farix, S, Q);
+  } else {
+    hipLaunchKernelGGL((k_far_cull<QPL, kArg>), dim3(unsigned(nqb)), dim3(kBlock), 0, st, h, pos4, ub, x, Q, far2,
+                       farix);
+  }
 }
 
 template <int QPL>
@@ -202,7 +271,7 @@ WsView ws_view(const Plan& plan, int64_t Q, void* ws) {
 }
 
 int launch_far_cull(const void* rec, int64_t N, const float* x, int64_t Q, int qpl, float* far2, int32_t* farix,
-                    hipStream_t st) {
+                    hipStream_t st, int S, int64_t per_split) {
   const Layout L(N);
   const char* base = static_cast<const char*>(rec);
   const Header* h = reinterpret_cast<const Header*>(base);
@@ -213,17 +282,20 @@ int launch_far_cull(const void* rec, int64_t N, const float* x, int64_t Q, int q
   int q = qpl >= 4 ? 4 : (qpl == 2 ? 2 : 1);
   while (q > 1 && (Q + int64_t(kBlock) * q - 1) / (int64_t(kBlock) * q) < 2048) q /= 2;
   const int64_t nqb = (Q + int64_t(kBlock) * q - 1) / (int64_t(kBlock) * q);
+  // with fewer than 1024 query blocks, sweep the point splits as separate
+  // workgroups (the caller's far2 / farix then hold S rows)
+  if (nqb >= 1024 || per_split <= 0) S = 1;
   if (farix) {
     switch (q) {
-      case 1: launch_far_q<1, true>(h, pos4, ub, x, Q, nqb, far2, farix, st); break;
-      case 2: launch_far_q<2, true>(h, pos4, ub, x, Q, nqb, far2, farix, st); break;
-      default: launch_far_q<4, true>(h, pos4, ub, x, Q, nqb, far2, farix, st); break;
+      case 1: launch_far_q<1, true>(h, pos4, ub, x, Q, nqb, S, per_split, far2, farix, st); break;
+      case 2: launch_far_q<2, true>(h, pos4, ub, x, Q, nqb, S, per_split, far2, farix, st); break;
+      default: launch_far_q<4, true>(h, pos4, ub, x, Q, nqb, S, per_split, far2, farix, st); break;
     }
   } else {
     switch (q) {
-      case 1: launch_far_q<1, false>(h, pos4, ub, x, Q, nqb, far2, nullptr, st); break;
-      case 2: launch_far_q<2, false>(h, pos4, ub, x, Q, nqb, far2, nullptr, st); break;
-      default: launch_far_q<4, false>(h, pos4, ub, x, Q, nqb, far2, nullptr, st); break;
+      case 1: launch_far_q<1, false>(h, pos4, ub, x, Q, nqb, S, per_split, far2, nullptr, st); break;
+      case 2: launch_far_q<2, false>(h, pos4, ub, x, Q, nqb, S, per_split, far2, nullptr, st); break;
+      default: launch_far_q<4, false>(h, pos4, ub, x, Q, nqb, S, per_split, far2, nullptr, st); break;
     }
   }
   return check_hip(hipGetLastError(), "farthest-point kernel");
@@ -231,7 +303,7 @@ int launch_far_cull(const void* rec, int64_t N, const float* x, int64_t Q, int q
 
 int launch_far(const void* rec, int64_t N, const float* x, int64_t Q, const Plan& plan, const WsView& ws,
                hipStream_t st) {
-  return launch_far_cull(rec, N, x, Q, plan.qpl, ws.far2, nullptr, st);
+  return launch_far_cull(rec, N, x, Q, plan.qpl, ws.far2, nullptr, st, plan.S, plan.per_split);
 }
 
 int launch_blend(const void* rec, int64_t N, const float* x, int64_t Q, float C, const Plan& plan,

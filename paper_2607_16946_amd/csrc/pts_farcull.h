@@ -17,6 +17,7 @@ namespace pts {
 
 constexpr int kChunkU = 256;             // units whose bounds are staged in LDS at once
 constexpr int kBatchU = kTile1 / kUnit;  // units per LDS tile of points
+constexpr int kSampleU = 64;             // units sampled across a cloud when a sweep covers one point split
 
 // LDS of one workgroup's culled sweep.
 struct FarLds {
@@ -47,6 +48,19 @@ __device__ __forceinline__ void far_bound(const float4* __restrict__ ub, int64_t
       }
     }
   }
+}
+
+// The bound of a sweep over the point split [beg, end) of a cloud of U
+// units: the extreme points of every stride-th unit (kSampleU of them) and of
+// the split's own units [u_lo, u_hi).
+template <int QPL>
+__device__ __forceinline__ void far_bound_split(const float4* __restrict__ ub, int64_t U, int64_t u_lo, int64_t u_hi,
+                                                const float (&qx)[QPL], const float (&qy)[QPL],
+                                                const float (&qz)[QPL], float (&lb)[QPL], FarLds& L) {
+  const int64_t stride = (U + kSampleU - 1) / kSampleU;
+  const int64_t n_samp = (U + stride - 1) / stride;
+  far_bound<QPL>(ub, n_samp + (u_hi - u_lo),
+                 [=](int64_t i) { return i < n_samp ? i * stride : u_lo + (i - n_samp); }, qx, qy, qz, lb, L);
 }
 
 // The squared bound becomes the cull threshold LB (1 - 1e-5); a query with a

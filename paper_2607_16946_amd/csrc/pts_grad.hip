@@ -201,7 +201,7 @@ void launch_grad_sweep(const Header* h, const float4* rec, const float* x, int64
 
 int launch_far_arg(const void* rec, int64_t N, const float* x, int64_t Q, const Plan& plan, const WsView& ws,
                    hipStream_t st) {
-  return launch_far_cull(rec, N, x, Q, plan.qpl, ws.far2, ws.farix, st);
+  return launch_far_cull(rec, N, x, Q, plan.qpl, ws.far2, ws.farix, st, plan.S, plan.per_split);
 }
 
 int launch_combine_stats(const void* rec, int64_t N, const float* x, int64_t Q, const Plan& plan, const WsView& ws,

@@ -158,9 +158,12 @@ int launch_radius_prepare(void* rec, int64_t N, float C, hipStream_t st);
 int launch_eval_radius(const void* rec, int64_t N, const float* x, int64_t Q, float* sdf, int32_t* count,
                        hipStream_t st);
 // Farthest-point sweep (culled by units): M^2 per query into far2[Q] and, if
-// farix is non-null, the first slot attaining it into farix[Q].
+// farix is non-null, the first slot attaining it into farix[Q].  With S > 1
+// and per_split > 0 (an evaluation plan's point split) a call with few query
+// blocks also sweeps the splits as separate workgroups; far2 and farix must
+// then hold S rows of Q, and row 0 gets the result (bitwise the same).
 int launch_far_cull(const void* rec, int64_t N, const float* x, int64_t Q, int qpl, float* far2, int32_t* farix,
-                    hipStream_t st);
+                    hipStream_t st, int S = 1, int64_t per_split = 0);
 int launch_far(const void* rec, int64_t N, const float* x, int64_t Q, const Plan& plan, const WsView& ws,
                hipStream_t st);
 int launch_blend(const void* rec, int64_t N, const float* x, int64_t Q, float C, const Plan& plan,

@@ -13,8 +13,6 @@ namespace pts {
 namespace {
 
 constexpr int kQpl = 2;
-constexpr int kSampleU = 64;              // units of the whole cloud that seed the lower bound
-
 // Farthest point per query and point split, culled (pts_farcull.h) within
 // the split: the lower bound comes from the extreme points of a fixed sample
 // of the cloud's units and of the split's own units, and only the split's
@@ -46,11 +44,8 @@ __global__ __launch_bounds__(kBlock) void k_far_multi(const WorkDesc* __restrict
   const int64_t beg = int64_t(d.split) * d.per_split;
   const int64_t end = min(N, beg + d.per_split);
   const int64_t u_lo = beg / kUnit, u_hi = max(u_lo, (end + kUnit - 1) / kUnit);
-  // 1. lower bound: extreme points of every stride-th unit, then of the split's units
-  const int64_t stride = (U + kSampleU - 1) / kSampleU;
-  const int64_t n_samp = (U + stride - 1) / stride;
-  far_bound<kQpl>(ub, n_samp + (u_hi - u_lo),
-                  [=](int64_t i) { return i < n_samp ? i * stride : u_lo + (i - n_samp); }, qx, qy, qz, lb, L);
+  // 1. lower bound: extreme points of sampled units and of the split's units
+  far_bound_split<kQpl>(ub, U, u_lo, u_hi, qx, qy, qz, lb, L);
   far_threshold<kQpl>(lb, ok);
   // 2./3. the split's units that can reach it
   far_sweep<kQpl, false>(pos4, ub, u_lo, u_hi, end, qx, qy, qz, ok, lb, acc, ix, L);
