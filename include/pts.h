@@ -144,7 +144,7 @@ int pts_cloud_decode(const void* rec, int64_t N, float* out, void* stream);
 
 /* Launch plan pts_eval uses for N points and Q queries (a pure function of N,
  * Q and the parameters): queries per lane, number of point splits, and points
- * per split (a multiple of 512; splits * per_split >= N, every split
+ * per split (a multiple of 128; splits * per_split >= N, every split
  * non-empty).  For inspection and tests; host only. */
 int pts_eval_plan(int64_t N, int64_t Q, const pts_params* prm, int* qpl, int* splits,
                   int64_t* per_split);

@@ -58,20 +58,21 @@ Plan make_plan(int64_t N, int64_t Q, const pts_params* prm) {
     if (v == 1 || v == 2 || v == 4 || v == 8) p.qpl = v;
   }
   p.nqb = (Q + int64_t(kBlock) * p.qpl - 1) / (int64_t(kBlock) * p.qpl);
-  const int64_t tiles = (N + kTile1 - 1) / kTile1;
+  const int64_t tiles = (N + kTile1 - 1) / kTile1;   // farthest-point tiles
+  const int64_t gran = (N + kTile2 - 1) / kTile2;    // blend tiles: the split granularity
   int S;
   if (prm && prm->splits > 0) {
     S = prm->splits;
   } else {
-    // one split per XCD when there are enough points; more splits while the
-    // grid is too small to fill 256 CUs and each split keeps >= 2 tiles
+    // one split per XCD when there are enough points (each split >= 2
+    // farthest-point tiles); more splits while the grid is too small to fill
+    // 256 CUs, down to 2 blend tiles per split
     S = 1;
     while (S < 8 && tiles >= int64_t(2) * S * 2) S *= 2;
-    while (S < 64 && p.nqb * S < 2048 && tiles >= int64_t(2) * S * 2) S *= 2;
+    while (S < 64 && p.nqb * S < 2048 && gran >= int64_t(2) * S * 2) S *= 2;
   }
-  S = int(std::max<int64_t>(1, std::min<int64_t>(S, tiles)));
-  const int64_t tiles_per = (tiles + S - 1) / S;
-  p.per_split = tiles_per * kTile1;
+  S = int(std::max<int64_t>(1, std::min<int64_t>(S, gran)));
+  p.per_split = (gran + S - 1) / S * kTile2;
   // splits that would start past the last point are dropped; the remaining
   // S * per_split >= N cover every point
   p.S = int((N + p.per_split - 1) / p.per_split);

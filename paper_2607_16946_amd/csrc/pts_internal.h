@@ -99,7 +99,7 @@ struct Layout {
 struct Plan {
   int qpl;            // queries per lane
   int S;              // point splits
-  int64_t per_split;  // points per split (multiple of kTile1)
+  int64_t per_split;  // points per split (multiple of kTile2)
   int64_t nqb;        // query blocks of kBlock * qpl queries
 };
 Plan make_plan(int64_t N, int64_t Q, const pts_params* prm);
