@@ -144,10 +144,12 @@ __global__ __launch_bounds__(kBlock) void k_backp(const Header* __restrict__ h, 
         kap = qk[j];
       }
       const float dx = X.x - P.x, dy = X.y - P.y, dz = X.z - P.z;
-      const float d = hw_sqrt(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+      const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+      const float id = safe_rsq(d2);                     // 1/d (both variants form d alike)
+      const float d = d2 * id;
       const float coef = hw_exp2(fmaf(d, X.w, C2)) * kap;
       const Geo r = direct ? geo_direct(X.x, X.y, X.z, U, Mv, K, G) : geo_anchored(X.x, X.y, X.z, P.w, U, Mv, K, G);
-      const float iq = safe_rcp(r.qn), ir = safe_rcp(r.rho);
+      const float iq = r.iqn, ir = r.irho;
       const float sq = G.z * iq;                       // sign / |q|
       const float bir = r.b * ir;                      // b / rho
       const float L = P.w, zr = G.y;                   // L, zeta r
@@ -162,7 +164,7 @@ __global__ __launch_bounds__(kBlock) void k_backp(const Header* __restrict__ h, 
       t[6] = fmaf(-c1, r.b * delta * ir, t[6]);                  // dg/dL
       t[7] = fmaf(coef, G.z * fmaf(copysignf(1.f, zr), r.b * iq, -1.f), t[7]);  // dg/dr
       if (kW) {  // weight: (w/W) lambda (g - phi) e, e = (x - p)/d
-        const float c3 = coef * lam * (r.g - phi) * safe_rcp(d);
+        const float c3 = coef * lam * (r.g - phi) * id;
         t[8] = fmaf(c3, dx, t[8]);
         t[9] = fmaf(c3, dy, t[9]);
         t[10] = fmaf(c3, dz, t[10]);

@@ -8,6 +8,14 @@ namespace pts {
 __device__ __forceinline__ float hw_sqrt(float v) { return __builtin_amdgcn_sqrtf(v); }
 __device__ __forceinline__ float hw_exp2(float v) { return __builtin_amdgcn_exp2f(v); }
 __device__ __forceinline__ float hw_rcp(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ __forceinline__ float hw_rsq(float v) { return __builtin_amdgcn_rsqf(v); }
+
+// 1/sqrt(v) for v > 1e-30, else 0.  With it, v * safe_rsq(v) is sqrt(v) (0 for
+// v <= 1e-30, i.e. below 1e-15) and a factor 1/sqrt(v) it supplies vanishes
+// there (the subgradient convention at a torus's axis, its core circle and a
+// query on a point): one transcendental gives a length and its reciprocal.
+// The cut stays clear of FP32 denormals, which the hardware flushes to 0.
+__device__ __forceinline__ float safe_rsq(float v) { return v > 1e-30f ? hw_rsq(v) : 0.f; }
 
 struct QueryIn {
   float x, y, z;
@@ -76,9 +84,10 @@ __device__ __forceinline__ float g_anchored(float x, float y, float z, float L, 
 }
 
 // Torus quantities of one pair needed by the derivatives: g, the components
-// (vu, vm, vk) of x - c in the frame (u, m, k), rho, b = rho - R and |q|.
+// (vu, vm, vk) of x - c in the frame (u, m, k), rho, b = rho - R, |q|, and
+// 1/rho, 1/|q| (0 where rho, |q| vanish; rho and |q| from safe_rsq).
 struct Geo {
-  float g, vu, vm, vk, rho, b, qn;
+  float g, vu, vm, vk, rho, b, qn, irho, iqn;
 };
 
 __device__ __forceinline__ Geo geo_direct(float x, float y, float z, const float4& U, const float4& Mv,
@@ -87,9 +96,13 @@ __device__ __forceinline__ Geo geo_direct(float x, float y, float z, const float
   r.vu = fmaf(z, U.z, fmaf(y, U.y, fmaf(x, U.x, U.w)));
   r.vm = fmaf(z, Mv.z, fmaf(y, Mv.y, fmaf(x, Mv.x, Mv.w)));
   r.vk = fmaf(z, K.z, fmaf(y, K.y, fmaf(x, K.x, K.w)));
-  r.rho = hw_sqrt(fmaf(r.vm, r.vm, r.vk * r.vk));
+  const float rho2 = fmaf(r.vm, r.vm, r.vk * r.vk);
+  r.irho = safe_rsq(rho2);
+  r.rho = rho2 * r.irho;
   r.b = r.rho - G.x;
-  r.qn = hw_sqrt(fmaf(r.b, r.b, r.vu * r.vu));
+  const float qn2 = fmaf(r.b, r.b, r.vu * r.vu);
+  r.iqn = safe_rsq(qn2);
+  r.qn = qn2 * r.iqn;
   r.g = fmaf(G.z, r.qn, G.w);
   return r;
 }
@@ -102,12 +115,16 @@ __device__ __forceinline__ Geo geo_anchored(float x, float y, float z, float L, 
   r.vk = fmaf(z, K.z, fmaf(y, K.y, fmaf(x, K.x, K.w)));
   r.vm = ym + L;
   const float yk2 = r.vk * r.vk;
-  r.rho = hw_sqrt(fmaf(r.vm, r.vm, yk2));
+  const float rho2 = fmaf(r.vm, r.vm, yk2);
+  r.irho = safe_rsq(rho2);
+  r.rho = rho2 * r.irho;
   const float alpha = fmaf(ym, r.vm + L, yk2);
   const float beta = alpha * hw_rcp(r.rho + L);
   r.b = beta + G.y;
   const float yu2 = r.vu * r.vu;
-  r.qn = hw_sqrt(fmaf(r.b, r.b, yu2));
+  const float qn2 = fmaf(r.b, r.b, yu2);
+  r.iqn = safe_rsq(qn2);
+  r.qn = qn2 * r.iqn;
   const float num = fmaf(beta, r.b + G.y, yu2);
   r.g = num * hw_rcp(fmaf(G.z, r.qn, -G.w));
   return r;

@@ -70,13 +70,15 @@ __device__ __forceinline__ void grad_pair(float qx, float qy, float qz, float nl
                                           const float4& P, const float4& U, const float4& Mv, const float4& K,
                                           const float4& G, float* A, float* B, float& D) {
   const float dx = qx - P.x, dy = qy - P.y, dz = qz - P.z;
-  const float d = hw_sqrt(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+  const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+  const float id = safe_rsq(d2);                   // 1/d (both variants form d alike)
+  const float d = d2 * id;
   const float w = hw_exp2(fmaf(d, nl, C2));
   const Geo r = kDirect ? geo_direct(qx, qy, qz, U, Mv, K, G) : geo_anchored(qx, qy, qz, P.w, U, Mv, K, G);
   const float we = w * (r.g - phi);
   if (kFull) {
-    const float sq = G.z * safe_rcp(r.qn);
-    const float f1 = sq * r.b * safe_rcp(r.rho);
+    const float sq = G.z * r.iqn;
+    const float f1 = sq * r.b * r.irho;
     const float f2 = sq * r.vu;
     const float a1 = f1 * r.vm, a2 = f1 * r.vk;
     const float gx = fmaf(a1, Mv.x, fmaf(a2, K.x, f2 * U.x));
@@ -85,7 +87,7 @@ __device__ __forceinline__ void grad_pair(float qx, float qy, float qz, float nl
     A[0] = fmaf(w, gx, A[0]);
     A[1] = fmaf(w, gy, A[1]);
     A[2] = fmaf(w, gz, A[2]);
-    const float c = we * safe_rcp(d);
+    const float c = we * id;
     B[0] = fmaf(c, dx, B[0]);
     B[1] = fmaf(c, dy, B[1]);
     B[2] = fmaf(c, dz, B[2]);

@@ -57,11 +57,13 @@ __device__ __forceinline__ void lap_pair(float qx, float qy, float qz, float nl,
                                          float ex, float ey, float ez, const float4& P, const float4& U,
                                          const float4& Mv, const float4& K, const float4& G, float* a) {
   const float dx = qx - P.x, dy = qy - P.y, dz = qz - P.z;
-  const float d = hw_sqrt(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+  const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+  const float id = safe_rsq(d2);                                    // 1/d
+  const float d = d2 * id;
   const float w = hw_exp2(fmaf(d, nl, C2));
   const Geo r = kDirect ? geo_direct(qx, qy, qz, U, Mv, K, G) : geo_anchored(qx, qy, qz, P.w, U, Mv, K, G);
-  const float sq = G.z * safe_rcp(r.qn);
-  const float bir = r.b * safe_rcp(r.rho);
+  const float sq = G.z * r.iqn;
+  const float bir = r.b * r.irho;
   const float f1 = sq * bir;
   const float f2 = sq * r.vu;
   const float a1 = f1 * r.vm, a2 = f1 * r.vk;
@@ -69,7 +71,6 @@ __device__ __forceinline__ void lap_pair(float qx, float qy, float qz, float nl,
   const float gy = fmaf(a1, Mv.y, fmaf(a2, K.y, f2 * U.y));
   const float gz = fmaf(a1, Mv.z, fmaf(a2, K.z, f2 * U.z));
   const float lapg = sq * (1.f + bir);
-  const float id = safe_rcp(d);
   const float ux = dx * id, uy = dy * id, uz = dz * id;            // e
   const float gdote = fmaf(gx, ux, fmaf(gy, uy, gz * uz));          // grad g . e
   const float gdots = fmaf(gx, ex, fmaf(gy, ey, gz * ez));          // grad g . e_*
