@@ -71,27 +71,32 @@ __device__ __forceinline__ void grad_pair(float qx, float qy, float qz, float nl
                                           const float4& G, float* A, float* B, float& D) {
   const float dx = qx - P.x, dy = qy - P.y, dz = qz - P.z;
   const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-  const float id = safe_rsq(d2);                   // 1/d (both variants form d alike)
+  if (!kFull) {  // the weight sweep needs neither reciprocals nor grad g: the blend's forms
+    const float d = hw_sqrt(d2);
+    const float w = hw_exp2(fmaf(d, nl, C2));
+    const float g = kDirect ? g_direct(qx, qy, qz, U, Mv, K, G) : g_anchored(qx, qy, qz, P.w, U, Mv, K, G);
+    D = fmaf(w * (g - phi), d, D);
+    return;
+  }
+  const float id = safe_rsq(d2);                   // 1/d
   const float d = d2 * id;
   const float w = hw_exp2(fmaf(d, nl, C2));
   const Geo r = kDirect ? geo_direct(qx, qy, qz, U, Mv, K, G) : geo_anchored(qx, qy, qz, P.w, U, Mv, K, G);
   const float we = w * (r.g - phi);
-  if (kFull) {
-    const float sq = G.z * r.iqn;
-    const float f1 = sq * r.b * r.irho;
-    const float f2 = sq * r.vu;
-    const float a1 = f1 * r.vm, a2 = f1 * r.vk;
-    const float gx = fmaf(a1, Mv.x, fmaf(a2, K.x, f2 * U.x));
-    const float gy = fmaf(a1, Mv.y, fmaf(a2, K.y, f2 * U.y));
-    const float gz = fmaf(a1, Mv.z, fmaf(a2, K.z, f2 * U.z));
-    A[0] = fmaf(w, gx, A[0]);
-    A[1] = fmaf(w, gy, A[1]);
-    A[2] = fmaf(w, gz, A[2]);
-    const float c = we * id;
-    B[0] = fmaf(c, dx, B[0]);
-    B[1] = fmaf(c, dy, B[1]);
-    B[2] = fmaf(c, dz, B[2]);
-  }
+  const float sq = G.z * r.iqn;
+  const float f1 = sq * r.b * r.irho;
+  const float f2 = sq * r.vu;
+  const float a1 = f1 * r.vm, a2 = f1 * r.vk;
+  const float gx = fmaf(a1, Mv.x, fmaf(a2, K.x, f2 * U.x));
+  const float gy = fmaf(a1, Mv.y, fmaf(a2, K.y, f2 * U.y));
+  const float gz = fmaf(a1, Mv.z, fmaf(a2, K.z, f2 * U.z));
+  A[0] = fmaf(w, gx, A[0]);
+  A[1] = fmaf(w, gy, A[1]);
+  A[2] = fmaf(w, gz, A[2]);
+  const float c = we * id;
+  B[0] = fmaf(c, dx, B[0]);
+  B[1] = fmaf(c, dy, B[1]);
+  B[2] = fmaf(c, dz, B[2]);
   D = fmaf(we, d, D);
 }
 
