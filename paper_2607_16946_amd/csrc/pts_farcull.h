@@ -134,9 +134,11 @@ __device__ __forceinline__ void far_sweep(const float4* __restrict__ pos4, const
           for (int j = 0; j < kUnit; ++j) {
             const float4 P = L.tile[u * kUnit + j];
 #pragma unroll
-            for (int k = 0; k < QPL; ++k) {
+            for (int k = 0; k < QPL; ++k) {  // branch-free: the first slot attaining the maximum
               const float a = fmaf(qz[k], P.z, fmaf(qy[k], P.y, fmaf(qx[k], P.x, P.w)));
-              if (a > acc[k]) { acc[k] = a; ix[k] = base + j; }
+              const bool gt = a > acc[k];
+              acc[k] = gt ? a : acc[k];
+              ix[k] = gt ? base + j : ix[k];
             }
           }
         }
