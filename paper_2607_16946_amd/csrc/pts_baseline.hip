@@ -63,14 +63,18 @@ __global__ __launch_bounds__(kBlock) void k_base(const Header* __restrict__ h, c
 #pragma unroll
       for (int k = 0; k < QPL; ++k) {
         const float dx = qx[k] - P.x, dy = qy[k] - P.y, dz = qz[k] - P.z;
-        const float d = hw_sqrt(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
-        const float w = hw_exp2(fmaf(d, nl[k], C2)) * P.w;
+        const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
         const float t = fmaf(dz, Nv.z, fmaf(dy, Nv.y, dx * Nv.x));
         if (KIND == PTS_BASELINE_SSPD) {
+          const float d = hw_sqrt(d2);
+          const float w = hw_exp2(fmaf(d, nl[k], C2)) * P.w;
           tn[k] = fmaf(w, t, tn[k]);
           td[k] += w;
         } else {
-          const float rd = hw_rcp(d);
+          // d and 1/d from one rsqrt; at d = 0 (rsqrt = inf) d is NaN and so is the sum
+          const float rd = hw_rsq(d2);
+          const float d = d2 * rd;
+          const float w = hw_exp2(fmaf(d, nl[k], C2)) * P.w;
           const float hv = d > 0.f ? fmaf(lam[k], d, 1.f) * t * (rd * rd * rd) * kInv2Pi : __builtin_nanf("");
           tn[k] = fmaf(w, hv, tn[k]);
         }
