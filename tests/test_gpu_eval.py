@@ -187,6 +187,28 @@ def test_split_count_only_changes_rounding():
         assert np.max(np.abs(o - outs[0])) <= TOL_REL * D, S
 
 
+def test_far_sweep_over_splits_is_exact():
+    """A call with few query blocks sweeps the farthest point over the point
+    splits and folds the rows; a call with many sweeps once per query block.
+    The farthest distance M and the farthest point (through e_*) of a query
+    must be the same bits either way (W and phi may differ by rounding: the
+    blend's split count depends on the number of queries)."""
+    cl, _ = synth.mid(N=40000, grid=4)
+    c = _build(cl)
+    lo, hi = synth.padded_bbox(cl.p, 0.1)
+    big = np.random.default_rng(31).uniform(lo, hi, size=(1 << 19, 3)).astype(np.float32)
+    small = big[:3000]
+    assert binding.eval_plan(cl.N, small.shape[0])[1] > 1
+    _, st_small = c(_dev(small), stats=True)
+    _, st_big = c(_dev(big), stats=True)
+    a = st_small.cpu().numpy()
+    b = st_big[:3000].cpu().numpy()
+    _say("far sweep split vs unsplit: M equal", np.array_equal(a[:, 0], b[:, 0]),
+         "e_* equal", np.array_equal(a[:, 3:6], b[:, 3:6]))
+    assert np.array_equal(a[:, 0].view(np.uint32), b[:, 0].view(np.uint32))
+    assert np.array_equal(a[:, 3:6].view(np.uint32), b[:, 3:6].view(np.uint32))
+
+
 def test_deterministic_bitwise():
     cl, x = synth.mid(N=10000, grid=10)
     c = _build(cl)
