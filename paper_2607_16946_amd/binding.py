@@ -165,6 +165,9 @@ def _ptr(t):
 def _dev(t: torch.Tensor, name: str, cols: int | None = None, dtype=torch.float32) -> torch.Tensor:
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.device.index != torch.cuda.current_device():
+        # the library launches on the current device's current stream
+        raise ValueError(f"{name} is on {t.device}, not on the current device cuda:{torch.cuda.current_device()}")
     if t.dtype != dtype:
         raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
     if not t.is_contiguous():
