@@ -239,6 +239,41 @@ def test_degenerate_queries_and_stats():
     assert abs(v[0]) < 1e-6
 
 
+def test_degenerate_clouds():
+    """Coincident points (zero bounding box: D = 1; at the point M = 0 and the
+    weights are uniform), collinear points (zero-extent axes of the spatial
+    sort) and a flat cloud (both curvatures floored, every point in the
+    anchored torus form), each against the oracle."""
+    rng = np.random.default_rng(51)
+    # five copies of one point with different normals and coefficients
+    p = np.repeat(np.array([[0.3, -0.2, 0.1]], np.float32), 5, axis=0)
+    n = rng.normal(size=(5, 3)).astype(np.float32)
+    a = np.zeros((5, 6), np.float32)
+    a[:, 4:6] = rng.uniform(-0.8, -0.2, size=(5, 2))
+    x = np.vstack([p[:1], rng.uniform(-1, 1, size=(200, 3))]).astype(np.float32)
+    cases = {"coincident": synth.Cloud(p, n, a, {})}
+    # points on a line
+    tl = np.linspace(-1, 1, 300, dtype=np.float32)[:, None]
+    pl = (tl * np.array([[0.6, 0.8, 0.0]], np.float32)).astype(np.float32)
+    nl = np.tile(np.array([[0.0, 0.0, 1.0]], np.float32), (300, 1))
+    al = np.zeros((300, 6), np.float32)
+    al[:, 4] = -0.5
+    cases["collinear"] = synth.Cloud(pl, nl, al, {})
+    # a flat square patch with a = 0
+    g = np.stack(np.meshgrid(np.linspace(-1, 1, 40), np.linspace(-1, 1, 40)), -1).reshape(-1, 2)
+    pf = np.c_[g, np.zeros(len(g))].astype(np.float32)
+    nf = np.tile(np.array([[0.0, 0.0, 1.0]], np.float32), (len(g), 1))
+    cases["flat"] = synth.Cloud(pf, nf, np.zeros((len(g), 6), np.float32), {})
+    for name, cl in cases.items():
+        c = _build(cl)
+        if name == "flat":
+            assert c.info().n_anchored == cl.N
+        got = c(_dev(x)).cpu().numpy()
+        ref, _ = _oracle_phi(cl, x)
+        D = max(oracle.bbox_diag(cl.p), 1.0)
+        _check_close(got, ref, D, name)
+
+
 def test_invalid_inputs_rejected():
     cl, _ = synth.tiny(Q=4)
     n = cl.n.copy()
