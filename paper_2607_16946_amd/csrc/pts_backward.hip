@@ -9,12 +9,12 @@
 // conditioned when L is large (nearly flat directions), where moving c and R
 // would cancel to O(1/L^2).  With v = x - c in the frame (vu, vm, vk),
 // rho = |(vm, vk)|, b = rho - R, |q| = |(b, vu)|, g = sign (|q| - r)
-// (Eq. SingleTorusSDF) and delta = rho - vm = vk^2 / (rho + vm) (vm > 0):
+// (Eq. SingleTorusSDF) and delta = rho - vm (= vk^2 / (rho + vm) for vm > 0):
 //   dg/do     = -grad g = -(sign/|q|) (vu, (b/rho) vm, (b/rho) vk)      [frame u, m, k]
 //   dg/domega = -(x - o) x grad g
-//             = (sign/|q|) ( b vk L / rho, -vu vk (1 - b/rho), -vu (L delta + vm zeta r) / rho )
+//             = (sign/|q|) ( b vk L / rho, -vu vk R / rho, -vu (L delta + vm zeta r) / rho )
 //   dg/dL     = -sign b delta / (rho |q|)
-//   dg/dr     =  sign (zeta b / |q| - 1)
+//   dg/dr     =  sign (zeta b / |q| - 1)  (= -sign vu^2 / (|q| (|q| + zeta b)))
 // and dL/dtheta_i = sum_q gout_q (w_qi / W_q) dg_i(x_q)/dtheta_i for theta
 // = a_i, n_i (the weights do not depend on them).  The anchor o = p + a00 n
 // moves rigidly with p, so the torus part of dL/dp_i is the force on o.
@@ -48,6 +48,8 @@
 #include "pts_device.h"
 #include "pts_fit.h"
 
+#include <type_traits>
+
 namespace pts {
 namespace {
 
@@ -77,8 +79,12 @@ __global__ __launch_bounds__(kBlock) void k_qrec(const Header* __restrict__ h, c
   qrec[3 * q + 2] = make_float4(f * st[3], f * st[4], f * st[5], 0.f);
 }
 
+// Occupancy: the coefficient sweep fits 64 VGPRs (8 waves per SIMD, so the
+// 2048-workgroup grid of the differentiation workload is one round); the sweep
+// with the weight terms keeps its 70 at 7 waves (fitting 64 made it spill and
+// ran 8% slower).
 template <bool kW>
-__global__ __launch_bounds__(kBlock) void k_backp(const Header* __restrict__ h, const float4* __restrict__ rec,
+__global__ __launch_bounds__(kBlock, kW ? 7 : 8) void k_backp(const Header* __restrict__ h, const float4* __restrict__ rec,
                                                   const float* __restrict__ x, int64_t Q, int Sq, int64_t per_qs,
                                                   const float* __restrict__ stats, const float* __restrict__ gout,
                                                   const float4* __restrict__ qrec, float C2,
@@ -102,6 +108,7 @@ __global__ __launch_bounds__(kBlock) void k_backp(const Header* __restrict__ h, 
     const float4* r = rec + slot * kRecF4;
     P = r[0]; U = r[1]; Mv = r[2]; K = r[3]; G = r[4];
   }
+  const bool wave_anchored = __ballot(valid && !direct) != 0ull;  // uniform across the wave
   float acc[kStride];
 #pragma unroll
   for (int c = 0; c < kStride; ++c) acc[c] = 0.f;
@@ -134,7 +141,11 @@ __global__ __launch_bounds__(kBlock) void k_backp(const Header* __restrict__ h, 
     float t[kStride];
 #pragma unroll
     for (int c = 0; c < kStride; ++c) t[c] = 0.f;
-    for (int j = 0; j < cnt; ++j) {
+    // One (query j, this lane's point) pair.  kMixed: the wave holds anchored
+    // points (their own torus form, and the cancellation-free rho - vm);
+    // waves of direct points only run the plain instance.
+    auto pair = [&](int j, auto mixed) {
+      constexpr bool kMixed = decltype(mixed)::value;
       const float4 X = qt[j];
       float kap, phi = 0.f, lam = 0.f;
       if (kW) {
@@ -148,27 +159,45 @@ __global__ __launch_bounds__(kBlock) void k_backp(const Header* __restrict__ h, 
       const float id = safe_rsq(d2);                     // 1/d (both variants form d alike)
       const float d = d2 * id;
       const float coef = hw_exp2(fmaf(d, X.w, C2)) * kap;
-      const Geo r = direct ? geo_direct(X.x, X.y, X.z, U, Mv, K, G) : geo_anchored(X.x, X.y, X.z, P.w, U, Mv, K, G);
+      const bool anch = kMixed && !direct;
+      const Geo r = anch ? geo_anchored(X.x, X.y, X.z, P.w, U, Mv, K, G) : geo_direct(X.x, X.y, X.z, U, Mv, K, G);
       const float iq = r.iqn, ir = r.irho;
       const float sq = G.z * iq;                       // sign / |q|
       const float bir = r.b * ir;                      // b / rho
       const float L = P.w, zr = G.y;                   // L, zeta r
-      const float delta = r.vm > 0.f ? r.vk * r.vk * safe_rcp(r.rho + r.vm) : r.rho - r.vm;
+      // rho - vm cancels for vm > 0 near the plane vk = 0; its rounding error, about
+      // eps rho, reaches the derivatives as eps L |vu| (dg/domega) and eps |b|
+      // (dg/dL), which matters only for the large radii of anchored points (L > 4 D):
+      // only they take the cancellation-free form (and its reciprocal)
+      const float delta = anch && r.vm > 0.f ? r.vk * r.vk * safe_rcp(r.rho + r.vm) : r.rho - r.vm;
       const float c1 = coef * sq;
       t[0] = fmaf(-c1, r.vu, t[0]);                              // dg/do along u
       t[1] = fmaf(-c1, bir * r.vm, t[1]);                        //            m
       t[2] = fmaf(-c1, bir * r.vk, t[2]);                        //            k
       t[3] = fmaf(c1, bir * r.vk * L, t[3]);                     // dg/domega along u
-      t[4] = fmaf(-c1, r.vu * r.vk * (1.f - bir), t[4]);         //                m
+      t[4] = fmaf(-c1, r.vu * r.vk * (G.x * ir), t[4]);          //                m (1 - b/rho = R/rho)
       t[5] = fmaf(-c1, r.vu * fmaf(L, delta, r.vm * zr) * ir, t[5]);  //           k
       t[6] = fmaf(-c1, r.b * delta * ir, t[6]);                  // dg/dL
-      t[7] = fmaf(coef, G.z * fmaf(copysignf(1.f, zr), r.b * iq, -1.f), t[7]);  // dg/dr
+      // dg/dr = sign (zeta b / |q| - 1) cancels where zeta b > 0 and |b| >> |vu|;
+      // there it is -sign vu^2 / (|q| (|q| + zeta b)).  Its error is multiplied by
+      // r^2 in dr/dkappa_max, so the anchored points (r up to L) take that form
+      const float zb = copysignf(1.f, zr) * r.b;
+      float dgr = fmaf(zb, iq, -1.f);
+      // (|q| + zeta b as one explicit fma, so that both sweeps round it alike)
+      if (anch && zb > 0.f) dgr = -(r.vu * r.vu) * iq * safe_rcp(fmaf(r.qn2, iq, zb));
+      t[7] = fmaf(coef, G.z * dgr, t[7]);                        // dg/dr
       if (kW) {  // weight: (w/W) lambda (g - phi) e, e = (x - p)/d
         const float c3 = coef * lam * (r.g - phi) * id;
         t[8] = fmaf(c3, dx, t[8]);
         t[9] = fmaf(c3, dy, t[9]);
         t[10] = fmaf(c3, dz, t[10]);
       }
+    };
+    if (wave_anchored) {
+      for (int j = 0; j < cnt; ++j) pair(j, std::true_type{});
+    } else {
+#pragma unroll 1
+      for (int j = 0; j < cnt; ++j) pair(j, std::false_type{});
     }
     if (kW) {  // farthest-point terms of this tile, in query order
       for (int w = 0; w < kQTile / 64; ++w) {

@@ -84,10 +84,10 @@ __device__ __forceinline__ float g_anchored(float x, float y, float z, float L, 
 }
 
 // Torus quantities of one pair needed by the derivatives: g, the components
-// (vu, vm, vk) of x - c in the frame (u, m, k), rho, b = rho - R, |q|, and
-// 1/rho, 1/|q| (0 where rho, |q| vanish; rho and |q| from safe_rsq).
+// (vu, vm, vk) of x - c in the frame (u, m, k), rho, b = rho - R, |q|^2, |q|,
+// and 1/rho, 1/|q| (0 where rho, |q| vanish; rho and |q| from safe_rsq).
 struct Geo {
-  float g, vu, vm, vk, rho, b, qn, irho, iqn;
+  float g, vu, vm, vk, rho, b, qn2, qn, irho, iqn;
 };
 
 __device__ __forceinline__ Geo geo_direct(float x, float y, float z, const float4& U, const float4& Mv,
@@ -100,9 +100,9 @@ __device__ __forceinline__ Geo geo_direct(float x, float y, float z, const float
   r.irho = safe_rsq(rho2);
   r.rho = rho2 * r.irho;
   r.b = r.rho - G.x;
-  const float qn2 = fmaf(r.b, r.b, r.vu * r.vu);
-  r.iqn = safe_rsq(qn2);
-  r.qn = qn2 * r.iqn;
+  r.qn2 = fmaf(r.b, r.b, r.vu * r.vu);
+  r.iqn = safe_rsq(r.qn2);
+  r.qn = r.qn2 * r.iqn;
   r.g = fmaf(G.z, r.qn, G.w);
   return r;
 }
@@ -122,9 +122,9 @@ __device__ __forceinline__ Geo geo_anchored(float x, float y, float z, float L, 
   const float beta = alpha * hw_rcp(r.rho + L);
   r.b = beta + G.y;
   const float yu2 = r.vu * r.vu;
-  const float qn2 = fmaf(r.b, r.b, yu2);
-  r.iqn = safe_rsq(qn2);
-  r.qn = qn2 * r.iqn;
+  r.qn2 = fmaf(r.b, r.b, yu2);
+  r.iqn = safe_rsq(r.qn2);
+  r.qn = r.qn2 * r.iqn;
   const float num = fmaf(beta, r.b + G.y, yu2);
   r.g = num * hw_rcp(fmaf(G.z, r.qn, -G.w));
   return r;
