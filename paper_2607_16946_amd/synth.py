@@ -285,6 +285,29 @@ def torus_cloud(N: int, R: float = 0.6, r: float = 0.25, seed: int = SEED_BASE +
     return Cloud(p, n, a, {"shape": "ring torus", "R": R, "r": r, "seed": seed, "noise": noise}), prim
 
 
+def cap_cloud(N: int = 1400, Q: int = 1500, radius: float = 50.0, seed: int = SEED_BASE + 11):
+    """A nearly flat cloud: N points on the cap |xy| < 1 of a sphere of the given
+    radius (center (0, 0, -radius)), outward normals, and curvatures
+    -(1 +- e)/radius with e ~ U(0.15, 0.3) along s and t (unequal, so no point
+    is umbilic).  Half of the Q queries lie within 0.1 of the cap along the
+    normal, half uniform in its bbox padded by 0.2.  Returns (cloud, queries)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    xy = rng.uniform(-1.0, 1.0, size=(4 * N, 2))
+    xy = xy[np.hypot(xy[:, 0], xy[:, 1]) < 1.0][:N]
+    z = np.sqrt(radius ** 2 - (xy ** 2).sum(axis=1)) - radius
+    p = np.c_[xy, z]
+    n = (p - np.array([0.0, 0.0, -radius])) / radius
+    e = rng.uniform(0.15, 0.3, size=len(p))
+    a = np.zeros((len(p), 6))
+    a[:, 4] = -0.5 / radius * (1.0 + e)     # a02
+    a[:, 5] = -0.5 / radius * (1.0 - e)     # a20
+    k = rng.integers(len(p), size=Q // 2)
+    near = p[k] + n[k] * rng.uniform(-0.1, 0.1, size=(Q // 2, 1))
+    box = rng.uniform(p.min(axis=0) - 0.2, p.max(axis=0) + 0.2, size=(Q - Q // 2, 3))
+    p, n, a, x = _f32(p, n, a, np.r_[near, box])
+    return Cloud(p, n, a, {"shape": "spherical cap", "radius": radius, "seed": seed}), x
+
+
 def tiny(Q: int = 4096, N: int = 4096):
     """Plain method, tiny: N points on the unit sphere, Q queries uniform in [-1.5,1.5]^3."""
     cl = sphere_cloud(N, SEED_BASE + 1)

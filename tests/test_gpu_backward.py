@@ -49,36 +49,15 @@ def _far_decided(p, x):
     return top[:, 1] - top[:, 0] > 1e-5 * top[:, 1]
 
 
-def _cap(N=1400, Q=1500, radius=50.0, seed=11):
-    """Points on a cap (|xy| < 1) of a sphere of radius 50 with slightly unequal
-    curvatures: every torus radius L is about 25 to 45 times the bbox diagonal,
-    so every point takes the anchored form (and the backward its
-    cancellation-free rho - vm).  Queries within 0.1 of the cap and in its box."""
-    rng = np.random.default_rng(seed)
-    xy = rng.uniform(-1.0, 1.0, size=(4 * N, 2))
-    xy = xy[np.hypot(xy[:, 0], xy[:, 1]) < 1.0][:N]
-    z = np.sqrt(radius ** 2 - (xy ** 2).sum(1)) - radius
-    p = np.c_[xy, z]
-    n = (p - np.array([0.0, 0.0, -radius])) / radius
-    a = np.zeros((N, 6))
-    aniso = rng.uniform(0.15, 0.3, N)
-    a[:, 4] = -0.5 / radius * (1.0 + aniso)     # a02
-    a[:, 5] = -0.5 / radius * (1.0 - aniso)     # a20
-    cl = synth.Cloud(p.astype(np.float32), n.astype(np.float32), a.astype(np.float32), {})
-    k = rng.integers(N, size=Q // 2)
-    near = p[k] + n[k] * rng.uniform(-0.1, 0.1, size=(Q // 2, 1))
-    box = rng.uniform(p.min(0) - 0.2, p.max(0) + 0.2, size=(Q - Q // 2, 3))
-    return _tilted(cl, seed + 1), np.r_[near, box].astype(np.float32)
-
-
 def _case(name):
     if name == "tiny":
         return synth.tiny(Q=1500, N=1200)
     if name == "mid":
         cl, x = synth.mid(N=1500, grid=11)
         return _tilted(cl, 1), x
-    if name == "cap":
-        return _cap()
+    if name == "cap":  # every torus radius L is 20 to 30 bbox diagonals: all anchored
+        cl, x = synth.cap_cloud()
+        return _tilted(cl, 12), x
     cl, q, mask = synth.diff_workload(N=2048, Q=3000)
     return cl, q
 

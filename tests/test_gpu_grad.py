@@ -86,6 +86,12 @@ def test_grad_mid_small_vs_oracle():
     _check(cl, x, "mid-6k")
 
 
+def test_grad_cap_vs_oracle():
+    # a nearly flat cloud: every point takes the anchored torus form
+    cl, x = synth.cap_cloud(N=1200, Q=1200)
+    _check(cl, x, "cap")
+
+
 def test_grad_diff_workload_sampled():
     # ellipsoid cloud of the differentiation workload, half the queries near
     # the surface; full-size cloud, a seeded sample of the queries

@@ -62,12 +62,14 @@ def _run(cl, x):
     return c, xs, st, g_eval, lap.cpu().numpy(), g.cpu().numpy(), eik.cpu().numpy()
 
 
-@pytest.mark.parametrize("name", ["tiny", "mid", "diff"])
+@pytest.mark.parametrize("name", ["tiny", "mid", "diff", "cap"])
 def test_laplacian_vs_oracle(name):
     if name == "tiny":
         cl, x = synth.tiny(Q=1200, N=900)
     elif name == "mid":
         cl, x = synth.mid(N=1500, grid=10)
+    elif name == "cap":  # nearly flat: every point takes the anchored torus form
+        cl, x = synth.cap_cloud(N=1200, Q=1500)
     else:
         cl, x, _ = synth.diff_workload(N=2048, Q=2000)
     x = x[_far_decided(cl.p, x)]

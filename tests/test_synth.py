@@ -47,3 +47,22 @@ def test_large_outliers_and_density():
     cl, x = synth.large(N=20000, Q=1000)
     assert cl.N == 20000 and cl.meta["outliers"] == 600
     assert x.shape == (1000, 3)
+
+
+def test_cap_cloud_is_nearly_flat():
+    """The cap generator: points on the sphere of radius 50, unit outward
+    normals, unequal curvatures -(1 +- e)/50; by the oracle's fit every torus
+    radius L = 1/|kappa_min| exceeds 4 bbox diagonals (the anchored form's range)."""
+    import oracle
+
+    cl, x = synth.cap_cloud(N=600, Q=300)
+    c2, x2 = synth.cap_cloud(N=600, Q=300)
+    assert _h(cl.p, cl.n, cl.a, x) == _h(c2.p, c2.n, c2.a, x2)
+    assert cl.N == 600 and x.shape == (300, 3)
+    p = cl.p.astype(np.float64)
+    assert np.allclose(np.linalg.norm(p - [0.0, 0.0, -50.0], axis=1), 50.0, atol=1e-4)
+    assert np.allclose(np.linalg.norm(cl.n, axis=1), 1.0, atol=1e-6)
+    assert np.all(cl.a[:, 4] < cl.a[:, 5]) and np.all(cl.a[:, 5] < 0)
+    tor = oracle.fit(cl.p, cl.n, cl.a)
+    L = 1.0 / np.abs(np.asarray(tor.kminf))
+    assert np.all(L > 4.0 * oracle.bbox_diag(cl.p))
