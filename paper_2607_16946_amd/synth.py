@@ -308,6 +308,25 @@ def cap_cloud(N: int = 1400, Q: int = 1500, radius: float = 50.0, seed: int = SE
     return Cloud(p, n, a, {"shape": "spherical cap", "radius": radius, "seed": seed}), x
 
 
+def mixed_forms_cloud(N: int = 6000, seed: int = 21) -> Cloud:
+    """The mid cloud's points with general coefficients interleaved in input
+    order: shift a00, tilt a10/a01, both, nearly flat points (a02, a20 scaled
+    by 1e-4: large radii) and exactly flat ones (a11 = a02 = a20 = 0: both
+    curvatures at the floor), next to the analytic ones."""
+    cl, _ = mid(N=N, grid=4)
+    rng = np.random.default_rng(seed)
+    a = cl.a.astype(np.float64).copy()
+    kind = rng.integers(0, 6, size=N)
+    a[kind == 1, 0] = rng.normal(0, 0.01, size=(kind == 1).sum())                 # shift
+    a[kind == 2, 1:3] = rng.normal(0, 0.2, size=((kind == 2).sum(), 2))          # tilt
+    both = kind == 3
+    a[both, 0] = rng.normal(0, 0.01, size=both.sum())
+    a[both, 1:3] = rng.normal(0, 0.2, size=(both.sum(), 2))
+    a[kind == 4, 4:6] *= 1e-4                                                     # nearly flat: large L
+    a[kind == 5, 3:6] = 0.0                                                       # flat
+    return Cloud(cl.p, cl.n, a.astype(np.float32), {"shape": "mixed forms", "seed": seed})
+
+
 def tiny(Q: int = 4096, N: int = 4096):
     """Plain method, tiny: N points on the unit sphere, Q queries uniform in [-1.5,1.5]^3."""
     cl = sphere_cloud(N, SEED_BASE + 1)

@@ -110,25 +110,8 @@ def test_mid_full_size_sampled():
     _say("anchored points:", info.n_anchored)
 
 
-def _mixed_coefficients_cloud(N=6000, seed=21):
-    """mid-shaped cloud with general coefficients interleaved in input order:
-    shift a00, tilt a10/a01, both, and nearly flat points (large L, anchored
-    form), next to the analytic ones."""
-    cl, _ = synth.mid(N=N, grid=4)
-    rng = np.random.default_rng(seed)
-    a = cl.a.astype(np.float64).copy()
-    kind = rng.integers(0, 5, size=N)
-    a[kind == 1, 0] = rng.normal(0, 0.01, size=(kind == 1).sum())                 # shift
-    a[kind == 2, 1:3] = rng.normal(0, 0.2, size=((kind == 2).sum(), 2))          # tilt
-    both = kind == 3
-    a[both, 0] = rng.normal(0, 0.01, size=both.sum())
-    a[both, 1:3] = rng.normal(0, 0.2, size=(both.sum(), 2))
-    a[kind == 4, 4:6] *= 1e-4                                                     # nearly flat: large L
-    return synth.Cloud(cl.p, cl.n, a.astype(np.float32), {})
-
-
 def test_mixed_coefficients_and_forms():
-    cl = _mixed_coefficients_cloud()
+    cl = synth.mixed_forms_cloud()
     c = _build(cl)
     info = c.info()
     tor = oracle.fit(cl.p, cl.n, cl.a)

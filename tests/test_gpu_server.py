@@ -39,7 +39,8 @@ def _dev(a):
 def _clouds():
     return [synth.sphere_cloud(3000, seed=11, jitter=0.01),
             synth.mid(N=20000, grid=4)[0],
-            synth.serving_cloud(3, nmax=70000)]
+            synth.serving_cloud(3, nmax=70000),
+            synth.mixed_forms_cloud(6000)]   # direct, anchored and R = 0 tori
 
 
 def _queries(cl, q, seed):
