@@ -143,7 +143,12 @@ __device__ int blend_within(const Tree& T, const float4* rec, int64_t nd, float 
         const float4* R = rec + s * kRecF4;
         const float4 P = R[0], U = R[1], Mv = R[2], K = R[3], G = R[4];
         const float g = s < nd ? g_direct(x, y, z, U, Mv, K, G) : g_anchored(x, y, z, P.w, U, Mv, K, G);
-        const float w = hw_exp2((sigma - sqrtf(d2)) * lam2);
+        // |x - p| in FP64 from the FP32 coordinates (their differences are exact):
+        // lambda = 1e3 / D is large, so the FP32 rounding of a distance of, say,
+        // half the cloud would reach the exponent as lambda eps d ~ 1e-3
+        const double ex = double(x) - double(P.x), ey = double(y) - double(P.y), ez = double(z) - double(P.z);
+        const double dd = sqrt(fma(ez, ez, fma(ey, ey, ex * ex)));
+        const float w = hw_exp2(float((double(sigma) - dd) * double(lam2)));
         num = fmaf(w, g, num);
         den += w;
         ++cnt;

@@ -67,6 +67,14 @@ def test_bounded_ragged_and_random_queries():
     _check(cl, x, 1e-5, what="ragged")
 
 
+@pytest.mark.parametrize("eps_rel", [0.0, 1e-5])
+def test_bounded_mixed_forms(eps_rel):
+    # direct, anchored and flat (both curvatures floored) tori in one cloud
+    cl = synth.mixed_forms_cloud(5000)
+    x = np.random.default_rng(9).uniform(-1.2, 1.2, size=(1500, 3)).astype(np.float32)
+    _check(cl, x, eps_rel, what="mixed forms")
+
+
 def test_bounded_benchmark_size_sampled():
     # the benchmark cloud (131072 points) on a 64^3 lattice; the oracle on a sample
     cl, x = synth.mid(N=131072, grid=64)

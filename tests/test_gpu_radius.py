@@ -99,6 +99,19 @@ def test_radius_parity_mid_both_modes():
     assert (cnt > 0).sum() > 200 and (cnt < 0).sum() > 1000
 
 
+def test_radius_parity_mixed_forms():
+    # direct, anchored and flat (both curvatures floored) tori in one cloud
+    cl = synth.mixed_forms_cloud(6000)
+    c, info = _prep(cl)
+    rng = np.random.default_rng(6)
+    near = cl.p[rng.choice(cl.N, 800, replace=False)] + \
+        rng.uniform(-0.6, 0.6, size=(800, 3)).astype(np.float32) * info.reval
+    far = rng.uniform(-1.2, 1.2, size=(800, 3)).astype(np.float32)
+    x = np.vstack([near, far]).astype(np.float32)
+    cnt = _compare(cl, c, info, x, "mixed forms")
+    assert (cnt > 0).sum() > 200 and (cnt < 0).sum() > 200
+
+
 def test_radius_sphere_closed_form():
     cl = synth.sphere_cloud(4000, seed=12, jitter=0.0)
     c, info = _prep(cl)
