@@ -148,7 +148,7 @@ __global__ __launch_bounds__(kBlock, kW ? 7 : 8) void k_backp(const Header* __re
       constexpr bool kMixed = decltype(mixed)::value;
       const float4 X = qt[j];
       float kap, phi = 0.f, lam = 0.f;
-      if (kW) {
+      if constexpr (kW) {
         const float4 A4 = qa[j];
         kap = A4.x; phi = A4.y; lam = A4.z;
       } else {
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(kBlock, kW ? 7 : 8) void k_backp(const Header* __re
       // (|q| + zeta b as one explicit fma, so that both sweeps round it alike)
       if (anch && zb > 0.f) dgr = -(r.vu * r.vu) * iq * safe_rcp(fmaf(r.qn2, iq, zb));
       t[7] = fmaf(coef, G.z * dgr, t[7]);                        // dg/dr
-      if (kW) {  // weight: (w/W) lambda (g - phi) e, e = (x - p)/d
+      if constexpr (kW) {  // weight: (w/W) lambda (g - phi) e, e = (x - p)/d
         const float c3 = coef * lam * (r.g - phi) * id;
         t[8] = fmaf(c3, dx, t[8]);
         t[9] = fmaf(c3, dy, t[9]);
