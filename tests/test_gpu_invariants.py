@@ -13,6 +13,9 @@ case):
 * a permutation of the points leaves phi unchanged;
 * a rotation of an isotropic cloud (a01 = a10 = a11 = 0, a02 = a20) leaves
   phi unchanged.
+
+The first four run on a curved cloud (mostly direct tori) and on a nearly
+flat cap (every torus in the anchored form).
 """
 
 import numpy as np
@@ -43,14 +46,18 @@ def _gpu():
     binding.lib()
 
 
-@pytest.fixture(scope="module")
-def cloud():
-    cl, _ = synth.mid(N=3000, grid=4)
+@pytest.fixture(scope="module", params=["mid", "cap"])
+def cloud(request):
+    """A curved cloud (mostly direct tori) and a nearly flat one (all anchored)."""
     rng = np.random.default_rng(41)
+    if request.param == "mid":
+        cl, _ = synth.mid(N=3000, grid=4)
+        x = rng.uniform(-1.2, 1.2, size=(2500, 3))
+    else:
+        cl, x = synth.cap_cloud(N=2000, Q=2500)
     a = cl.a.astype(np.float64)
     a[:, 0] += rng.normal(scale=0.01, size=cl.N)
     a[:, 1:3] += rng.normal(scale=0.05, size=(cl.N, 2))
-    x = rng.uniform(-1.2, 1.2, size=(2500, 3))
     p, n, a, x = (v.astype(np.float32) for v in (cl.p, cl.n, a, x))
     return p, n, a, x, oracle.bbox_diag(p)
 
