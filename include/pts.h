@@ -177,6 +177,24 @@ int pts_grad_ws_bytes(int64_t N, int64_t Q, const pts_params* prm, size_t* out_b
 int pts_eval(const void* rec, int64_t N, const float* x, int64_t Q, float* sdf, float* grad,
              float* stats, const pts_params* prm, void* ws, size_t ws_bytes, void* stream);
 
+/* pts_eval without gradient or statistics, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same kernels and the same results, bit for bit,
+ * as pts_eval(rec, N, x, Q, sdf, NULL, NULL, prm, ws, ws_bytes, stream), with
+ * the workspace taken from a static device array of 64 MiB that the library
+ * holds on every device it runs on until the process ends.  Nothing is
+ * allocated by this call, ever.  The array's device address is looked up on
+ * the first call on each device.
+ *   rec, x [Q,3], sdf [Q]  as pts_eval (device; owned by the caller).
+ * Errors as pts_eval, and PTS_EINVAL when the evaluation's workspace
+ * (pts_eval_ws_bytes(N, Q, prm)) exceeds 64 MiB -- e.g. 2^20 queries with 8
+ * point splits need 128 MiB; call pts_eval with a workspace then.  Every call
+ * on one device uses the same array: calls that overlap on a device (two
+ * streams, two threads) race and give wrong results; serialise them.  Each
+ * call overwrites every byte it reads, so no clearing is needed between calls. */
+int pts_eval_noalloc(const void* rec, int64_t N, const float* x, int64_t Q, float* sdf, const pts_params* prm,
+                     void* stream);
+
 /* Scratch bytes for pts_eval_bounded. */
 int pts_eval_bounded_ws_bytes(int64_t N, int64_t Q, const pts_params* prm, size_t* out_bytes);
 

@@ -93,6 +93,7 @@ SIGNATURES = {
                                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_I64)]),
     "pts_eval_ws_bytes": (ctypes.c_int, [_I64, _I64, ctypes.POINTER(Params), ctypes.POINTER(_SZ)]),
     "pts_eval": (ctypes.c_int, [_P, _I64, _P, _I64, _P, _P, _P, ctypes.POINTER(Params), _P, _SZ, _P]),
+    "pts_eval_noalloc": (ctypes.c_int, [_P, _I64, _P, _I64, _P, ctypes.POINTER(Params), _P]),
     "pts_eval_far": (ctypes.c_int, [_P, _I64, _P, _I64, ctypes.POINTER(Params), _P, _SZ, _P]),
     "pts_eval_blend": (ctypes.c_int, [_P, _I64, _P, _I64, ctypes.POINTER(Params), _P, _SZ, _P]),
     "pts_eval_combine": (ctypes.c_int, [_I64, _I64, _P, ctypes.POINTER(Params), _P, _SZ, _P]),
@@ -269,6 +270,20 @@ def eval(rec: torch.Tensor, N: int, x: torch.Tensor, params: Params | None = Non
     if stats:
         res.append(st)
     return res[0] if len(res) == 1 else tuple(res)
+
+
+def eval_noalloc(rec: torch.Tensor, N: int, x: torch.Tensor, params: Params | None = None,
+                 out: torch.Tensor | None = None) -> torch.Tensor:
+    """phi(x) at queries x [Q,3] with the library's static device scratch (no allocation by the library)."""
+    _dev(x, "x", 3)
+    Q = x.shape[0]
+    prm = params if params is not None else make_params()
+    sdf = out if out is not None else torch.empty(Q, dtype=torch.float32, device=x.device)
+    _dev(sdf, "out")
+    if sdf.numel() != Q:
+        raise ValueError("out must have one value per query")
+    _check(lib().pts_eval_noalloc(_ptr(rec), int(N), _ptr(x), Q, _ptr(sdf), ctypes.byref(prm), _stream()))
+    return sdf
 
 
 def eval_bounded_ws_bytes(N: int, Q: int, params: Params | None = None) -> int:

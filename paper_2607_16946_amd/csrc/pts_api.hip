@@ -242,6 +242,18 @@ int pts_eval(const void* rec, int64_t N, const float* x, int64_t Q, float* sdf, 
   return PTS_OK;
 }
 
+int pts_eval_noalloc(const void* rec, int64_t N, const float* x, int64_t Q, float* sdf, const pts_params* prm,
+                     void* stream) {
+  if (N < 1 || Q < 0) return fail(PTS_EINVAL, "N must be >= 1 and Q >= 0");
+  if (Q > (int64_t(1) << 31) - 1) return fail(PTS_EINVAL, "Q must be < 2^31");
+  const pts_params P = resolve(prm);
+  if (int rc = check_params(P)) return rc;
+  if (Q == 0) return PTS_OK;
+  if (!rec || !x || !sdf) return fail(PTS_EINVAL, "null pointer");
+  // eval_noalloc refuses a plan whose workspace exceeds the static scratch
+  return eval_noalloc(rec, N, x, Q, sdf, P, make_plan(N, Q, &P), static_cast<hipStream_t>(stream));
+}
+
 int pts_eval_far(const void* rec, int64_t N, const float* x, int64_t Q, const pts_params* prm, void* ws,
                  size_t ws_bytes, void* stream) {
   Plan plan;

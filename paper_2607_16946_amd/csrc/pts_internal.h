@@ -138,6 +138,13 @@ int launch_decode(const void* rec, int64_t N, float* out, hipStream_t st);
 int launch_radix_sort(uint32_t* key[2], int32_t* idx[2], int64_t n, int passes, int32_t* rhist, hipStream_t st,
                       int* out);
 
+// Plain evaluation (phi only) with the workspace in a static device array
+// (pts_noalloc.hip): no allocation of any kind; rejects plans whose workspace
+// exceeds noalloc_scratch_bytes().
+size_t noalloc_scratch_bytes();
+int eval_noalloc(const void* rec, int64_t N, const float* x, int64_t Q, float* sdf, const pts_params& P,
+                 const Plan& plan, hipStream_t st);
+
 // Error-bounded evaluation (pts_bounded.hip): the blend with point units
 // skipped while a proven bound on the change of phi stays within eps.
 Plan bounded_plan(int64_t N, int64_t Q);

@@ -74,6 +74,17 @@ def test_host_side_errors(L):
     assert wp.value >= wa.value * 12 // 8 + 3000 * (4 + 4 + 48)
 
 
+def test_noalloc_refuses_a_workspace_beyond_its_static_scratch(L):
+    # checked on the host before any device call: 2^22 queries with 8 splits need 512 MiB > 64 MiB
+    prm = binding.make_params()
+    fake = ctypes.c_void_p(256)
+    rc = L.pts_eval_noalloc(fake, 1 << 17, fake, 1 << 22, fake, ctypes.byref(prm), None)
+    assert rc == binding.PTS_EINVAL
+    assert b"static scratch" in L.pts_last_error()
+    assert L.pts_eval_noalloc(None, 10, None, 0, None, ctypes.byref(prm), None) == binding.PTS_OK
+    assert L.pts_eval_noalloc(None, 10, None, 5, None, ctypes.byref(prm), None) == binding.PTS_EINVAL
+
+
 def test_probe_library_exports():
     path = os.path.join(ROOT, "paper_2607_16946_amd", "libpts_probe.so")
     P = ctypes.CDLL(path)
