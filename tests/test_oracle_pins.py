@@ -79,6 +79,50 @@ def test_golden_worked_examples():
         assert np.max(np.abs(phi - np.array(cs["g"]))) < tol, cs["name"]
 
 
+WEIGHTS = os.path.join(os.path.dirname(__file__), "golden", "blend_weights.json")
+
+
+def test_blend_weights_three_spheres_hand_derived():
+    """Sec. 4.2, Eqs. (BasicFormulaShifted), (RelationshipBetweenLambdaAndRadius); App. D: a hand-derived
+    blend of three exact spheres whose two near points differ in distance by M/(2C), so that the
+    weight ratio e^-(lambda delta) depends on the factor in lambda_x = 2C/M.  Checks the fit, phi,
+    the statistics (M and the shifted weight sum W) and grad phi with its lambda_x term."""
+    G = json.load(open(WEIGHTS))
+    p, n, a, x = (np.array(G[k], dtype=np.float64) for k in ("p", "n", "a", "x"))
+    tor = oracle.fit(p, n, a)
+    assert np.allclose(tor.c, [[0.75, 0, 0], [0, 3 / 128 - 1, 0], [0, 0, -2]], atol=1e-14)
+    assert np.allclose(tor.R, 0.0, atol=1e-14) and np.allclose(tor.r, [0.25, 2.0, 1.0], atol=1e-14)
+    assert np.all(tor.sgn == 1.0)
+    assert np.allclose(oracle.torus_g(tor, x[None])[0], G["cases"][0]["g"], atol=1e-14)
+    for case in G["cases"]:
+        phi, g, st = oracle.eval_sdf(p, tor, x[None], C=case["C"], grad=True, stats=True)
+        assert abs(phi[0] - case["phi"]) <= 1e-13, (case["C"], phi[0], case["phi"])
+        assert np.abs(g[0] - np.array(case["grad"])).max() <= 1e-11 * max(1.0, np.abs(case["grad"]).max())
+        assert st[0, 0] == case["M"]
+        assert abs(st[0, 1] - case["W"]) <= 1e-12 * case["W"]
+        assert abs(st[0, 2] - case["phi"]) <= 1e-13
+
+
+def test_blend_weights_pin_rejects_planted_misreadings():
+    """The pin above fails for the plausible misreadings: lambda = C/M (the oracle run with C halved
+    computes exactly that) moves phi by >= 0.027 and grad phi by >= 0.5; a dropped shift
+    (w = exp(-lambda d)) leaves phi but scales W by e^-C."""
+    G = json.load(open(WEIGHTS))
+    p, n, a, x = (np.array(G[k], dtype=np.float64) for k in ("p", "n", "a", "x"))
+    tor = oracle.fit(p, n, a)
+    for case in G["cases"]:
+        C = case["C"]
+        phi, g, st = oracle.eval_sdf(p, tor, x[None], C=C / 2, grad=True, stats=True)
+        assert abs(phi[0] - G["misreading_lambda_C_over_M_phi"][str(int(C))]) <= 1e-13
+        assert abs(phi[0] - case["phi"]) > 0.025
+        # grad of the misread phi at lambda = C/M differs in every component
+        assert np.abs(g[0] - np.array(case["grad"])).max() > 0.1
+        # dropped shift: W would be sum exp(-lambda d_i) = W exp(-lambda sigma) = W e^-C
+        unshifted = sum(math.exp(-case["lambda"] * di) for di in case["d"])
+        assert abs(unshifted - case["W"] * math.exp(-C)) <= 1e-12 * unshifted
+        assert abs(unshifted - case["W"]) > 0.5 * case["W"]
+
+
 def test_printed_center_fails_on_saddle():
     # The inner-equator case separates the two center readings: the printed
     # formula puts the torus axis on the wrong side (planted-mistake check).
