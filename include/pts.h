@@ -75,9 +75,20 @@ const char* pts_last_error(void);
 /* Parameters.  A NULL pointer means the defaults below. */
 typedef struct pts_params {
   float C;           /* screening constant of Eq. (RelationshipBetweenLambdaAndRadius);
-                        default 64 (Sec. 4.2).  0 < C <= 87 (FP32 range of e^-C). */
+                        default 64 (Sec. 4.2).  0 < C <= 75.  phi does not
+                        depend on the additive shift of Eq. (BasicFormulaShifted);
+                        the FP32 kernels shift the exponents by s = min(C, 64)
+                        instead of C, so the weights lie in [e^(s - 2C), e^s]:
+                        the largest is at most e^64, which keeps the sums below
+                        FLT_MAX while N * max|g| < 5e10 (coordinates in units
+                        of the cloud), and the smallest stays a normal FP32
+                        number (>= 2^-126) for C <= 75 (a query nearly
+                        equidistant from every point would otherwise get 0/0).
+                        Statistics report W with this shift. */
   float kfloor_rel;  /* curvature floor kappa_floor = kfloor_rel / D, D = bbox
-                        diagonal of the cloud (D = 1 if it is 0); default 1e-6.
+                        diagonal of the cloud (D = 1 if it is 0); default 1e-6;
+                        at least 1e-12 (radii reach D / kfloor_rel and the
+                        anchored torus form squares them in FP32).
                         Applied at build time.  Principal curvatures smaller in
                         magnitude are raised to +-kappa_floor (sign(0) = -1),
                         which keeps planar and cylindrical points at finite,
@@ -169,8 +180,9 @@ int pts_grad_ws_bytes(int64_t N, int64_t Q, const pts_params* prm, size_t* out_b
  *               circle) and at a query on a point, the undefined factor is 0.
  *               Requires ws_bytes >= pts_grad_ws_bytes(N, Q, prm).
  *   stats [Q,6] device float32 output or NULL: (M, W, phi, e_*) with
- *               M = max_i |x - p_i|, W = sum_i exp(-lambda_x(|x-p_i| - sigma_x))
- *               (the shifted weight sum of Eq. BasicFormulaShifted), phi, and
+ *               M = max_i |x - p_i|, W = sum_i exp(s - lambda_x |x-p_i|) with
+ *               s = min(C, 64) (the shifted weight sum of Eq. BasicFormulaShifted,
+ *               whose shift lambda_x sigma_x is C; see pts_params.C), phi, and
  *               e_* as above.  The input of pts_grad_x.
  *   ws          device scratch of ws_bytes >= pts_eval_ws_bytes(N, Q, prm).
  * A query with a NaN or infinite coordinate gives NaN.  Q = 0 is a no-op. */

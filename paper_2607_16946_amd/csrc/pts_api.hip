@@ -30,8 +30,9 @@ pts_params resolve(const pts_params* prm) {
 }
 
 int check_params(const pts_params& p) {
-  if (!(p.C > 0.0f && p.C <= 87.0f)) return fail(PTS_EINVAL, "C must be in (0, 87]");
-  if (!(p.kfloor_rel > 0.0f && std::isfinite(p.kfloor_rel))) return fail(PTS_EINVAL, "kfloor_rel must be > 0");
+  if (!(p.C > 0.0f && p.C <= kCMax)) return fail(PTS_EINVAL, "C must be in (0, 75]");
+  if (!(p.kfloor_rel >= kKfloorRelMin && std::isfinite(p.kfloor_rel)))
+    return fail(PTS_EINVAL, "kfloor_rel must be finite and >= 1e-12");
   if (p.splits < 0 || p.splits > 64 || (p.splits & (p.splits - 1)) != 0)
     return fail(PTS_EINVAL, "splits must be 0 or a power of two <= 64");
   if (!std::isfinite(p.offset)) return fail(PTS_EINVAL, "offset must be finite");

@@ -87,7 +87,7 @@ template <bool kW>
 __global__ __launch_bounds__(kBlock, kW ? 7 : 8) void k_backp(const Header* __restrict__ h, const float4* __restrict__ rec,
                                                   const float* __restrict__ x, int64_t Q, int Sq, int64_t per_qs,
                                                   const float* __restrict__ stats, const float* __restrict__ gout,
-                                                  const float4* __restrict__ qrec, float C2,
+                                                  const float4* __restrict__ qrec, float C2, float S2,
                                                   float* __restrict__ gpp) {
   constexpr int kStride = kW ? 12 : 8;
   __shared__ float4 qt[kQTile];
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(kBlock, kW ? 7 : 8) void k_backp(const Header* __re
       const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
       const float id = safe_rsq(d2);                     // 1/d (both variants form d alike)
       const float d = d2 * id;
-      const float coef = hw_exp2(fmaf(d, X.w, C2)) * kap;
+      const float coef = hw_exp2(fmaf(d, X.w, S2)) * kap;
       const bool anch = kMixed && !direct;
       const Geo r = anch ? geo_anchored(X.x, X.y, X.z, P.w, U, Mv, K, G) : geo_direct(X.x, X.y, X.z, U, Mv, K, G);
       const float iq = r.iqn, ir = r.irho;
@@ -344,7 +344,7 @@ int launch_backward(const void* rec, int64_t N, const float* p, const float* n, 
   const BackPlan b = make_back_plan(N, Q);
   const float4* recs = reinterpret_cast<const float4*>(base + L.rec);
   const int32_t* perm = reinterpret_cast<const int32_t*>(base + L.perm);
-  const float C2 = C * kLog2e;
+  const float C2 = C * kLog2e, S2 = shift2_of(C);
   const unsigned gb = unsigned(b.pbs * b.Sq);
   if (gp) {
     const BackPointsWs v = back_points_ws(N, Q, plan, ws);
@@ -353,7 +353,7 @@ int launch_backward(const void* rec, int64_t N, const float* p, const float* n, 
     hipLaunchKernelGGL(k_qrec, dim3(unsigned((Q + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, h, x, Q, stats,
                        v.vpart, plan.S, v.farix, gout, C, v.qrec);
     hipLaunchKernelGGL(k_backp<true>, dim3(gb), dim3(kBlock), 0, st, h, recs, x, Q, b.Sq, b.per_qs, stats, gout,
-                       v.qrec, C2, v.gpp);
+                       v.qrec, C2, S2, v.gpp);
     if (gn)
       hipLaunchKernelGGL((k_chain<9, true>), dim3(unsigned(b.pbs)), dim3(kBlock), 0, st, h, perm, p, n, a, N, b.Sq,
                          v.gpp, ga, gp, gn);
@@ -363,7 +363,7 @@ int launch_backward(const void* rec, int64_t N, const float* p, const float* n, 
   } else {
     float* gpp = static_cast<float*>(ws);
     hipLaunchKernelGGL(k_backp<false>, dim3(gb), dim3(kBlock), 0, st, h, recs, x, Q, b.Sq, b.per_qs, stats, gout,
-                       nullptr, C2, gpp);
+                       nullptr, C2, S2, gpp);
     if (gn)
       hipLaunchKernelGGL((k_chain<9, false>), dim3(unsigned(b.pbs)), dim3(kBlock), 0, st, h, perm, p, n, a, N,
                          b.Sq, gpp, ga, gp, gn);

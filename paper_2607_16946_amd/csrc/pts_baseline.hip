@@ -34,7 +34,7 @@ __global__ __launch_bounds__(kBlock) void k_base(const Header* __restrict__ h, c
   const int split = int(blockIdx.x % unsigned(S));
   const int64_t qb = blockIdx.x / unsigned(S);
   const int64_t N = h->N;
-  const float C2 = C * kLog2e;
+  const float C2 = C * kLog2e, S2 = shift2_of(C);
   float qx[QPL], qy[QPL], qz[QPL], nl[QPL], lam[QPL], num[QPL], den[QPL];
 #pragma unroll
   for (int k = 0; k < QPL; ++k) {
@@ -67,14 +67,14 @@ __global__ __launch_bounds__(kBlock) void k_base(const Header* __restrict__ h, c
         const float t = fmaf(dz, Nv.z, fmaf(dy, Nv.y, dx * Nv.x));
         if (KIND == PTS_BASELINE_SSPD) {
           const float d = hw_sqrt(d2);
-          const float w = hw_exp2(fmaf(d, nl[k], C2)) * P.w;
+          const float w = hw_exp2(fmaf(d, nl[k], S2)) * P.w;
           tn[k] = fmaf(w, t, tn[k]);
           td[k] += w;
         } else {
           // d and 1/d from one rsqrt; at d = 0 (rsqrt = inf) d is NaN and so is the sum
           const float rd = hw_rsq(d2);
           const float d = d2 * rd;
-          const float w = hw_exp2(fmaf(d, nl[k], C2)) * P.w;
+          const float w = hw_exp2(fmaf(d, nl[k], S2)) * P.w;
           const float hv = d > 0.f ? fmaf(lam[k], d, 1.f) * t * (rd * rd * rd) * kInv2Pi : __builtin_nanf("");
           tn[k] = fmaf(w, hv, tn[k]);
         }
@@ -107,7 +107,9 @@ __global__ __launch_bounds__(kBlock) void k_base_combine(const float2* __restric
   } else {
     const float M = sqrtf(fmaxf(far2[q], 0.f));
     const float sg = num < 0.f ? -1.f : 1.f;
-    sdf[q] = sg * (-logf(fabsf(num)) * M / (2.f * C) + 0.5f * M) - offset;
+    // the weights carry the factor e^s, s = min(C, 64), i.e. -log adds s / lambda_x = s M / (2C) (= M/2 for s = C)
+    const float back = C <= kShiftMaxC ? 0.5f * M : kShiftMaxC * M / (2.f * C);
+    sdf[q] = sg * (-logf(fabsf(num)) * M / (2.f * C) + back) - offset;
   }
 }
 

@@ -78,12 +78,12 @@ __global__ __launch_bounds__(kBlock) void k_qkeys(const Header* __restrict__ h, 
 }
 
 template <bool kDirect>
-__device__ __forceinline__ void pair(float qx, float qy, float qz, float nl, float C2, const float4& P,
+__device__ __forceinline__ void pair(float qx, float qy, float qz, float nl, float S2, const float4& P,
                                      const float4& U, const float4& Mv, const float4& K, const float4& G, float& tn,
                                      float& td) {
   const float dx = qx - P.x, dy = qy - P.y, dz = qz - P.z;
   const float d = hw_sqrt(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
-  const float w = hw_exp2(fmaf(d, nl, C2));
+  const float w = hw_exp2(fmaf(d, nl, S2));
   const float g = kDirect ? g_direct(qx, qy, qz, U, Mv, K, G) : g_anchored(qx, qy, qz, P.w, U, Mv, K, G);
   tn = fmaf(w, g, tn);
   td += w;
@@ -130,7 +130,7 @@ constexpr int kWorkBlock = 64;
 __global__ __launch_bounds__(kWorkBlock) void k_bwork(const Header* __restrict__ h, const float4* __restrict__ ub,
                                                       const float* __restrict__ x, const int32_t* __restrict__ order,
                                                       int64_t Q, int64_t nqb, int qpl, const float* __restrict__ far2,
-                                                      float C2, float eps, uint32_t* __restrict__ key,
+                                                      float C2, float S2, float eps, uint32_t* __restrict__ key,
                                                       int32_t* __restrict__ idx) {
   const int64_t b = int64_t(blockIdx.x) * kWorkBlock + threadIdx.x;
   if (b >= nqb) return;
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(kWorkBlock) void k_bwork(const Header* __restrict__
   for (int64_t u = 0; u < nunit; ++u) {
     const float4 cb = ub[2 * u];
     const float ex = r.x - cb.x, ey = r.y - cb.y, ez = r.z - cb.z;
-    W += hw_exp2(fmaf(hw_sqrt(fmaf(ez, ez, fmaf(ey, ey, ex * ex))), nl, C2));
+    W += hw_exp2(fmaf(hw_sqrt(fmaf(ez, ez, fmaf(ey, ey, ex * ex))), nl, S2));
   }
   const float thr = eps * W / (10.f * float(nunit));
   uint32_t cnt = 0;
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(kWorkBlock) void k_bwork(const Header* __restrict__
     const float4 cb = ub[2 * u];
     const float ex = r.x - cb.x, ey = r.y - cb.y, ez = r.z - cb.z;
     const float s = hw_sqrt(fmaf(ez, ez, fmaf(ey, ey, ex * ex)));
-    const float du = hw_exp2(fmaf(fmaxf(s - cb.w, 0.f), nl, C2));
+    const float du = hw_exp2(fmaf(fmaxf(s - cb.w, 0.f), nl, S2));
     cnt += du * (s + cb.w + M + 2.f * A) > thr ? 1u : 0u;
   }
   key[b] = 0xffffffu - (cnt < 0xffffffu ? cnt : 0xffffffu);   // ascending sort = heaviest first
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(kWorkBlock) void k_bwork(const Header* __restrict__
 // (and the skipped bounds added) if every live query's budget allows it.
 template <int QPL>
 __device__ __forceinline__ bool vote(const float4& sb, float n, const float* qx, const float* qy, const float* qz,
-                                     const float* nl, float C2, float A, const float* phimax, float* gs, float* ds,
+                                     const float* nl, float S2, float A, const float* phimax, float* gs, float* ds,
                                      const float* den, const float* wseed, float eps, const bool* live) {
   float du[QPL], gu[QPL];
   bool ok = true;
@@ -175,7 +175,7 @@ __device__ __forceinline__ bool vote(const float4& sb, float n, const float* qx,
     const float ex = qx[k] - sb.x, ey = qy[k] - sb.y, ez = qz[k] - sb.z;
     const float s = hw_sqrt(fmaf(ez, ez, fmaf(ey, ey, ex * ex)));
     const float dmin = fmaxf(s * (1.f - kSlack) - sb.w * (1.f + kSlack), 0.f);
-    du[k] = n * hw_exp2(fmaf(dmin, nl[k], C2)) * (1.f + kSlack);
+    du[k] = n * hw_exp2(fmaf(dmin, nl[k], S2)) * (1.f + kSlack);
     gu[k] = du[k] * (s + sb.w + A) * (1.f + kSlack);
     const bool skip = (gs[k] + gu[k]) + phimax[k] * (ds[k] + du[k]) <= eps * (den[k] * (1.f - kSlack) + wseed[k]);
     ok = ok && (skip || !live[k]);
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(kBW) void k_bounded(const Header* __restrict__ h, c
                                                  const float* __restrict__ x,
                                                  const int32_t* __restrict__ order, const int32_t* __restrict__ border,
                                                  int64_t Q, int S, int64_t per_split,
-                                                 const float* __restrict__ far2, float C2, float eps_total,
+                                                 const float* __restrict__ far2, float C2, float S2, float eps_total,
                                                  float4* __restrict__ part, int32_t* __restrict__ kpart) {
   // 5 KB of LDS per wave (8 waves per SIMD); the seed searches' reductions
   // use the unit tile, which holds nothing yet (every tile write is preceded
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(kBW) void k_bounded(const Header* __restrict__ h, c
       for (int k = 0; k < QPL; ++k) {
         const float dx = qx[k] - P.x, dy = qy[k] - P.y, dz = qz[k] - P.z;
         const float d = hw_sqrt(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
-        wseed[k] += hw_exp2(fmaf(d, nl[k], C2));
+        wseed[k] += hw_exp2(fmaf(d, nl[k], S2));
       }
     }
 #pragma unroll
@@ -257,7 +257,7 @@ __global__ __launch_bounds__(kBW) void k_bounded(const Header* __restrict__ h, c
     int64_t b = bstart + ib;
     if (b >= b_end) b -= nbk;
     const int64_t bu0 = max(b * kBlkU, u_beg), bu1 = min(b * kBlkU + kBlkU, u_end);
-    if (ib > 0 && vote<QPL>(bb[b], float(min(end, bu1 * kUnit) - bu0 * kUnit), qx, qy, qz, nl, C2, A, phimax, gs, ds, den,
+    if (ib > 0 && vote<QPL>(bb[b], float(min(end, bu1 * kUnit) - bu0 * kUnit), qx, qy, qz, nl, S2, A, phimax, gs, ds, den,
                        wseed, eps, live)) continue;
     const int64_t nub = bu1 - bu0;
     const int64_t us = ib == 0 ? ustart : bu0;
@@ -266,7 +266,7 @@ __global__ __launch_bounds__(kBW) void k_bounded(const Header* __restrict__ h, c
       if (u >= bu1) u -= nub;
       const int64_t t0 = u * kUnit;
       const int cnt = int(min<int64_t>(kUnit, end - t0));
-      if (vote<QPL>(ub[2 * u], float(cnt), qx, qy, qz, nl, C2, A, phimax, gs, ds, den, wseed, eps, live)) continue;
+      if (vote<QPL>(ub[2 * u], float(cnt), qx, qy, qz, nl, S2, A, phimax, gs, ds, den, wseed, eps, live)) continue;
       kept += cnt;
       __syncthreads();                 // the previous unit is read
       for (int j = threadIdx.x; j < cnt * kRecF4; j += kBW) tile[j] = rec[t0 * kRecF4 + j];
@@ -279,13 +279,13 @@ __global__ __launch_bounds__(kBW) void k_bounded(const Header* __restrict__ h, c
         const float4 P = tile[j * kRecF4 + 0], U = tile[j * kRecF4 + 1], Mv = tile[j * kRecF4 + 2],
                      K = tile[j * kRecF4 + 3], G = tile[j * kRecF4 + 4];
 #pragma unroll
-        for (int k = 0; k < QPL; ++k) pair<true>(qx[k], qy[k], qz[k], nl[k], C2, P, U, Mv, K, G, tn[k], td[k]);
+        for (int k = 0; k < QPL; ++k) pair<true>(qx[k], qy[k], qz[k], nl[k], S2, P, U, Mv, K, G, tn[k], td[k]);
       }
       for (int j = jd; j < cnt; ++j) {
         const float4 P = tile[j * kRecF4 + 0], U = tile[j * kRecF4 + 1], Mv = tile[j * kRecF4 + 2],
                      K = tile[j * kRecF4 + 3], G = tile[j * kRecF4 + 4];
 #pragma unroll
-        for (int k = 0; k < QPL; ++k) pair<false>(qx[k], qy[k], qz[k], nl[k], C2, P, U, Mv, K, G, tn[k], td[k]);
+        for (int k = 0; k < QPL; ++k) pair<false>(qx[k], qy[k], qz[k], nl[k], S2, P, U, Mv, K, G, tn[k], td[k]);
       }
 #pragma unroll
       for (int k = 0; k < QPL; ++k) { num[k] += tn[k]; den[k] += td[k]; }
@@ -328,9 +328,9 @@ __global__ __launch_bounds__(kBlock) void k_bcombine(const float4* __restrict__ 
 template <int QPL>
 void launch_bounded_q(const Header* h, const float4* rec, const float4* ub, const float4* bb, const float* x,
                       const int32_t* order, const int32_t* border, int64_t Q, const Plan& plan, const float* far2,
-                      float C2, float eps, float4* part, int32_t* kpart, hipStream_t st) {
+                      float C2, float S2, float eps, float4* part, int32_t* kpart, hipStream_t st) {
   hipLaunchKernelGGL(k_bounded<QPL>, dim3(unsigned(plan.nqb * plan.S)), dim3(kBW), 0, st, h, rec, ub, bb, x, order,
-                     border, Q, plan.S, plan.per_split, far2, C2, eps, part, kpart);
+                     border, Q, plan.S, plan.per_split, far2, C2, S2, eps, part, kpart);
 }
 
 // Workspace: far2 [Q], partials float4 [S][Q], kept int32 [S][Q], keys and
@@ -408,16 +408,16 @@ int launch_bounded(const void* rec, int64_t N, const float* x, int64_t Q, float 
   const int32_t* order = v.idx[cur];
   if (int rc = launch_far_cull(rec, N, x, Q, plan.qpl, v.far2, nullptr, st)) return rc;
   // heavy query blocks first
-  const float C2 = C * kLog2e;
+  const float C2 = C * kLog2e, S2 = shift2_of(C);
   hipLaunchKernelGGL(k_bwork, dim3(unsigned((plan.nqb + kWorkBlock - 1) / kWorkBlock)), dim3(kWorkBlock), 0, st, h, ub,
-                     x, order, Q, plan.nqb, plan.qpl, v.far2, C2, eps, v.bkey[0], v.bidx[0]);
+                     x, order, Q, plan.nqb, plan.qpl, v.far2, C2, S2, eps, v.bkey[0], v.bidx[0]);
   int bcur = 0;
   if (int rc = launch_radix_sort(v.bkey, v.bidx, plan.nqb, 6, v.rhist, st, &bcur)) return rc;
   const int32_t* border = v.bidx[bcur];
   switch (plan.qpl) {
-    case 1: launch_bounded_q<1>(h, recs, ub, bb, x, order, border, Q, plan, v.far2, C2, eps, v.part, v.kpart, st); break;
-    case 2: launch_bounded_q<2>(h, recs, ub, bb, x, order, border, Q, plan, v.far2, C2, eps, v.part, v.kpart, st); break;
-    default: launch_bounded_q<4>(h, recs, ub, bb, x, order, border, Q, plan, v.far2, C2, eps, v.part, v.kpart, st); break;
+    case 1: launch_bounded_q<1>(h, recs, ub, bb, x, order, border, Q, plan, v.far2, C2, S2, eps, v.part, v.kpart, st); break;
+    case 2: launch_bounded_q<2>(h, recs, ub, bb, x, order, border, Q, plan, v.far2, C2, S2, eps, v.part, v.kpart, st); break;
+    default: launch_bounded_q<4>(h, recs, ub, bb, x, order, border, Q, plan, v.far2, C2, S2, eps, v.part, v.kpart, st); break;
   }
   hipLaunchKernelGGL(k_bcombine, dim3(qblocks), dim3(kBlock), 0, st, v.part, v.kpart, order, plan.S, Q, sdf, bound,
                      kept, offset);

@@ -70,7 +70,7 @@ __global__ void k_init(Header* h, int64_t N) {
   h->rl_lambda = 0.f;
   h->rl_reval = 0.f;
   h->rl_ready = 0;
-  h->pad1 = 0;
+  h->rl_shift = 0.f;
   h->a00max_bits = 0u;
   h->pad2 = 0;
 }

@@ -18,8 +18,9 @@
 // splits are combined in a fixed order (k_combine), so results are
 // deterministic and depend on S only through rounding.
 //
-// Weights are computed with the shift of Eq. (BasicFormulaShifted):
-//   w = 2^(C log2e - lambda_x log2e |x - p|)  in [2^-C log2e, 2^C log2e],
+// Weights are computed with the shift of Eq. (BasicFormulaShifted), capped at
+// 64 (shift2_of in pts_internal.h; the paper's C = 64 is not capped):
+//   w = 2^((s - lambda_x |x - p|) log2e)  in [e^(s - 2C), e^s],
 // and the sums are accumulated per tile and then per split (two-level), which
 // bounds FP32 accumulation error by ~(tile + N/(S tile)) ulp.
 
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(kBlock) void k_far_fold(float* __restrict__ far2, i
 template <int QPL>
 __global__ __launch_bounds__(kBlock) void k_blend(const Header* __restrict__ h, const float4* __restrict__ rec,
                                                   const float* __restrict__ x, int64_t Q, int S, int64_t per_split,
-                                                  const float* __restrict__ far2, float C2,
+                                                  const float* __restrict__ far2, float C2, float S2,
                                                   float2* __restrict__ part) {
   __shared__ float4 tile[kTile2 * kRecF4];
   const int split = int(blockIdx.x % unsigned(S));
@@ -160,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_blend(const Header* __restrict__ h, 
     num[k] = 0.f;
     den[k] = 0.f;
   }
-  const float c2 = C2;
+  const float c2 = S2;
   const int64_t beg = int64_t(split) * per_split;
   const int64_t end = min(N, beg + per_split);
   for (int64_t t0 = beg; t0 < end; t0 += kTile2) {
@@ -237,9 +238,9 @@ void launch_far_q(const Header* h, const float4* pos4, const float4* ub, const f
 
 template <int QPL>
 void launch_blend_q(const Header* h, const float4* rec, const float* x, int64_t Q, const Plan& plan,
-                    const float* far2, float2* part, float C2, hipStream_t st) {
+                    const float* far2, float2* part, float C2, float S2, hipStream_t st) {
   hipLaunchKernelGGL(k_blend<QPL>, dim3(unsigned(plan.nqb * plan.S)), dim3(kBlock), 0, st, h, rec, x, Q, plan.S,
-                     plan.per_split, far2, C2, part);
+                     plan.per_split, far2, C2, S2, part);
 }
 
 }  // namespace
@@ -312,12 +313,12 @@ int launch_blend(const void* rec, int64_t N, const float* x, int64_t Q, float C,
   const char* base = static_cast<const char*>(rec);
   const Header* h = reinterpret_cast<const Header*>(base);
   const float4* recs = reinterpret_cast<const float4*>(base + L.rec);
-  const float C2 = C * kLog2e;
+  const float C2 = C * kLog2e, S2 = shift2_of(C);
   switch (plan.qpl) {
-    case 1: launch_blend_q<1>(h, recs, x, Q, plan, ws.far2, ws.part, C2, st); break;
-    case 2: launch_blend_q<2>(h, recs, x, Q, plan, ws.far2, ws.part, C2, st); break;
-    case 8: launch_blend_q<8>(h, recs, x, Q, plan, ws.far2, ws.part, C2, st); break;
-    default: launch_blend_q<4>(h, recs, x, Q, plan, ws.far2, ws.part, C2, st); break;
+    case 1: launch_blend_q<1>(h, recs, x, Q, plan, ws.far2, ws.part, C2, S2, st); break;
+    case 2: launch_blend_q<2>(h, recs, x, Q, plan, ws.far2, ws.part, C2, S2, st); break;
+    case 8: launch_blend_q<8>(h, recs, x, Q, plan, ws.far2, ws.part, C2, S2, st); break;
+    default: launch_blend_q<4>(h, recs, x, Q, plan, ws.far2, ws.part, C2, S2, st); break;
   }
   return check_hip(hipGetLastError(), "blend kernel");
 }

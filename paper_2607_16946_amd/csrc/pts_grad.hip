@@ -66,21 +66,21 @@ __global__ __launch_bounds__(kBlock) void k_combine_stats(const Header* __restri
 
 // kFull = false: only D (the weight sweep of the point backward).
 template <bool kDirect, bool kFull>
-__device__ __forceinline__ void grad_pair(float qx, float qy, float qz, float nl, float C2, float phi,
+__device__ __forceinline__ void grad_pair(float qx, float qy, float qz, float nl, float S2, float phi,
                                           const float4& P, const float4& U, const float4& Mv, const float4& K,
                                           const float4& G, float* A, float* B, float& D) {
   const float dx = qx - P.x, dy = qy - P.y, dz = qz - P.z;
   const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
   if (!kFull) {  // the weight sweep needs neither reciprocals nor grad g: the blend's forms
     const float d = hw_sqrt(d2);
-    const float w = hw_exp2(fmaf(d, nl, C2));
+    const float w = hw_exp2(fmaf(d, nl, S2));
     const float g = kDirect ? g_direct(qx, qy, qz, U, Mv, K, G) : g_anchored(qx, qy, qz, P.w, U, Mv, K, G);
     D = fmaf(w * (g - phi), d, D);
     return;
   }
   const float id = safe_rsq(d2);                   // 1/d
   const float d = d2 * id;
-  const float w = hw_exp2(fmaf(d, nl, C2));
+  const float w = hw_exp2(fmaf(d, nl, S2));
   const Geo r = kDirect ? geo_direct(qx, qy, qz, U, Mv, K, G) : geo_anchored(qx, qy, qz, P.w, U, Mv, K, G);
   const float we = w * (r.g - phi);
   const float sq = G.z * r.iqn;
@@ -105,7 +105,7 @@ __device__ __forceinline__ void grad_pair(float qx, float qy, float qz, float nl
 template <int QPL, bool kFull>
 __global__ __launch_bounds__(kBlock) void k_grad(const Header* __restrict__ h, const float4* __restrict__ rec,
                                                  const float* __restrict__ x, int64_t Q, int S, int64_t per_split,
-                                                 const float* __restrict__ stats, float C2,
+                                                 const float* __restrict__ stats, float C2, float S2,
                                                  float4* __restrict__ gpart, float* __restrict__ vpart) {
   __shared__ float4 tile[kTile2 * kRecF4];
   const int split = int(blockIdx.x % unsigned(S));
@@ -147,13 +147,13 @@ __global__ __launch_bounds__(kBlock) void k_grad(const Header* __restrict__ h, c
       const float4 P = tile[j * kRecF4 + 0], U = tile[j * kRecF4 + 1], Mv = tile[j * kRecF4 + 2],
                    K = tile[j * kRecF4 + 3], G = tile[j * kRecF4 + 4];
 #pragma unroll
-      for (int k = 0; k < QPL; ++k) grad_pair<true, kFull>(qx[k], qy[k], qz[k], nl[k], C2, ph[k], P, U, Mv, K, G, tA[k], tB[k], tD[k]);
+      for (int k = 0; k < QPL; ++k) grad_pair<true, kFull>(qx[k], qy[k], qz[k], nl[k], S2, ph[k], P, U, Mv, K, G, tA[k], tB[k], tD[k]);
     }
     for (int j = jd; j < cnt; ++j) {
       const float4 P = tile[j * kRecF4 + 0], U = tile[j * kRecF4 + 1], Mv = tile[j * kRecF4 + 2],
                    K = tile[j * kRecF4 + 3], G = tile[j * kRecF4 + 4];
 #pragma unroll
-      for (int k = 0; k < QPL; ++k) grad_pair<false, kFull>(qx[k], qy[k], qz[k], nl[k], C2, ph[k], P, U, Mv, K, G, tA[k], tB[k], tD[k]);
+      for (int k = 0; k < QPL; ++k) grad_pair<false, kFull>(qx[k], qy[k], qz[k], nl[k], S2, ph[k], P, U, Mv, K, G, tA[k], tB[k], tD[k]);
     }
 #pragma unroll
     for (int k = 0; k < QPL; ++k) {
@@ -199,9 +199,9 @@ __global__ __launch_bounds__(kBlock) void k_grad_combine(const float4* __restric
 
 template <int QPL, bool kFull>
 void launch_grad_sweep(const Header* h, const float4* rec, const float* x, int64_t Q, const Plan& plan,
-                       const float* stats, float C2, float4* gpart, float* vpart, hipStream_t st) {
+                       const float* stats, float C, float4* gpart, float* vpart, hipStream_t st) {
   hipLaunchKernelGGL((k_grad<QPL, kFull>), dim3(unsigned(plan.nqb * plan.S)), dim3(kBlock), 0, st, h, rec, x, Q,
-                     plan.S, plan.per_split, stats, C2, gpart, vpart);
+                     plan.S, plan.per_split, stats, C * kLog2e, shift2_of(C), gpart, vpart);
 }
 
 }  // namespace
@@ -227,12 +227,11 @@ int launch_grad(const void* rec, int64_t N, const float* x, int64_t Q, const flo
   const char* base = static_cast<const char*>(rec);
   const Header* h = reinterpret_cast<const Header*>(base);
   const float4* recs = reinterpret_cast<const float4*>(base + L.rec);
-  const float C2 = C * kLog2e;
   const int qpl = plan.qpl > 2 ? 2 : plan.qpl;
   const Plan p = with_qpl(plan, qpl, Q);
   switch (qpl) {
-    case 1: launch_grad_sweep<1, true>(h, recs, x, Q, p, stats, C2, ws.gpart, nullptr, st); break;
-    default: launch_grad_sweep<2, true>(h, recs, x, Q, p, stats, C2, ws.gpart, nullptr, st); break;
+    case 1: launch_grad_sweep<1, true>(h, recs, x, Q, p, stats, C, ws.gpart, nullptr, st); break;
+    default: launch_grad_sweep<2, true>(h, recs, x, Q, p, stats, C, ws.gpart, nullptr, st); break;
   }
   hipLaunchKernelGGL(k_grad_combine, dim3(unsigned((Q + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, ws.gpart,
                      stats, plan.S, Q, C, gout, gx);
@@ -245,12 +244,11 @@ int launch_vsum(const void* rec, int64_t N, const float* x, int64_t Q, const flo
   const char* base = static_cast<const char*>(rec);
   const Header* h = reinterpret_cast<const Header*>(base);
   const float4* recs = reinterpret_cast<const float4*>(base + L.rec);
-  const float C2 = C * kLog2e;
   const int qpl = plan.qpl > 2 ? 2 : plan.qpl;
   const Plan p = with_qpl(plan, qpl, Q);
   switch (qpl) {
-    case 1: launch_grad_sweep<1, false>(h, recs, x, Q, p, stats, C2, nullptr, vpart, st); break;
-    default: launch_grad_sweep<2, false>(h, recs, x, Q, p, stats, C2, nullptr, vpart, st); break;
+    case 1: launch_grad_sweep<1, false>(h, recs, x, Q, p, stats, C, nullptr, vpart, st); break;
+    default: launch_grad_sweep<2, false>(h, recs, x, Q, p, stats, C, nullptr, vpart, st); break;
   }
   return check_hip(hipGetLastError(), "weight sweep kernel");
 }

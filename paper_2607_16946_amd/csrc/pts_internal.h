@@ -19,6 +19,21 @@ constexpr int kTile2 = 128;               // points per LDS tile, blend pass (80
 constexpr int kTile1 = 512;               // points per LDS tile, farthest-point pass (16 B each)
 constexpr int kRecF4 = 5;                 // float4 per point record
 constexpr float kLog2e = 1.4426950408889634f;
+// Screening constant C (Eq. RelationshipBetweenLambdaAndRadius) and the
+// additive shift of the weights.  The paper shifts every exponent by
+// lambda_x sigma_x = C (Eq. BasicFormulaShifted), so the weights lie in
+// [e^-C, e^C]; phi does not depend on the shift, only the FP32 range of the
+// sums does.  The kernels shift by s = min(C, 64): the largest weight is then
+// at most e^64, so sums over N points of w |g| stay below FLT_MAX while
+// N max|g| < 5e10, and the smallest, e^(s - 2C), stays a normal FP32 number
+// (>= 2^-126) for every C <= 75.  s = C for the paper's C = 64.
+constexpr float kShiftMaxC = 64.0f;
+constexpr float kCMax = 75.0f;
+// Smallest relative curvature floor: torus radii reach D / kfloor_rel, and the
+// anchored form squares them (t^2 with t ~ L), so L must stay well below
+// sqrt(FLT_MAX) ~ 1.8e19 for clouds up to D ~ 1e6.
+constexpr float kKfloorRelMin = 1e-12f;
+__host__ __device__ inline float shift2_of(float C) { return (C < kShiftMaxC ? C : kShiftMaxC) * kLog2e; }
 constexpr double kDirectMaxL = 4.0;       // direct torus form when L <= 4 D
 constexpr int kUnit = 64;                 // points per culling unit of the farthest-point pass
 constexpr int kBlkU = 64;                 // units per block of the two-level sphere hierarchy
@@ -48,7 +63,7 @@ struct alignas(256) Header {
   float rl_lambda;      // 1e3 / rl_D
   float rl_reval;       // 2 C / rl_lambda
   int32_t rl_ready;     // 1 once the three values above are set
-  int32_t pad1;
+  float rl_shift;       // min(C, 64) / rl_lambda: the exponent shift (a distance) of the radius branch
   uint32_t a00max_bits; // bits of max_i |a00_i| (non-negative, so integer order is float order)
   int32_t pad2;
 };

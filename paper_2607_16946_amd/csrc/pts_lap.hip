@@ -53,14 +53,14 @@ constexpr int kLapD2 = 11;  // partials per (split, query): 22 doubles in 11 dou
 constexpr int kSub = 16;    // points per FP32 run before the FP64 carry
 
 template <bool kDirect>
-__device__ __forceinline__ void lap_pair(float qx, float qy, float qz, float nl, float C2, float phi,
+__device__ __forceinline__ void lap_pair(float qx, float qy, float qz, float nl, float S2, float phi,
                                          float ex, float ey, float ez, const float4& P, const float4& U,
                                          const float4& Mv, const float4& K, const float4& G, float* a) {
   const float dx = qx - P.x, dy = qy - P.y, dz = qz - P.z;
   const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
   const float id = safe_rsq(d2);                                    // 1/d
   const float d = d2 * id;
-  const float w = hw_exp2(fmaf(d, nl, C2));
+  const float w = hw_exp2(fmaf(d, nl, S2));
   const Geo r = kDirect ? geo_direct(qx, qy, qz, U, Mv, K, G) : geo_anchored(qx, qy, qz, P.w, U, Mv, K, G);
   const float sq = G.z * r.iqn;
   const float bir = r.b * r.irho;
@@ -105,7 +105,7 @@ __device__ __forceinline__ void lap_pair(float qx, float qy, float qz, float nl,
 template <int QPL>
 __global__ __launch_bounds__(kBlock) void k_lap(const Header* __restrict__ h, const float4* __restrict__ rec,
                                                 const float* __restrict__ x, int64_t Q, int S, int64_t per_split,
-                                                const float* __restrict__ stats, float C2,
+                                                const float* __restrict__ stats, float C2, float S2,
                                                 double2* __restrict__ part) {
   __shared__ float4 tile[kTile2 * kRecF4];
   const int split = int(blockIdx.x % unsigned(S));
@@ -153,14 +153,14 @@ __global__ __launch_bounds__(kBlock) void k_lap(const Header* __restrict__ h, co
                      K = tile[j * kRecF4 + 3], G = tile[j * kRecF4 + 4];
 #pragma unroll
         for (int k = 0; k < QPL; ++k)
-          lap_pair<true>(qx[k], qy[k], qz[k], nl[k], C2, ph[k], es[k][0], es[k][1], es[k][2], P, U, Mv, K, G, T[k]);
+          lap_pair<true>(qx[k], qy[k], qz[k], nl[k], S2, ph[k], es[k][0], es[k][1], es[k][2], P, U, Mv, K, G, T[k]);
       }
       for (int j = max(j0, jd); j < j1; ++j) {
         const float4 P = tile[j * kRecF4 + 0], U = tile[j * kRecF4 + 1], Mv = tile[j * kRecF4 + 2],
                      K = tile[j * kRecF4 + 3], G = tile[j * kRecF4 + 4];
 #pragma unroll
         for (int k = 0; k < QPL; ++k)
-          lap_pair<false>(qx[k], qy[k], qz[k], nl[k], C2, ph[k], es[k][0], es[k][1], es[k][2], P, U, Mv, K, G, T[k]);
+          lap_pair<false>(qx[k], qy[k], qz[k], nl[k], S2, ph[k], es[k][0], es[k][1], es[k][2], P, U, Mv, K, G, T[k]);
       }
 #pragma unroll
       for (int k = 0; k < QPL; ++k)
@@ -238,9 +238,9 @@ __global__ __launch_bounds__(kBlock) void k_lap_combine(const double2* __restric
 
 template <int QPL>
 void launch_lap_sweep(const Header* h, const float4* rec, const float* x, int64_t Q, const Plan& plan,
-                      const float* stats, float C2, double2* part, hipStream_t st) {
+                      const float* stats, float C, double2* part, hipStream_t st) {
   hipLaunchKernelGGL(k_lap<QPL>, dim3(unsigned(plan.nqb * plan.S)), dim3(kBlock), 0, st, h, rec, x, Q, plan.S,
-                     plan.per_split, stats, C2, part);
+                     plan.per_split, stats, C * kLog2e, shift2_of(C), part);
 }
 
 }  // namespace
@@ -256,9 +256,8 @@ int launch_lap(const void* rec, int64_t N, const float* x, int64_t Q, const floa
   const Header* h = reinterpret_cast<const Header*>(base);
   const float4* recs = reinterpret_cast<const float4*>(base + L.rec);
   double2* part = static_cast<double2*>(ws);
-  const float C2 = C * kLog2e;
   const Plan p = with_qpl(plan, 1, Q);
-  launch_lap_sweep<1>(h, recs, x, Q, p, stats, C2, part, st);
+  launch_lap_sweep<1>(h, recs, x, Q, p, stats, C, part, st);
   hipLaunchKernelGGL(k_lap_combine, dim3(unsigned((Q + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, part, stats,
                      plan.S, Q, C, lap, grad, eik);
   return check_hip(hipGetLastError(), "Laplacian kernels");

@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kBlock) void k_far_multi(const WorkDesc* __restrict
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_blend_multi(const WorkDesc* __restrict__ descs, float C2) {
+__global__ __launch_bounds__(kBlock) void k_blend_multi(const WorkDesc* __restrict__ descs, float C2, float S2) {
   __shared__ float4 tile[kTile2 * kRecF4];
   const WorkDesc d = descs[blockIdx.x];
   const Header* h = reinterpret_cast<const Header*>(d.rec);
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kBlock) void k_blend_multi(const WorkDesc* __restri
       for (int k = 0; k < kQpl; ++k) {
         const float dx = qx[k] - P.x, dy = qy[k] - P.y, dz = qz[k] - P.z;
         const float dd = hw_sqrt(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
-        const float w = hw_exp2(fmaf(dd, nl[k], C2));
+        const float w = hw_exp2(fmaf(dd, nl[k], S2));
         const float g = g_direct(qx[k], qy[k], qz[k], U, Mv, K, G);
         tn[k] = fmaf(w, g, tn[k]);
         td[k] += w;
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kBlock) void k_blend_multi(const WorkDesc* __restri
       for (int k = 0; k < kQpl; ++k) {
         const float dx = qx[k] - P.x, dy = qy[k] - P.y, dz = qz[k] - P.z;
         const float dd = hw_sqrt(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
-        const float w = hw_exp2(fmaf(dd, nl[k], C2));
+        const float w = hw_exp2(fmaf(dd, nl[k], S2));
         const float g = g_anchored(qx[k], qy[k], qz[k], P.w, U, Mv, K, G);
         tn[k] = fmaf(w, g, tn[k]);
         td[k] += w;
@@ -143,7 +143,8 @@ int launch_multi(const WorkDesc* d_work, int64_t n_work, const CombDesc* d_comb,
                  hipStream_t st) {
   if (n_work > 0) {
     hipLaunchKernelGGL(k_far_multi, dim3(unsigned(n_work)), dim3(kBlock), 0, st, d_work);
-    hipLaunchKernelGGL(k_blend_multi, dim3(unsigned(n_work)), dim3(kBlock), 0, st, d_work, C * kLog2e);
+    hipLaunchKernelGGL(k_blend_multi, dim3(unsigned(n_work)), dim3(kBlock), 0, st, d_work, C * kLog2e,
+                       shift2_of(C));
   }
   if (n_comb > 0) hipLaunchKernelGGL(k_combine_multi, dim3(unsigned(n_comb)), dim3(kBlock), 0, st, d_comb);
   return check_hip(hipGetLastError(), "packed eval kernels");

@@ -219,6 +219,7 @@ __global__ __launch_bounds__(1024) void k_knn_finish(Header* __restrict__ h, con
     h->rl_D = D;
     h->rl_lambda = float(lam);
     h->rl_reval = float(2.0 * double(C) / lam);
+    h->rl_shift = float(double(C < kShiftMaxC ? C : kShiftMaxC) / lam);  // = rl_reval / 2 for C <= 64
     h->rl_ready = 1;
   }
 }
@@ -241,7 +242,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_radius(const Header* __restrict
   const float4* rec = reinterpret_cast<const float4*>(static_cast<const char*>(recb) + Layout(N).rec);
   const float lam2 = h->rl_lambda * kLog2e, reval = h->rl_reval;
   float num = 0.f, den = 0.f;
-  int cnt = blend_within(T, rec, h->n_direct, qi.x, qi.y, qi.z, reval * reval, 0.5f * reval, lam2, num, den);
+  int cnt = blend_within(T, rec, h->n_direct, qi.x, qi.y, qi.z, reval * reval, h->rl_shift, lam2, num, den);
   if (cnt == 0) {
     float a[kKnnFb];
     knn<kKnnFb>(T, qi.x, qi.y, qi.z, -1, a);

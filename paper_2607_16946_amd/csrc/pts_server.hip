@@ -42,6 +42,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstdlib>
 #include <cstring>
@@ -1089,8 +1090,9 @@ int pts_server_create(const pts_server_cfg* cfg, pts_server** out) {
   if (c.max_queue <= 0) c.max_queue = 1 << 20;
   if (c.max_batch_work <= 0) c.max_batch_work = 131072;
   if (c.max_batch_work > (int64_t(1) << 24)) return fail(PTS_EINVAL, "max_batch_work must be <= 2^24");
-  if (c.C != 0.f && !(c.C > 0.f && c.C <= 87.f)) return fail(PTS_EINVAL, "C must be in (0, 87]");
-  if (!(c.kfloor_rel >= 0.f)) return fail(PTS_EINVAL, "kfloor_rel must be >= 0");
+  if (c.C != 0.f && !(c.C > 0.f && c.C <= pts::kCMax)) return fail(PTS_EINVAL, "C must be in (0, 75]");
+  if (!(c.kfloor_rel == 0.f || (c.kfloor_rel >= pts::kKfloorRelMin && std::isfinite(c.kfloor_rel))))
+    return fail(PTS_EINVAL, "kfloor_rel must be 0 (default) or in [1e-12, inf)");
   if (c.mock && !(c.mock_pairs_per_s >= 0)) return fail(PTS_EINVAL, "mock_pairs_per_s must be >= 0");
   auto h = std::make_unique<pts_server>();
   h->s = std::make_unique<pts::Server>(c);

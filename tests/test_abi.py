@@ -74,6 +74,27 @@ def test_host_side_errors(L):
     assert wp.value >= wa.value * 12 // 8 + 3000 * (4 + 4 + 48)
 
 
+def test_parameter_ranges(L):
+    """C in (0, 75] (the weights' FP32 range with the shift min(C, 64)); kfloor_rel >= 1e-12."""
+    out = ctypes.c_size_t(0)
+    for C, ok in ((75.0, True), (64.0, True), (0.5, True), (75.5, False), (87.0, False), (-1.0, False)):
+        prm = binding.make_params(C=C)
+        rc = L.pts_eval_ws_bytes(10, 10, ctypes.byref(prm), ctypes.byref(out))
+        assert (rc == binding.PTS_OK) == ok, C
+    for kf, ok in ((1e-12, True), (1e-6, True), (1e-13, False), (float("inf"), False)):
+        prm = binding.make_params(kfloor_rel=kf)
+        rc = L.pts_eval_ws_bytes(10, 10, ctypes.byref(prm), ctypes.byref(out))
+        assert (rc == binding.PTS_OK) == ok, kf
+    cfg = binding.ServerCfg()
+    cfg.mock = 1
+    cfg.C = 80.0
+    srv = ctypes.c_void_p()
+    assert L.pts_server_create(ctypes.byref(cfg), ctypes.byref(srv)) == binding.PTS_EINVAL
+    cfg.C = 0.0
+    cfg.kfloor_rel = 1e-13
+    assert L.pts_server_create(ctypes.byref(cfg), ctypes.byref(srv)) == binding.PTS_EINVAL
+
+
 def test_noalloc_refuses_a_workspace_beyond_its_static_scratch(L):
     # checked on the host before any device call: 2^22 queries with 8 splits need 512 MiB > 64 MiB
     prm = binding.make_params()

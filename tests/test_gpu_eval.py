@@ -276,3 +276,26 @@ def test_invalid_inputs_rejected():
     rc = binding.lib().pts_eval(binding._ptr(c.rec), c.N, binding._ptr(x), 10, binding._ptr(out), None, None,
                                 ctypes.byref(c.params), binding._ptr(ws), 16, binding._stream())
     assert rc == binding.PTS_EINVAL and b"workspace" in binding.lib().pts_last_error()
+
+
+def test_blend_weights_three_spheres_hand_derived():
+    """The hand-derived three-sphere blend (Sec. 4.2, Eqs. BasicFormulaShifted and
+    RelationshipBetweenLambdaAndRadius; App. D) through pts_eval: phi, its statistics and grad phi
+    against the stored closed forms, at C = 64 and C = 4."""
+    import json
+    import os
+    G = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "blend_weights.json")))
+    p, n, a = (np.array(G[k], dtype=np.float32) for k in ("p", "n", "a"))
+    x = np.array([G["x"]], dtype=np.float32)
+    D = float(np.linalg.norm(p.max(0).astype(np.float64) - p.min(0)))
+    for case in G["cases"]:
+        _say(f"three spheres, C = {case['C']}")
+        prm = binding.make_params(C=case["C"])
+        c = binding.Cloud(_dev(p), _dev(n), _dev(a), C=case["C"])
+        phi, g, st = binding.eval(c.rec, 3, _dev(x), prm, grad=True, stats=True)
+        phi, g, st = phi.cpu().numpy(), g.cpu().numpy(), st.cpu().numpy()
+        _say(f"  phi {phi[0]:.8f} (closed form {case['phi']:.8f}), grad {g[0]} ({case['grad']})")
+        assert abs(phi[0] - case["phi"]) <= TOL_REL * D
+        assert np.abs(g[0] - np.array(case["grad"])).max() <= 1e-4 * max(1.0, np.abs(case["grad"]).max())
+        assert abs(st[0, 0] - case["M"]) <= 1e-6 * case["M"]
+        assert abs(st[0, 2] - case["phi"]) <= TOL_REL * D
