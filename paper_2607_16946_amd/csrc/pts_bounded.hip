@@ -392,6 +392,18 @@ BoundedWs bounded_ws(const Plan& plan, int64_t Q, void* ws) {
 
 size_t bounded_ws_bytes(const Plan& plan, int64_t Q) { return bounded_ws(plan, Q, nullptr).bytes; }
 
+int launch_query_order(const void* rec, const float* x, int64_t Q, uint32_t* key[2], int32_t* idx[2],
+                       int32_t* rhist, hipStream_t st, const int32_t** order) {
+  const Header* h = static_cast<const Header*>(rec);
+  hipLaunchKernelGGL(k_qkeys, dim3(unsigned((Q + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, h, x, Q, key[0],
+                     idx[0]);
+  if (int rc = check_hip(hipGetLastError(), "query key kernel")) return rc;
+  int cur = 0;
+  if (int rc = launch_radix_sort(key, idx, Q, 6, rhist, st, &cur)) return rc;
+  *order = idx[cur];
+  return PTS_OK;
+}
+
 int launch_bounded(const void* rec, int64_t N, const float* x, int64_t Q, float eps, float C, const Plan& plan,
                    void* ws, float* sdf, float* bound, int32_t* kept, hipStream_t st, float offset) {
   const Layout L(N);
@@ -402,10 +414,8 @@ int launch_bounded(const void* rec, int64_t N, const float* x, int64_t Q, float 
   const float4* bb = reinterpret_cast<const float4*>(base + L.bb);
   BoundedWs v = bounded_ws(plan, Q, ws);
   const unsigned qblocks = unsigned((Q + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL(k_qkeys, dim3(qblocks), dim3(kBlock), 0, st, h, x, Q, v.key[0], v.idx[0]);
-  int cur = 0;
-  if (int rc = launch_radix_sort(v.key, v.idx, Q, 6, v.rhist, st, &cur)) return rc;
-  const int32_t* order = v.idx[cur];
+  const int32_t* order = nullptr;
+  if (int rc = launch_query_order(rec, x, Q, v.key, v.idx, v.rhist, st, &order)) return rc;
   if (int rc = launch_far_cull(rec, N, x, Q, plan.qpl, v.far2, nullptr, st)) return rc;
   // heavy query blocks first
   const float C2 = C * kLog2e, S2 = shift2_of(C);

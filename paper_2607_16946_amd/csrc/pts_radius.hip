@@ -11,6 +11,10 @@
 // the nearest distance, which keeps the largest weight at 1; phi does not
 // depend on the shift).
 //
+// Queries are taken in Morton order of the cloud's bbox (a radix sort of
+// their keys on the device), so that neighbouring lanes walk the same part of
+// the hierarchy instead of the union of 64 unrelated walks.
+//
 // Search structure: the build orders points spatially and bounds every unit
 // of kUnit slots and every block of kBlkU units by a sphere.  Each lane owns one
 // query and walks the blocks and units in slot order, skipping every sphere
@@ -224,12 +228,17 @@ __global__ __launch_bounds__(1024) void k_knn_finish(Header* __restrict__ h, con
   }
 }
 
-// phi at queries: points within R_eval, else the 32 nearest.
+// phi at queries: points within R_eval, else the 32 nearest.  Lane i takes the
+// i-th query in Morton order (order[i]), so a wavefront's queries are a compact
+// brick and its lanes walk nearly the same blocks and units; results go back to
+// the query's own index.
 __global__ __launch_bounds__(kBlock) void k_eval_radius(const Header* __restrict__ h, const void* __restrict__ recb,
                                                         const float* __restrict__ x, int64_t Q,
+                                                        const int32_t* __restrict__ order,
                                                         float* __restrict__ sdf, int32_t* __restrict__ count) {
-  const int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (q >= Q) return;
+  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= Q) return;
+  const int64_t q = order[i];
   const int64_t N = h->N;
   const QueryIn qi = load_query(x, q, Q, h);
   const bool finite = isfinite(qi.x) && isfinite(qi.y) && isfinite(qi.z);
@@ -275,11 +284,41 @@ int launch_radius_prepare(void* rec, int64_t N, float C, hipStream_t st) {
   return check_hip(hipGetLastError(), "radius prepare kernels");
 }
 
+// Workspace: Morton keys and query indices [2][Q] each, radix histograms.
+namespace {
+struct RadiusWs {
+  uint32_t* key[2];
+  int32_t* idx[2];
+  int32_t* rhist;
+  size_t bytes;
+};
+RadiusWs radius_ws(int64_t Q, void* ws) {
+  char* c = static_cast<char*>(ws);
+  RadiusWs v;
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    char* r = c ? c + o : nullptr;
+    o += align256(b);
+    return r;
+  };
+  for (int k = 0; k < 2; ++k) v.key[k] = reinterpret_cast<uint32_t*>(take(size_t(Q) * 4));
+  for (int k = 0; k < 2; ++k) v.idx[k] = reinterpret_cast<int32_t*>(take(size_t(Q) * 4));
+  v.rhist = reinterpret_cast<int32_t*>(take(size_t((Q + kBlock - 1) / kBlock) * 16 * 4));
+  v.bytes = o;
+  return v;
+}
+}  // namespace
+
+size_t eval_radius_ws_bytes(int64_t Q) { return radius_ws(Q, nullptr).bytes; }
+
 int launch_eval_radius(const void* rec, int64_t N, const float* x, int64_t Q, float* sdf, int32_t* count,
-                       hipStream_t st) {
+                       void* ws, hipStream_t st) {
   (void)N;
+  RadiusWs v = radius_ws(Q, ws);
+  const int32_t* order = nullptr;
+  if (int rc = launch_query_order(rec, x, Q, v.key, v.idx, v.rhist, st, &order)) return rc;
   hipLaunchKernelGGL(k_eval_radius, dim3(unsigned((Q + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
-                     static_cast<const Header*>(rec), rec, x, Q, sdf, count);
+                     static_cast<const Header*>(rec), rec, x, Q, order, sdf, count);
   return check_hip(hipGetLastError(), "radius evaluation kernel");
 }
 

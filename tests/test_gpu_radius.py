@@ -160,3 +160,20 @@ def test_radius_edge_cases():
     fresh = binding.Cloud(_dev(base.p), _dev(base.n), _dev(base.a))
     phi, cnt = binding.eval_radius(fresh.rec, fresh.N, _dev(x[:1]), count=True)
     assert np.isnan(phi.item()) and cnt.item() == 0
+
+
+def test_radius_result_does_not_depend_on_query_order():
+    """Queries run in Morton order of the bbox; a query's value and count must be bitwise the same whatever
+    the other queries of the call (a permuted set, a subset, a single query)."""
+    cl, _ = synth.mid(N=5000, grid=4)
+    c, info = _prep(cl)
+    x = np.random.default_rng(17).uniform(-1.3, 1.3, size=(3001, 3)).astype(np.float32)
+    phi, cnt = binding.eval_radius(c.rec, c.N, _dev(x), count=True)
+    perm = np.random.default_rng(18).permutation(len(x))
+    phi_p, cnt_p = binding.eval_radius(c.rec, c.N, _dev(x[perm]), count=True)
+    assert torch.equal(phi_p.cpu(), phi.cpu()[perm]) and torch.equal(cnt_p.cpu(), cnt.cpu()[perm])
+    sub = np.arange(5, 3001, 37)
+    phi_s, cnt_s = binding.eval_radius(c.rec, c.N, _dev(x[sub]), count=True)
+    assert torch.equal(phi_s.cpu(), phi.cpu()[sub]) and torch.equal(cnt_s.cpu(), cnt.cpu()[sub])
+    phi_1 = binding.eval_radius(c.rec, c.N, _dev(x[7:8]))
+    assert torch.equal(phi_1.cpu(), phi.cpu()[7:8])
