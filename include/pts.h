@@ -93,9 +93,10 @@ typedef struct pts_params {
                         magnitude are raised to +-kappa_floor (sign(0) = -1),
                         which keeps planar and cylindrical points at finite,
                         very large torus radii (Sec. 6, "Sharp feature extraction"). */
-  int splits;        /* 0 = automatic.  Otherwise the number of point ranges a
-                        query's sum is split over (power of two, <= 64); results
-                        depend on it only through FP32 rounding order. */
+  int splits;        /* 0 = automatic (up to 1024, see pts_eval_plan).  Otherwise
+                        the number of point ranges a query's sum is split over
+                        (power of two, <= 64); results depend on it only
+                        through FP32 rounding order. */
   float offset;      /* default 0.  pts_eval, pts_eval_bounded and pts_eval_baseline
                         return phi - offset, the signed distance to the offset
                         surface phi = offset (Sec. 5.2, "Offset surfaces and
@@ -155,8 +156,11 @@ int pts_cloud_decode(const void* rec, int64_t N, float* out, void* stream);
 
 /* Launch plan pts_eval uses for N points and Q queries (a pure function of N,
  * Q and the parameters): queries per lane, number of point splits, and points
- * per split (a multiple of 128; splits * per_split >= N, every split
- * non-empty).  For inspection and tests; host only. */
+ * per split (a multiple of 64; splits * per_split >= N, every split
+ * non-empty).  Few queries get many short splits (down to 64 points, at most
+ * 1024 splits): a workgroup walks its split serially, so the split length
+ * sets the latency of a small evaluation.  For inspection and tests; host
+ * only. */
 int pts_eval_plan(int64_t N, int64_t Q, const pts_params* prm, int* qpl, int* splits,
                   int64_t* per_split);
 
@@ -230,9 +234,12 @@ int pts_eval_bounded(const void* rec, int64_t N, const float* x, int64_t Q, floa
                      float* bound, int32_t* kept, const pts_params* prm, void* ws, size_t ws_bytes,
                      void* stream);
 
-/* The three launches of pts_eval without gradient or statistics as separate
+/* The three stages of pts_eval without gradient or statistics as separate
  * calls, with the same arguments and workspace, for callers that time or
- * schedule them individually (pts_eval is exactly these three in order):
+ * schedule them individually; the three in order give pts_eval's result bit
+ * for bit (pts_eval itself skips the folding of the farthest-point sweep's
+ * per-split maxima that pts_eval_far does when there are at most 16 of them,
+ * and lets the blend sweep take their maximum):
  *   pts_eval_far      farthest-point sweep: M = max_i |x - p_i| per query and
  *                     point split (Eq. RelationshipBetweenLambdaAndRadius);
  *   pts_eval_blend    weighted sweep: per split, sum_i w_i g_i and sum_i w_i
@@ -427,13 +434,20 @@ int pts_radius_prepare(void* rec, int64_t N, const pts_params* prm, void* stream
 /* Read them back (blocks). */
 int pts_radius_info_get(const void* rec, pts_radius_info* out, void* stream);
 
+/* Scratch bytes for pts_eval_radius with Q queries (16 bytes per query plus
+ * radix-sort histograms). */
+int pts_eval_radius_ws_bytes(int64_t N, int64_t Q, size_t* out_bytes);
+
 /* Radius-limited phi at Q queries (device x [Q,3] -> sdf [Q]); count [Q]
  * int32 or NULL: number of points blended, negated when the 32-nearest
  * fallback was used, 0 for a query with a non-finite coordinate (phi NaN).
  * phi is NaN everywhere if pts_radius_prepare has not run on the record.
- * Needs no workspace.  Q = 0 is a no-op. */
-int pts_eval_radius(const void* rec, int64_t N, const float* x, int64_t Q, float* sdf, int32_t* count,
-                    void* stream);
+ * The queries are evaluated in Morton order of the cloud's bounding box (a
+ * device radix sort in ws), which only changes the order of work: each
+ * query's result depends on that query alone.  ws_bytes >=
+ * pts_eval_radius_ws_bytes(N, Q).  Q = 0 is a no-op. */
+int pts_eval_radius(const void* rec, int64_t N, const float* x, int64_t Q, float* sdf, int32_t* count, void* ws,
+                    size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Serving: a resident-cloud server with continuous batching.
@@ -455,11 +469,14 @@ int pts_eval_radius(const void* rec, int64_t N, const float* x, int64_t Q, float
  * GPU_MAX_HW_QUEUES=8 or more in its environment (results do not depend on
  * it, latency does).
  *
- * A request on a cloud of N points is evaluated with the point split
- * pts_server_cloud_plan reports, a function of N only (the march split of
- * pts_trace, capped at 64 splits instead of 16): its results are bitwise the
- * same alone or in any mix, and equal pts_eval / pts_trace called with
- * pts_params.splits set to that split (same C, kfloor_rel).
+ * A query request of Q queries on a cloud of N points is evaluated with
+ * pts_eval's automatic plan for (N, Q) -- or, if one launch of max_batch_work
+ * workgroups cannot hold it, with the largest power-of-two split <= 64 that
+ * fits -- and a trace request with the point split pts_server_cloud_plan
+ * reports, a function of N only (the march split of pts_trace, capped at 64
+ * splits instead of 16).  Results are bitwise the same alone or in any mix,
+ * and equal pts_eval (default splits, or the fitting split) and pts_trace
+ * (pts_params.splits set to the cloud's split) with the same C, kfloor_rel.
  *
  * All device memory (records, request buffers, launch descriptors) comes from
  * one allocation of hbm_budget_bytes made at creation; that is the budget

@@ -119,7 +119,8 @@ SIGNATURES = {
                                  ctypes.POINTER(Params), _P, _SZ, _P]),
     "pts_radius_prepare": (ctypes.c_int, [_P, _I64, ctypes.POINTER(Params), _P]),
     "pts_radius_info_get": (ctypes.c_int, [_P, ctypes.POINTER(RadiusInfo), _P]),
-    "pts_eval_radius": (ctypes.c_int, [_P, _I64, _P, _I64, _P, _P, _P]),
+    "pts_eval_radius_ws_bytes": (ctypes.c_int, [_I64, _I64, ctypes.POINTER(_SZ)]),
+    "pts_eval_radius": (ctypes.c_int, [_P, _I64, _P, _I64, _P, _P, _P, _SZ, _P]),
     "pts_server_create": (ctypes.c_int, [ctypes.POINTER(ServerCfg), ctypes.POINTER(_P)]),
     "pts_server_add_cloud": (ctypes.c_int, [_P, _P, _P, _P, _I64, ctypes.POINTER(ctypes.c_int)]),
     "pts_server_cloud_plan": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(_I64), ctypes.POINTER(ctypes.c_int)]),
@@ -527,14 +528,24 @@ def radius_info(rec: torch.Tensor) -> RadiusInfo:
     return out
 
 
-def eval_radius(rec: torch.Tensor, N: int, x: torch.Tensor, count: bool = False):
+def eval_radius_ws_bytes(N: int, Q: int) -> int:
+    out = _SZ(0)
+    _check(lib().pts_eval_radius_ws_bytes(int(N), int(Q), ctypes.byref(out)))
+    return int(out.value)
+
+
+def eval_radius(rec: torch.Tensor, N: int, x: torch.Tensor, count: bool = False, ws: torch.Tensor | None = None):
     """Radius-limited phi (Sec. 4.2) at x [Q,3]; with count=True also the int32 count of blended points
     (negative for the 32-nearest fallback)."""
     _dev(x, "x", 3)
     Q = x.shape[0]
     sdf = torch.empty(Q, dtype=torch.float32, device=x.device)
     cnt = torch.empty(Q, dtype=torch.int32, device=x.device) if count else None
-    _check(lib().pts_eval_radius(_ptr(rec), int(N), _ptr(x), Q, _ptr(sdf), _ptr(cnt), _stream()))
+    need = eval_radius_ws_bytes(N, Q)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 256), dtype=torch.uint8, device=x.device)
+    _check(lib().pts_eval_radius(_ptr(rec), int(N), _ptr(x), Q, _ptr(sdf), _ptr(cnt), _ptr(ws), ws.numel(),
+                                 _stream()))
     return (sdf, cnt) if count else sdf
 
 

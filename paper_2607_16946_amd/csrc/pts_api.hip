@@ -50,7 +50,7 @@ int check_hip(hipError_t e, const char* what) {
   return fail(PTS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-Plan make_plan(int64_t N, int64_t Q, const pts_params* prm) {
+Plan make_plan(int64_t N, int64_t Q, const pts_params* prm, int max_auto_splits) {
   Plan p;
   // queries per lane: 4 once there are enough queries to fill the device
   p.qpl = Q >= 4 * 256 * kBlock ? 4 : (Q >= 2 * 64 * kBlock ? 2 : 1);
@@ -60,20 +60,23 @@ Plan make_plan(int64_t N, int64_t Q, const pts_params* prm) {
   }
   p.nqb = (Q + int64_t(kBlock) * p.qpl - 1) / (int64_t(kBlock) * p.qpl);
   const int64_t tiles = (N + kTile1 - 1) / kTile1;   // farthest-point tiles
-  const int64_t gran = (N + kTile2 - 1) / kTile2;    // blend tiles: the split granularity
+  const int64_t gran = (N + kUnit - 1) / kUnit;      // 64-point units: the split granularity
   int S;
   if (prm && prm->splits > 0) {
     S = prm->splits;
   } else {
     // one split per XCD when there are enough points (each split >= 2
-    // farthest-point tiles); more splits while the grid is too small to fill
-    // 256 CUs, down to 2 blend tiles per split
+    // farthest-point tiles); then, while the grid has fewer than 4096
+    // workgroups (16 waves per CU), more splits, down to one 64-point unit
+    // each and at most max_auto_splits: a workgroup walks its split serially,
+    // so for few queries the split length is the latency (about 0.12 us per
+    // point)
     S = 1;
     while (S < 8 && tiles >= int64_t(2) * S * 2) S *= 2;
-    while (S < 64 && p.nqb * S < 2048 && gran >= int64_t(2) * S * 2) S *= 2;
+    while (S < max_auto_splits && p.nqb * S < 4096 && gran >= int64_t(2) * S) S *= 2;
   }
   S = int(std::max<int64_t>(1, std::min<int64_t>(S, gran)));
-  p.per_split = (gran + S - 1) / S * kTile2;
+  p.per_split = (gran + S - 1) / S * kUnit;
   // splits that would start past the last point are dropped; the remaining
   // S * per_split >= N cover every point
   p.S = int((N + p.per_split - 1) / p.per_split);
@@ -166,12 +169,22 @@ int pts_radius_info_get(const void* rec, pts_radius_info* out, void* stream) {
   return PTS_OK;
 }
 
-int pts_eval_radius(const void* rec, int64_t N, const float* x, int64_t Q, float* sdf, int32_t* count,
-                    void* stream) {
-  if (Q == 0) return PTS_OK;
-  if (!rec || !x || !sdf) return fail(PTS_EINVAL, "null pointer");
+int pts_eval_radius_ws_bytes(int64_t N, int64_t Q, size_t* out_bytes) {
+  if (!out_bytes) return fail(PTS_EINVAL, "out_bytes is NULL");
   if (N < 1 || Q < 0) return fail(PTS_EINVAL, "N must be >= 1 and Q >= 0");
-  return launch_eval_radius(rec, N, x, Q, sdf, count, static_cast<hipStream_t>(stream));
+  if (Q > (int64_t(1) << 31) - 1) return fail(PTS_EINVAL, "Q must be < 2^31");
+  *out_bytes = Q == 0 ? 0 : eval_radius_ws_bytes(Q);
+  return PTS_OK;
+}
+
+int pts_eval_radius(const void* rec, int64_t N, const float* x, int64_t Q, float* sdf, int32_t* count, void* ws,
+                    size_t ws_bytes, void* stream) {
+  if (N < 1 || Q < 0) return fail(PTS_EINVAL, "N must be >= 1 and Q >= 0");
+  if (Q > (int64_t(1) << 31) - 1) return fail(PTS_EINVAL, "Q must be < 2^31");
+  if (Q == 0) return PTS_OK;
+  if (!rec || !x || !sdf || !ws) return fail(PTS_EINVAL, "null pointer");
+  if (ws_bytes < eval_radius_ws_bytes(Q)) return fail(PTS_EINVAL, "workspace too small");
+  return launch_eval_radius(rec, N, x, Q, sdf, count, ws, static_cast<hipStream_t>(stream));
 }
 
 int pts_eval_plan(int64_t N, int64_t Q, const pts_params* prm, int* qpl, int* splits, int64_t* per_split) {
@@ -179,7 +192,7 @@ int pts_eval_plan(int64_t N, int64_t Q, const pts_params* prm, int* qpl, int* sp
   if (N < 1 || Q < 1) return fail(PTS_EINVAL, "N and Q must be >= 1");
   const pts_params P = resolve(prm);
   if (int rc = check_params(P)) return rc;
-  const Plan plan = make_plan(N, Q, &P);
+  const Plan plan = make_plan(N, Q, &P, kPlainSplitMax);
   *qpl = plan.qpl;
   *splits = plan.S;
   *per_split = plan.per_split;
@@ -191,7 +204,7 @@ int pts_eval_ws_bytes(int64_t N, int64_t Q, const pts_params* prm, size_t* out_b
   if (N < 1 || Q < 0) return fail(PTS_EINVAL, "N must be >= 1 and Q >= 0");
   const pts_params P = resolve(prm);
   if (int rc = check_params(P)) return rc;
-  *out_bytes = Q == 0 ? 0 : eval_ws_bytes(make_plan(N, Q, &P), Q);
+  *out_bytes = Q == 0 ? 0 : eval_ws_bytes(make_plan(N, Q, &P, kPlainSplitMax), Q);
   return PTS_OK;
 }
 
@@ -208,13 +221,13 @@ namespace {
 // Common checks; on success *plan and *P are set.  need_grad_ws selects the
 // workspace size that the call requires.
 int eval_checks(int64_t N, int64_t Q, const pts_params* prm, size_t ws_bytes, bool need_grad_ws, Plan* plan,
-                pts_params* P) {
+                pts_params* P, bool plain = false) {
   if (N < 1 || Q < 0) return fail(PTS_EINVAL, "N must be >= 1 and Q >= 0");
   if (Q > (int64_t(1) << 31) - 1) return fail(PTS_EINVAL, "Q must be < 2^31");
   *P = resolve(prm);
   if (int rc = check_params(*P)) return rc;
   if (Q == 0) return PTS_OK;
-  *plan = make_plan(N, Q, P);
+  *plan = make_plan(N, Q, P, plain ? kPlainSplitMax : kAutoSplitMax);
   const size_t need = need_grad_ws ? grad_ws_bytes(*plan, Q) : eval_ws_bytes(*plan, Q);
   if (ws_bytes < need) return fail(PTS_EINVAL, "workspace too small");
   return PTS_OK;
@@ -225,16 +238,12 @@ int pts_eval(const void* rec, int64_t N, const float* x, int64_t Q, float* sdf, 
              const pts_params* prm, void* ws, size_t ws_bytes, void* stream) {
   Plan plan;
   pts_params P;
-  if (int rc = eval_checks(N, Q, prm, ws_bytes, grad != nullptr, &plan, &P)) return rc;
+  if (int rc = eval_checks(N, Q, prm, ws_bytes, grad != nullptr, &plan, &P, !grad && !stats)) return rc;
   if (Q == 0) return PTS_OK;
   if (!rec || !x || !sdf || !ws) return fail(PTS_EINVAL, "null pointer");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const WsView v = ws_view(plan, Q, ws);
-  if (!grad && !stats) {
-    if (int rc = launch_far(rec, N, x, Q, plan, v, st)) return rc;
-    if (int rc = launch_blend(rec, N, x, Q, P.C, plan, v, st)) return rc;
-    return launch_combine(Q, plan, v, sdf, st, P.offset);
-  }
+  if (!grad && !stats) return launch_eval_plain(rec, N, x, Q, P.C, plan, v, sdf, st, P.offset);
   float* st6 = stats ? stats : v.stats;
   if (int rc = launch_far_arg(rec, N, x, Q, plan, v, st)) return rc;
   if (int rc = launch_blend(rec, N, x, Q, P.C, plan, v, st)) return rc;
@@ -252,14 +261,14 @@ int pts_eval_noalloc(const void* rec, int64_t N, const float* x, int64_t Q, floa
   if (Q == 0) return PTS_OK;
   if (!rec || !x || !sdf) return fail(PTS_EINVAL, "null pointer");
   // eval_noalloc refuses a plan whose workspace exceeds the static scratch
-  return eval_noalloc(rec, N, x, Q, sdf, P, make_plan(N, Q, &P), static_cast<hipStream_t>(stream));
+  return eval_noalloc(rec, N, x, Q, sdf, P, make_plan(N, Q, &P, kPlainSplitMax), static_cast<hipStream_t>(stream));
 }
 
 int pts_eval_far(const void* rec, int64_t N, const float* x, int64_t Q, const pts_params* prm, void* ws,
                  size_t ws_bytes, void* stream) {
   Plan plan;
   pts_params P;
-  if (int rc = eval_checks(N, Q, prm, ws_bytes, false, &plan, &P)) return rc;
+  if (int rc = eval_checks(N, Q, prm, ws_bytes, false, &plan, &P, true)) return rc;
   if (Q == 0) return PTS_OK;
   if (!rec || !x || !ws) return fail(PTS_EINVAL, "null pointer");
   return launch_far(rec, N, x, Q, plan, ws_view(plan, Q, ws), static_cast<hipStream_t>(stream));
@@ -269,7 +278,7 @@ int pts_eval_blend(const void* rec, int64_t N, const float* x, int64_t Q, const 
                    size_t ws_bytes, void* stream) {
   Plan plan;
   pts_params P;
-  if (int rc = eval_checks(N, Q, prm, ws_bytes, false, &plan, &P)) return rc;
+  if (int rc = eval_checks(N, Q, prm, ws_bytes, false, &plan, &P, true)) return rc;
   if (Q == 0) return PTS_OK;
   if (!rec || !x || !ws) return fail(PTS_EINVAL, "null pointer");
   return launch_blend(rec, N, x, Q, P.C, plan, ws_view(plan, Q, ws), static_cast<hipStream_t>(stream));
@@ -279,7 +288,7 @@ int pts_eval_combine(int64_t N, int64_t Q, float* sdf, const pts_params* prm, vo
                      void* stream) {
   Plan plan;
   pts_params P;
-  if (int rc = eval_checks(N, Q, prm, ws_bytes, false, &plan, &P)) return rc;
+  if (int rc = eval_checks(N, Q, prm, ws_bytes, false, &plan, &P, true)) return rc;
   if (Q == 0) return PTS_OK;
   if (!sdf || !ws) return fail(PTS_EINVAL, "null pointer");
   return launch_combine(Q, plan, ws_view(plan, Q, ws), sdf, static_cast<hipStream_t>(stream), P.offset);

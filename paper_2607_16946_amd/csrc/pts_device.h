@@ -130,6 +130,70 @@ __device__ __forceinline__ Geo geo_anchored(float x, float y, float z, float L, 
   return r;
 }
 
+// A query's S split partials (sum w g, sum w) summed in a fixed order: in
+// split order by one lane (combine_seq), or by one wavefront (combine_wave),
+// lane l summing splits l, l + 64, ... in order, then a butterfly over the 64
+// lane sums (each step adds a pair of values in both lanes of the pair, and
+// addition is commutative, so every lane ends with the same bits).  Every
+// lane of the wave calls combine_wave; lanes with q >= Q only contribute 0.
+__device__ __forceinline__ float2 combine_seq(const float2* __restrict__ part, int S, int64_t Q, int64_t q) {
+  float num = 0.f, den = 0.f;
+  for (int s = 0; s < S; ++s) {
+    const float2 v = part[int64_t(s) * Q + q];
+    num += v.x;
+    den += v.y;
+  }
+  return make_float2(num, den);
+}
+
+__device__ __forceinline__ float2 combine_wave(const float2* __restrict__ part, int S, int64_t Q, int64_t q,
+                                               int lane) {
+  float num = 0.f, den = 0.f;
+  if (q < Q)
+    for (int s = lane; s < S; s += 64) {
+      const float2 v = part[int64_t(s) * Q + q];
+      num += v.x;
+      den += v.y;
+    }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    num += __shfl_xor(num, o, 64);
+    den += __shfl_xor(den, o, 64);
+  }
+  return make_float2(num, den);
+}
+
+// Fold of a query's S per-split maxima into row 0 of far2 (exact in any
+// order; a NaN row 0 stays NaN, as the comparisons v > m never take a value
+// over it): by one lane, or, for many rows, by one wavefront (lane l taking
+// rows l, l + 64, ..., lane 0 starting from row 0, then a butterfly); only
+// lane 0 of the wave holds the result.
+__device__ __forceinline__ float fold_seq(const float* __restrict__ far2, int S, int64_t Q, int64_t q) {
+  float m = far2[q];
+  for (int s = 1; s < S; ++s) {
+    const float v = far2[int64_t(s) * Q + q];
+    m = v > m ? v : m;
+  }
+  return m;
+}
+
+__device__ __forceinline__ float fold_wave(const float* __restrict__ far2, int S, int64_t Q, int64_t q, int lane) {
+  float m = -3.0e38f;
+  if (q < Q) {
+    if (lane == 0) m = far2[q];
+    for (int s = lane == 0 ? 64 : lane; s < S; s += 64) {
+      const float v = far2[int64_t(s) * Q + q];
+      m = v > m ? v : m;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const float v = __shfl_xor(m, o, 64);
+    m = v > m ? v : m;
+  }
+  return m;
+}
+
 // 1/v, or 0 where v is 0 (the derivative factors it scales vanish there; a
 // subgradient on the torus axis, its core circle, and at the points).
 __device__ __forceinline__ float safe_rcp(float v) { return v > 0.f ? hw_rcp(v) : 0.f; }

@@ -75,8 +75,9 @@ __global__ __launch_bounds__(kBlock) void k_far_cull(const Header* __restrict__ 
 
 // The same sweep for calls with few query blocks, over the blend's point
 // splits as well: workgroup b covers split b % S of query block b / S, with
-// the bound of pts_farcull.h's far_bound_split, and writes row `split` of
-// far2 (and farix).  A split may miss its own maximum but never the cloud's;
+// the bound of pts_farcull.h's far_bound_split (splits of at most
+// kFarPlainMax points are swept whole), and writes row `split` of far2 (and
+// farix).  A split may miss its own maximum but never the cloud's;
 // k_far_fold keeps the largest row and, among equal ones, the first split
 // (the lowest slots), so row 0 ends up bitwise what k_far_cull writes.
 template <int QPL, bool kArg>
@@ -103,10 +104,14 @@ __global__ __launch_bounds__(kBlock) void k_far_split(const Header* __restrict__
   }
   const int64_t beg = int64_t(split) * per_split;
   const int64_t end = min(N, beg + per_split);
-  const int64_t u_lo = beg / kUnit, u_hi = max(u_lo, (end + kUnit - 1) / kUnit);
-  far_bound_split<QPL>(ub, U, u_lo, u_hi, qx, qy, qz, lb, L);
-  far_threshold<QPL>(lb, ok);
-  far_sweep<QPL, kArg>(pos4, ub, u_lo, u_hi, end, qx, qy, qz, ok, lb, acc, ix, L);
+  if (per_split <= kFarPlainMax) {  // uniform across the grid
+    far_sweep_plain<QPL, kArg>(pos4, beg, end, qx, qy, qz, acc, ix, L);
+  } else {
+    const int64_t u_lo = beg / kUnit, u_hi = max(u_lo, (end + kUnit - 1) / kUnit);
+    far_bound_split<QPL>(ub, U, u_lo, u_hi, qx, qy, qz, lb, L);
+    far_threshold<QPL>(lb, ok);
+    far_sweep<QPL, kArg>(pos4, ub, u_lo, u_hi, end, qx, qy, qz, ok, lb, acc, ix, L);
+  }
 #pragma unroll
   for (int k = 0; k < QPL; ++k) {
     const int64_t q = qb * (kBlock * QPL) + k * kBlock + threadIdx.x;
@@ -136,13 +141,24 @@ __global__ __launch_bounds__(kBlock) void k_far_fold(float* __restrict__ far2, i
   if (farix) farix[q] = ix;
 }
 
+// The same fold for many rows (plain sweeps only, no slots): one wavefront per
+// query (fold_wave, pts_device.h).
+__global__ __launch_bounds__(kBlock) void k_far_fold_wave(float* __restrict__ far2, int S, int64_t Q) {
+  const int64_t q = int64_t(blockIdx.x) * (kBlock / 64) + threadIdx.x / 64;
+  const int lane = int(threadIdx.x & 63);
+  const float m = fold_wave(far2, S, Q, q, lane);
+  if (lane == 0 && q < Q) far2[q] = m;
+}
+
 // ---------------------------------------------------------------------------
 // Sweep 2: partial (sum w g, sum w) per split.
 // ---------------------------------------------------------------------------
+// far_rows: rows of far2 holding per-split maxima (1 once k_far_fold has
+// folded them); the blend takes their maximum itself when the fold is skipped.
 template <int QPL>
 __global__ __launch_bounds__(kBlock) void k_blend(const Header* __restrict__ h, const float4* __restrict__ rec,
                                                   const float* __restrict__ x, int64_t Q, int S, int64_t per_split,
-                                                  const float* __restrict__ far2, float C2, float S2,
+                                                  const float* __restrict__ far2, int far_rows, float C2, float S2,
                                                   float2* __restrict__ part) {
   __shared__ float4 tile[kTile2 * kRecF4];
   const int split = int(blockIdx.x % unsigned(S));
@@ -157,7 +173,7 @@ __global__ __launch_bounds__(kBlock) void k_blend(const Header* __restrict__ h, 
     qx[k] = qi.x; qy[k] = qi.y; qz[k] = qi.z;
     float M = 0.f;
     nl[k] = 0.f;
-    if (qi.valid) far_of(far2, 1, Q, q, C2, M, nl[k]);
+    if (qi.valid) far_of(far2, far_rows, Q, q, C2, M, nl[k]);
     num[k] = 0.f;
     den[k] = 0.f;
   }
@@ -209,27 +225,38 @@ __global__ __launch_bounds__(kBlock) void k_blend(const Header* __restrict__ h, 
   }
 }
 
-// Fixed-order combine of the split partials.
+// Fixed-order combine of the split partials (pts_device.h): one lane per
+// query up to kLaneSplitsMax splits, one wavefront per query beyond.
 __global__ __launch_bounds__(kBlock) void k_combine(const float2* __restrict__ part, int S, int64_t Q,
                                                     float* __restrict__ sdf, float offset) {
   const int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x;
   if (q >= Q) return;
-  float num = 0.f, den = 0.f;
-  for (int s = 0; s < S; ++s) {
-    const float2 v = part[int64_t(s) * Q + q];
-    num += v.x;
-    den += v.y;
-  }
-  sdf[q] = num / den - offset;
+  const float2 v = combine_seq(part, S, Q, q);
+  sdf[q] = v.x / v.y - offset;
 }
 
+__global__ __launch_bounds__(kBlock) void k_combine_wave(const float2* __restrict__ part, int S, int64_t Q,
+                                                         float* __restrict__ sdf, float offset) {
+  const int64_t q = int64_t(blockIdx.x) * (kBlock / 64) + threadIdx.x / 64;
+  const int lane = int(threadIdx.x & 63);
+  const float2 v = combine_wave(part, S, Q, q, lane);
+  if (lane == 0 && q < Q) sdf[q] = v.x / v.y - offset;
+}
+
+// fold = false: the split rows are left for the blend to take the maximum of
+// (worth it for a few rows only: every blend workgroup of a query reads them).
 template <int QPL, bool kArg>
 void launch_far_q(const Header* h, const float4* pos4, const float4* ub, const float* x, int64_t Q, int64_t nqb,
-                  int S, int64_t per_split, float* far2, int32_t* farix, hipStream_t st) {
+                  int S, int64_t per_split, float* far2, int32_t* farix, hipStream_t st, bool fold) {
   if (S > 1) {
     hipLaunchKernelGGL((k_far_split<QPL, kArg>), dim3(unsigned(nqb * S)), dim3(kBlock), 0, st, h, pos4, ub, x, Q, S,
                        per_split, far2, farix);
-    hipLaunchKernelGGL(k_far_fold, dim3(unsigned((Q + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, far2, farix, S, Q);
+    if (fold && (farix || S <= kLaneSplitsMax))
+      hipLaunchKernelGGL(k_far_fold, dim3(unsigned((Q + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, far2, farix, S,
+                         Q);
+    else if (fold)
+      hipLaunchKernelGGL(k_far_fold_wave, dim3(unsigned((Q + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), 0, st,
+                         far2, S, Q);
   } else {
     hipLaunchKernelGGL((k_far_cull<QPL, kArg>), dim3(unsigned(nqb)), dim3(kBlock), 0, st, h, pos4, ub, x, Q, far2,
                        farix);
@@ -238,9 +265,26 @@ void launch_far_q(const Header* h, const float4* pos4, const float4* ub, const f
 
 template <int QPL>
 void launch_blend_q(const Header* h, const float4* rec, const float* x, int64_t Q, const Plan& plan,
-                    const float* far2, float2* part, float C2, float S2, hipStream_t st) {
+                    const float* far2, int far_rows, float2* part, float C2, float S2, hipStream_t st) {
   hipLaunchKernelGGL(k_blend<QPL>, dim3(unsigned(plan.nqb * plan.S)), dim3(kBlock), 0, st, h, rec, x, Q, plan.S,
-                     plan.per_split, far2, C2, S2, part);
+                     plan.per_split, far2, far_rows, C2, S2, part);
+}
+
+// The farthest-point sweep's launch shape for an evaluation plan: queries per
+// lane lowered (from at most 4) until there are >= 2048 workgroups, and split
+// over the plan's point ranges when there are fewer than 1024 query blocks.
+struct FarShape {
+  int q;
+  int64_t nqb;
+  int S;
+};
+FarShape far_shape(int qpl, int64_t Q, int S, int64_t per_split) {
+  FarShape f;
+  f.q = qpl >= 4 ? 4 : (qpl == 2 ? 2 : 1);
+  while (f.q > 1 && (Q + int64_t(kBlock) * f.q - 1) / (int64_t(kBlock) * f.q) < 2048) f.q /= 2;
+  f.nqb = (Q + int64_t(kBlock) * f.q - 1) / (int64_t(kBlock) * f.q);
+  f.S = (f.nqb >= 1024 || per_split <= 0) ? 1 : S;
+  return f;
 }
 
 }  // namespace
@@ -279,24 +323,21 @@ int launch_far_cull(const void* rec, int64_t N, const float* x, int64_t Q, int q
   const float4* pos4 = reinterpret_cast<const float4*>(base + L.pos);
   const float4* ub = reinterpret_cast<const float4*>(base + L.ub);
   // one workgroup per query block: keep at least 2048 of them (8 per CU) when
-  // there are queries enough, by lowering the queries per lane
-  int q = qpl >= 4 ? 4 : (qpl == 2 ? 2 : 1);
-  while (q > 1 && (Q + int64_t(kBlock) * q - 1) / (int64_t(kBlock) * q) < 2048) q /= 2;
-  const int64_t nqb = (Q + int64_t(kBlock) * q - 1) / (int64_t(kBlock) * q);
-  // with fewer than 1024 query blocks, sweep the point splits as separate
-  // workgroups (the caller's far2 / farix then hold S rows)
-  if (nqb >= 1024 || per_split <= 0) S = 1;
+  // there are queries enough, by lowering the queries per lane; with fewer
+  // than 1024 query blocks, sweep the point splits as separate workgroups (the
+  // caller's far2 / farix then hold S rows)
+  const FarShape f = far_shape(qpl, Q, S, per_split);
   if (farix) {
-    switch (q) {
-      case 1: launch_far_q<1, true>(h, pos4, ub, x, Q, nqb, S, per_split, far2, farix, st); break;
-      case 2: launch_far_q<2, true>(h, pos4, ub, x, Q, nqb, S, per_split, far2, farix, st); break;
-      default: launch_far_q<4, true>(h, pos4, ub, x, Q, nqb, S, per_split, far2, farix, st); break;
+    switch (f.q) {
+      case 1: launch_far_q<1, true>(h, pos4, ub, x, Q, f.nqb, f.S, per_split, far2, farix, st, true); break;
+      case 2: launch_far_q<2, true>(h, pos4, ub, x, Q, f.nqb, f.S, per_split, far2, farix, st, true); break;
+      default: launch_far_q<4, true>(h, pos4, ub, x, Q, f.nqb, f.S, per_split, far2, farix, st, true); break;
     }
   } else {
-    switch (q) {
-      case 1: launch_far_q<1, false>(h, pos4, ub, x, Q, nqb, S, per_split, far2, nullptr, st); break;
-      case 2: launch_far_q<2, false>(h, pos4, ub, x, Q, nqb, S, per_split, far2, nullptr, st); break;
-      default: launch_far_q<4, false>(h, pos4, ub, x, Q, nqb, S, per_split, far2, nullptr, st); break;
+    switch (f.q) {
+      case 1: launch_far_q<1, false>(h, pos4, ub, x, Q, f.nqb, f.S, per_split, far2, nullptr, st, true); break;
+      case 2: launch_far_q<2, false>(h, pos4, ub, x, Q, f.nqb, f.S, per_split, far2, nullptr, st, true); break;
+      default: launch_far_q<4, false>(h, pos4, ub, x, Q, f.nqb, f.S, per_split, far2, nullptr, st, true); break;
     }
   }
   return check_hip(hipGetLastError(), "farthest-point kernel");
@@ -315,17 +356,49 @@ int launch_blend(const void* rec, int64_t N, const float* x, int64_t Q, float C,
   const float4* recs = reinterpret_cast<const float4*>(base + L.rec);
   const float C2 = C * kLog2e, S2 = shift2_of(C);
   switch (plan.qpl) {
-    case 1: launch_blend_q<1>(h, recs, x, Q, plan, ws.far2, ws.part, C2, S2, st); break;
-    case 2: launch_blend_q<2>(h, recs, x, Q, plan, ws.far2, ws.part, C2, S2, st); break;
-    case 8: launch_blend_q<8>(h, recs, x, Q, plan, ws.far2, ws.part, C2, S2, st); break;
-    default: launch_blend_q<4>(h, recs, x, Q, plan, ws.far2, ws.part, C2, S2, st); break;
+    case 1: launch_blend_q<1>(h, recs, x, Q, plan, ws.far2, 1, ws.part, C2, S2, st); break;
+    case 2: launch_blend_q<2>(h, recs, x, Q, plan, ws.far2, 1, ws.part, C2, S2, st); break;
+    case 8: launch_blend_q<8>(h, recs, x, Q, plan, ws.far2, 1, ws.part, C2, S2, st); break;
+    default: launch_blend_q<4>(h, recs, x, Q, plan, ws.far2, 1, ws.part, C2, S2, st); break;
   }
   return check_hip(hipGetLastError(), "blend kernel");
 }
 
+int launch_eval_plain(const void* rec, int64_t N, const float* x, int64_t Q, float C, const Plan& plan,
+                      const WsView& ws, float* sdf, hipStream_t st, float offset) {
+  const Layout L(N);
+  const char* base = static_cast<const char*>(rec);
+  const Header* h = reinterpret_cast<const Header*>(base);
+  const float4* pos4 = reinterpret_cast<const float4*>(base + L.pos);
+  const float4* ub = reinterpret_cast<const float4*>(base + L.ub);
+  const float4* recs = reinterpret_cast<const float4*>(base + L.rec);
+  const FarShape f = far_shape(plan.qpl, Q, plan.S, plan.per_split);
+  const bool fold = f.S > kLaneSplitsMax;
+  const int rows = fold ? 1 : f.S;
+  switch (f.q) {
+    case 1: launch_far_q<1, false>(h, pos4, ub, x, Q, f.nqb, f.S, plan.per_split, ws.far2, nullptr, st, fold); break;
+    case 2: launch_far_q<2, false>(h, pos4, ub, x, Q, f.nqb, f.S, plan.per_split, ws.far2, nullptr, st, fold); break;
+    default: launch_far_q<4, false>(h, pos4, ub, x, Q, f.nqb, f.S, plan.per_split, ws.far2, nullptr, st, fold); break;
+  }
+  if (int rc = check_hip(hipGetLastError(), "farthest-point kernel")) return rc;
+  const float C2 = C * kLog2e, S2 = shift2_of(C);
+  switch (plan.qpl) {
+    case 1: launch_blend_q<1>(h, recs, x, Q, plan, ws.far2, rows, ws.part, C2, S2, st); break;
+    case 2: launch_blend_q<2>(h, recs, x, Q, plan, ws.far2, rows, ws.part, C2, S2, st); break;
+    case 8: launch_blend_q<8>(h, recs, x, Q, plan, ws.far2, rows, ws.part, C2, S2, st); break;
+    default: launch_blend_q<4>(h, recs, x, Q, plan, ws.far2, rows, ws.part, C2, S2, st); break;
+  }
+  if (int rc = check_hip(hipGetLastError(), "blend kernel")) return rc;
+  return launch_combine(Q, plan, ws, sdf, st, offset);
+}
+
 int launch_combine(int64_t Q, const Plan& plan, const WsView& ws, float* sdf, hipStream_t st, float offset) {
-  hipLaunchKernelGGL(k_combine, dim3(unsigned((Q + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, ws.part, plan.S,
-                     Q, sdf, offset);
+  if (plan.S <= kLaneSplitsMax)
+    hipLaunchKernelGGL(k_combine, dim3(unsigned((Q + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, ws.part, plan.S,
+                       Q, sdf, offset);
+  else
+    hipLaunchKernelGGL(k_combine_wave, dim3(unsigned((Q + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), 0, st,
+                       ws.part, plan.S, Q, sdf, offset);
   return check_hip(hipGetLastError(), "combine kernel");
 }
 

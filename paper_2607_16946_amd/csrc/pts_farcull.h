@@ -157,4 +157,38 @@ __device__ __forceinline__ void far_sweep(const float4* __restrict__ pos4, const
   }
 }
 
+// Splits of at most this many points are swept whole: the bound and marking
+// phases (three rounds of loads and barriers) cost more than the sweep they
+// save.
+constexpr int64_t kFarPlainMax = 1024;
+
+// The same maximum (and first slot attaining it) over every point of
+// [beg, end), without culling.
+template <int QPL, bool kArg>
+__device__ __forceinline__ void far_sweep_plain(const float4* __restrict__ pos4, int64_t beg, int64_t end,
+                                                const float (&qx)[QPL], const float (&qy)[QPL],
+                                                const float (&qz)[QPL], float (&acc)[QPL], int32_t (&ix)[QPL],
+                                                FarLds& L) {
+  for (int64_t t0 = beg; t0 < end; t0 += kTile1) {
+    const int cnt = int(min<int64_t>(kTile1, end - t0));
+    __syncthreads();
+    for (int t = threadIdx.x; t < cnt; t += kBlock) L.tile[t] = pos4[t0 + t];
+    __syncthreads();
+    for (int j = 0; j < cnt; ++j) {
+      const float4 P = L.tile[j];
+#pragma unroll
+      for (int k = 0; k < QPL; ++k) {
+        const float a = fmaf(qz[k], P.z, fmaf(qy[k], P.y, fmaf(qx[k], P.x, P.w)));
+        if (kArg) {
+          const bool gt = a > acc[k];
+          acc[k] = gt ? a : acc[k];
+          ix[k] = gt ? int32_t(t0 + j) : ix[k];
+        } else {
+          acc[k] = fmaxf(acc[k], a);
+        }
+      }
+    }
+  }
+}
+
 }  // namespace pts

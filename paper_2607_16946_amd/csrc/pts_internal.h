@@ -114,10 +114,22 @@ struct Layout {
 struct Plan {
   int qpl;            // queries per lane
   int S;              // point splits
-  int64_t per_split;  // points per split (multiple of kTile2)
+  int64_t per_split;  // points per split (multiple of kUnit)
   int64_t nqb;        // query blocks of kBlock * qpl queries
 };
-Plan make_plan(int64_t N, int64_t Q, const pts_params* prm);
+// max_auto_splits bounds the automatic split count (prm->splits == 0): the
+// plain evaluation (phi only: pts_eval without gradient or statistics, its
+// staged calls, the server's query requests) allows kPlainSplitMax, every
+// other path kAutoSplitMax (their combine kernels sum a query's splits in
+// one lane).
+constexpr int kAutoSplitMax = 64;
+constexpr int kPlainSplitMax = 1024;
+// The plain evaluation's per-query reductions over splits -- the fold of the
+// farthest-point sweep's per-split maxima and the combine of the blend's
+// partials -- run in one lane up to kLaneSplitsMax splits (the blend then
+// reads the unfolded maxima itself), in one wavefront beyond.
+constexpr int kLaneSplitsMax = 16;
+Plan make_plan(int64_t N, int64_t Q, const pts_params* prm, int max_auto_splits = kAutoSplitMax);
 // The same split with a different number of queries per lane.
 inline Plan with_qpl(Plan p, int qpl, int64_t Q) {
   p.qpl = qpl;
@@ -160,6 +172,12 @@ size_t noalloc_scratch_bytes();
 int eval_noalloc(const void* rec, int64_t N, const float* x, int64_t Q, float* sdf, const pts_params& P,
                  const Plan& plan, hipStream_t st);
 
+// Queries in Morton order of the cloud's bbox (3 x 8 bits; pts_bounded.hip):
+// keys into key[0], a stable radix sort, and *order = the sorted query indices
+// (one of idx[0], idx[1]).  key, idx: [2][Q]; rhist: 16 * ceil(Q / kBlock) int32.
+int launch_query_order(const void* rec, const float* x, int64_t Q, uint32_t* key[2], int32_t* idx[2],
+                       int32_t* rhist, hipStream_t st, const int32_t** order);
+
 // Error-bounded evaluation (pts_bounded.hip): the blend with point units
 // skipped while a proven bound on the change of phi stays within eps.
 Plan bounded_plan(int64_t N, int64_t Q);
@@ -177,8 +195,9 @@ int launch_compose(const float* a, const float* b, int64_t n, int op, float c, f
 // Radius-limited evaluation (pts_radius.hip).
 int launch_blocks(void* rec, int64_t N, hipStream_t st);
 int launch_radius_prepare(void* rec, int64_t N, float C, hipStream_t st);
+size_t eval_radius_ws_bytes(int64_t Q);
 int launch_eval_radius(const void* rec, int64_t N, const float* x, int64_t Q, float* sdf, int32_t* count,
-                       hipStream_t st);
+                       void* ws, hipStream_t st);
 // Farthest-point sweep (culled by units): M^2 per query into far2[Q] and, if
 // farix is non-null, the first slot attaining it into farix[Q].  With S > 1
 // and per_split > 0 (an evaluation plan's point split) a call with few query
@@ -190,6 +209,13 @@ int launch_far(const void* rec, int64_t N, const float* x, int64_t Q, const Plan
                hipStream_t st);
 int launch_blend(const void* rec, int64_t N, const float* x, int64_t Q, float C, const Plan& plan,
                  const WsView& ws, hipStream_t st);
+// The whole plain evaluation (phi only): the farthest-point sweep (with few
+// split rows left unfolded for the blend sweep to take their maximum), the
+// blend sweep and the combine.  Bitwise equal to launch_far + launch_blend +
+// launch_combine, one launch fewer when the farthest-point sweep runs split
+// over at most 16 splits.
+int launch_eval_plain(const void* rec, int64_t N, const float* x, int64_t Q, float C, const Plan& plan,
+                      const WsView& ws, float* sdf, hipStream_t st, float offset = 0.f);
 // sdf = num / den - offset (the offset surface phi = offset; 0 leaves phi bitwise unchanged)
 int launch_combine(int64_t Q, const Plan& plan, const WsView& ws, float* sdf, hipStream_t st, float offset = 0.f);
 int launch_far_arg(const void* rec, int64_t N, const float* x, int64_t Q, const Plan& plan, const WsView& ws,

@@ -21,8 +21,10 @@ struct WorkDesc {
   int32_t pad;
 };
 
-// One workgroup of the packed combine: kBlock queries of one request.
+// One workgroup of the packed combine: block qb of one request's queries,
+// kBlock queries each for S <= kLaneSplitsMax, kBlock / 64 beyond.
 struct CombDesc {
+  float* far2;  // the request's per-split maxima, folded here when S > kLaneSplitsMax
   const float2* part;
   float* out;
   int64_t Q;
@@ -30,8 +32,9 @@ struct CombDesc {
   int32_t qb;
 };
 
+// fold: some request of the launch has more than kLaneSplitsMax splits.
 int launch_multi(const WorkDesc* d_work, int64_t n_work, const CombDesc* d_comb, int64_t n_comb, float C,
-                 hipStream_t st);
+                 bool fold, hipStream_t st);
 int multi_qpl();
 
 }  // namespace pts

@@ -3,9 +3,10 @@
 // Each workgroup reads a work descriptor naming its request (cloud record,
 // queries, workspace), its query block and its point split, and then runs the
 // same farthest-point / blend code as the single-request kernels.  A request's
-// split count is a function of its cloud's N only, and a query's sums depend
-// only on the split and tile boundaries, so a request gets bit-identical
-// results whether it is launched alone or packed with others.
+// split count is a function of the request alone (its cloud's N and its query
+// count), and a query's sums depend only on the split and tile boundaries, so
+// a request gets bit-identical results whether it is launched alone or packed
+// with others.
 #include "pts_farcull.h"
 #include "pts_multi.h"
 
@@ -43,12 +44,16 @@ __global__ __launch_bounds__(kBlock) void k_far_multi(const WorkDesc* __restrict
   }
   const int64_t beg = int64_t(d.split) * d.per_split;
   const int64_t end = min(N, beg + d.per_split);
-  const int64_t u_lo = beg / kUnit, u_hi = max(u_lo, (end + kUnit - 1) / kUnit);
-  // 1. lower bound: extreme points of sampled units and of the split's units
-  far_bound_split<kQpl>(ub, U, u_lo, u_hi, qx, qy, qz, lb, L);
-  far_threshold<kQpl>(lb, ok);
-  // 2./3. the split's units that can reach it
-  far_sweep<kQpl, false>(pos4, ub, u_lo, u_hi, end, qx, qy, qz, ok, lb, acc, ix, L);
+  if (d.per_split <= kFarPlainMax) {  // a short split: swept whole, as the bound would cost more
+    far_sweep_plain<kQpl, false>(pos4, beg, end, qx, qy, qz, acc, ix, L);
+  } else {
+    const int64_t u_lo = beg / kUnit, u_hi = max(u_lo, (end + kUnit - 1) / kUnit);
+    // 1. lower bound: extreme points of sampled units and of the split's units
+    far_bound_split<kQpl>(ub, U, u_lo, u_hi, qx, qy, qz, lb, L);
+    far_threshold<kQpl>(lb, ok);
+    // 2./3. the split's units that can reach it
+    far_sweep<kQpl, false>(pos4, ub, u_lo, u_hi, end, qx, qy, qz, ok, lb, acc, ix, L);
+  }
 #pragma unroll
   for (int k = 0; k < kQpl; ++k) {
     const int64_t q = int64_t(d.qb) * (kBlock * kQpl) + k * kBlock + threadIdx.x;
@@ -72,7 +77,7 @@ __global__ __launch_bounds__(kBlock) void k_blend_multi(const WorkDesc* __restri
     qx[k] = qi.x; qy[k] = qi.y; qz[k] = qi.z;
     float M = 0.f;
     nl[k] = 0.f;
-    if (qi.valid) far_of(d.far2, S, Q, q, C2, M, nl[k]);
+    if (qi.valid) far_of(d.far2, S <= kLaneSplitsMax ? S : 1, Q, q, C2, M, nl[k]);
     num[k] = 0.f;
     den[k] = 0.f;
   }
@@ -123,26 +128,43 @@ __global__ __launch_bounds__(kBlock) void k_blend_multi(const WorkDesc* __restri
   }
 }
 
-// One workgroup per (request, block of kBlock queries): fixed-order combine.
+// Between the two sweeps, for requests with more than kLaneSplitsMax splits:
+// their per-split maxima folded into row 0, one wavefront per query, over
+// the combine's descriptors (kBlock / 64 queries each for such requests).
+__global__ __launch_bounds__(kBlock) void k_fold_multi(const CombDesc* __restrict__ descs) {
+  const CombDesc c = descs[blockIdx.x];
+  if (c.S <= kLaneSplitsMax) return;
+  const int64_t q = int64_t(c.qb) * (kBlock / 64) + threadIdx.x / 64;
+  const int lane = int(threadIdx.x & 63);
+  const float m = fold_wave(c.far2, c.S, c.Q, q, lane);
+  if (lane == 0 && q < c.Q) c.far2[q] = m;
+}
+
+// One workgroup per (request, block of queries): the fixed-order combine of
+// pts_device.h, as k_combine / k_combine_wave do it -- kBlock queries one per
+// lane up to kLaneSplitsMax splits, else kBlock / 64 queries one per wave.
 __global__ __launch_bounds__(kBlock) void k_combine_multi(const CombDesc* __restrict__ descs) {
   const CombDesc c = descs[blockIdx.x];
-  const int64_t q = int64_t(c.qb) * kBlock + threadIdx.x;
-  if (q >= c.Q) return;
-  float num = 0.f, den = 0.f;
-  for (int s = 0; s < c.S; ++s) {
-    const float2 v = c.part[int64_t(s) * c.Q + q];
-    num += v.x;
-    den += v.y;
+  if (c.S <= kLaneSplitsMax) {
+    const int64_t q = int64_t(c.qb) * kBlock + threadIdx.x;
+    if (q >= c.Q) return;
+    const float2 v = combine_seq(c.part, c.S, c.Q, q);
+    c.out[q] = v.x / v.y;
+  } else {
+    const int64_t q = int64_t(c.qb) * (kBlock / 64) + threadIdx.x / 64;
+    const int lane = int(threadIdx.x & 63);
+    const float2 v = combine_wave(c.part, c.S, c.Q, q, lane);
+    if (lane == 0 && q < c.Q) c.out[q] = v.x / v.y;
   }
-  c.out[q] = num / den;
 }
 
 }  // namespace
 
 int launch_multi(const WorkDesc* d_work, int64_t n_work, const CombDesc* d_comb, int64_t n_comb, float C,
-                 hipStream_t st) {
+                 bool fold, hipStream_t st) {
   if (n_work > 0) {
     hipLaunchKernelGGL(k_far_multi, dim3(unsigned(n_work)), dim3(kBlock), 0, st, d_work);
+    if (fold && n_comb > 0) hipLaunchKernelGGL(k_fold_multi, dim3(unsigned(n_comb)), dim3(kBlock), 0, st, d_comb);
     hipLaunchKernelGGL(k_blend_multi, dim3(unsigned(n_work)), dim3(kBlock), 0, st, d_work, C * kLog2e,
                        shift2_of(C));
   }

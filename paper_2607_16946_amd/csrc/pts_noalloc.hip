@@ -56,10 +56,7 @@ int eval_noalloc(const void* rec, int64_t N, const float* x, int64_t Q, float* s
                                 std::to_string(kScratchBytes) + " bytes; use pts_eval with a workspace");
   void* ws = nullptr;
   if (int rc = scratch_address(&ws)) return rc;
-  const WsView v = ws_view(plan, Q, ws);
-  if (int rc = launch_far(rec, N, x, Q, plan, v, st)) return rc;
-  if (int rc = launch_blend(rec, N, x, Q, P.C, plan, v, st)) return rc;
-  return launch_combine(Q, plan, v, sdf, st, P.offset);
+  return launch_eval_plain(rec, N, x, Q, P.C, plan, ws_view(plan, Q, ws), sdf, st, P.offset);
 }
 
 }  // namespace pts

@@ -28,10 +28,12 @@
 // A request's region returns to the arena only after the device work that
 // uses it has completed (observed through an event), so reuse never races.
 //
-// Determinism.  A request's point splits (march_splits / normal_plan of the
-// tracer) depend only on its cloud's N, and a query's sums only on the split
-// and the tile boundaries, so results are bitwise the same alone or packed
-// with any other requests, and equal to pts_trace's for trace requests.
+// Determinism.  A query request's point splits are pts_eval's automatic plan
+// for its (N, Q), a trace request's those of the tracer (march_splits /
+// normal_plan: N only), and a query's sums depend only on the split and the
+// tile boundaries, so results are bitwise the same alone or packed with any
+// other requests, and equal to pts_eval's (default parameters) for query
+// requests and to pts_trace's for trace requests.
 //
 // Mock mode.  With cfg.mock the scheduler runs unchanged without a device: a
 // launch "takes" pairs / mock_pairs_per_s seconds and outputs are a pattern,
@@ -170,7 +172,12 @@ int64_t work_descs(int64_t n, int S) {
   const int64_t per = int64_t(kBlock) * multi_qpl();
   return ((n + per - 1) / per) * S;
 }
-int64_t comb_descs(int64_t n) { return (n + kBlock - 1) / kBlock; }
+// Packed combine workgroups: kBlock queries each, or kBlock / 64 once the
+// splits are summed by a wavefront per query (S > kLaneSplitsMax).
+int64_t comb_descs(int64_t n, int S) {
+  const int64_t per = S <= kLaneSplitsMax ? kBlock : kBlock / 64;
+  return (n + per - 1) / per;
+}
 
 enum {
   ST_QUEUED = PTS_STATE_QUEUED,
@@ -375,8 +382,22 @@ class Server {
     q->N = c.N;
     const int64_t n = r->count;
     if (n > 0) {
-      q->plan = march_plan(c.N, n, P_, kServerSplitCap);
-      if (work_descs(n, q->plan.S) > max_work_ || comb_descs(n) > max_comb_) {
+      // query requests: pts_eval's own plan (its results bit for bit), or, if
+      // one launch cannot hold that many workgroups, the largest power-of-two
+      // split <= 64 that fits (pts_eval with pts_params.splits set to it);
+      // trace requests: the march's split, a function of N only
+      if (r->kind == PTS_REQ_EVAL) {
+        q->plan = make_plan(c.N, n, &P_, kPlainSplitMax);
+        for (int cap = kAutoSplitMax; cap >= 1 && (work_descs(n, q->plan.S) > max_work_ ||
+                                                    comb_descs(n, q->plan.S) > max_comb_); cap /= 2) {
+          pts_params F = P_;
+          F.splits = cap;
+          q->plan = make_plan(c.N, n, &F);
+        }
+      } else {
+        q->plan = march_plan(c.N, n, P_, kServerSplitCap);
+      }
+      if (work_descs(n, q->plan.S) > max_work_ || comb_descs(n, q->plan.S) > max_comb_) {
         std::lock_guard<std::mutex> lk(mu_);
         ++rejected_;
         return fail(PTS_EINVAL, "request needs more workgroups than one launch holds; split it");
@@ -930,7 +951,7 @@ class Server {
       for (Req* q : running_) {
         if (q->in_batch >= 0 || q->finalizing || q->n_active <= 0) continue;
         if (int64_t(work.size()) >= cfg_.max_inflight) break;
-        const int64_t w = work_descs(q->n_active, q->plan.S), c = comb_descs(q->n_active);
+        const int64_t w = work_descs(q->n_active, q->plan.S), c = comb_descs(q->n_active, q->plan.S);
         if (nw + w > max_work_ || nc + c > max_comb_) break;  // leads the next launch
         nw += w;
         nc += c;
@@ -942,7 +963,9 @@ class Server {
     const int qpl = multi_qpl();
     double pairs = 0;
     int64_t iw = 0, ic = 0;
+    bool fold = false;
     for (Req* q : work) {
+      fold = fold || q->plan.S > kLaneSplitsMax;
       const int64_t n = q->n_active;
       const Layout L(q->N);
       const bool ev = q->r.kind == PTS_REQ_EVAL;
@@ -975,8 +998,9 @@ class Server {
           d.split = s;
           d.pad = 0;
         }
-      for (int64_t qb = 0; qb < comb_descs(n); ++qb) {
+      for (int64_t qb = 0; qb < comb_descs(n, q->plan.S); ++qb) {
         CombDesc& cd = b.h_comb[ic++];
+        cd.far2 = far2;
         cd.part = part;
         cd.out = out;
         cd.Q = n;
@@ -1005,7 +1029,7 @@ class Server {
       if (!rc)
         rc = check_hip(hipMemcpyAsync(d_comb, b.h_comb, size_t(nc) * sizeof(CombDesc), hipMemcpyHostToDevice, st),
                        "descriptor upload");
-      if (!rc) rc = launch_multi(d_work, nw, d_comb, nc, P_.C, st);
+      if (!rc) rc = launch_multi(d_work, nw, d_comb, nc, P_.C, fold, st);
       for (size_t i = 0; i < work.size() && !rc; ++i) {
         Req* q = work[i];
         const int64_t n = q->r.count;

@@ -229,9 +229,7 @@ int launch_trace(const void* rec, int64_t N, const float* org, const float* dir,
     const Plan plan = march_plan(N, na, P, kTraceSplitCap);
     const WsView wv = ws_view(plan, na, v.eval);
     hipLaunchKernelGGL(k_positions, dim3(nblk(na)), dim3(kBlock), 0, st, act, na, org, dir, t, v.xq);
-    if (int rc = launch_far(rec, N, v.xq, na, plan, wv, st)) return rc;
-    if (int rc = launch_blend(rec, N, v.xq, na, P.C, plan, wv, st)) return rc;
-    if (int rc = launch_combine(na, plan, wv, v.phi, st, P.offset)) return rc;
+    if (int rc = launch_eval_plain(rec, N, v.xq, na, P.C, plan, wv, v.phi, st, P.offset)) return rc;
     hipLaunchKernelGGL(k_advance, dim3(nblk(na)), dim3(kBlock), 0, st, act, na, v.phi, eps, tmax, k, t, hit, nsteps,
                        v.keep);
     int64_t nn = 0;

@@ -299,3 +299,27 @@ def test_blend_weights_three_spheres_hand_derived():
         assert np.abs(g[0] - np.array(case["grad"])).max() <= 1e-4 * max(1.0, np.abs(case["grad"]).max())
         assert abs(st[0, 0] - case["M"]) <= 1e-6 * case["M"]
         assert abs(st[0, 2] - case["phi"]) <= TOL_REL * D
+
+
+@pytest.mark.parametrize("N,Q", [(4096, 4096), (1537, 777), (20000, 300001), (8192, 1 << 20), (3000, 1),
+                                 (65536, 100), (65536, 3000)])
+def test_eval_equals_the_three_stages(N, Q):
+    """pts_eval leaves the farthest-point sweep's per-split maxima unfolded and lets the blend take their
+    maximum; it must equal pts_eval_far + pts_eval_blend + pts_eval_combine bit for bit, whether the
+    farthest-point sweep ran split (few query blocks) or not, and on repeated calls."""
+    cl, _ = synth.mid(N=N, grid=4)
+    x = np.random.default_rng(N + Q).uniform(-1.2, 1.2, size=(Q, 3)).astype(np.float32)
+    prm = binding.make_params()
+    c = binding.Cloud(_dev(cl.p), _dev(cl.n), _dev(cl.a))
+    xd = _dev(x)
+    ws = torch.empty(binding.eval_ws_bytes(N, Q, prm), dtype=torch.uint8, device="cuda")
+    staged = torch.empty(Q, dtype=torch.float32, device="cuda")
+    binding.eval_far(c.rec, N, xd, prm, ws)
+    binding.eval_blend(c.rec, N, xd, prm, ws)
+    binding.eval_combine(N, Q, staged, prm, ws)
+    ws.fill_(0xA5)  # the fused path must not depend on what the workspace held
+    for rep in range(3):
+        fused = binding.eval(c.rec, N, xd, prm, ws=ws)
+        torch.cuda.synchronize()
+        assert torch.equal(fused.view(torch.int32), staged.view(torch.int32)), (N, Q, rep)
+    _say(f"eval N={N} Q={Q}: plan {binding.eval_plan(N, Q, prm)}, bitwise equal to the stages")

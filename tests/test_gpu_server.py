@@ -130,8 +130,12 @@ def test_server_equals_direct_calls_and_oracle():
             c = binding.Cloud(_dev(cl.p), _dev(cl.n), _dev(cl.a), splits=split)
             x = _queries(cl, 3000 + 517 * k, 300 + k)
             got = S.wait(S.submit_eval(cid, x))
-            ref = binding.eval(c.rec, c.N, _dev(x), params=prm).cpu().numpy()
-            assert np.array_equal(got, ref), f"cloud {k}: server != pts_eval(splits={split})"
+            # query requests use pts_eval's own plan (default parameters); traces the cloud's split
+            ref = binding.eval(c.rec, c.N, _dev(x)).cpu().numpy()
+            assert np.array_equal(got, ref), f"cloud {k}: server != pts_eval (plan {binding.eval_plan(c.N, len(x))})"
+            for n_small in (1, 37, 300):  # few queries: many short splits, the wavefront combine beyond 64
+                xs = x[:n_small]
+                assert np.array_equal(S.wait(S.submit_eval(cid, xs)), binding.eval(c.rec, c.N, _dev(xs)).cpu().numpy())
             D = oracle.bbox_diag(cl.p)
             tor = oracle.fit(cl.p, cl.n, cl.a)
             sub = x[:600]

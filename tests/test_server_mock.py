@@ -124,9 +124,10 @@ def test_admission_by_budget_and_fifo():
         for t in (a, b, big, d):
             S.wait(t)
 
-        # a request larger than the budget is refused at once
+        # a request larger than the budget is refused at once (64 q queries fit one launch of this server
+        # only with 2 splits, 40 bytes per query: more than the 2.5 requests of q queries leave room for)
         with pytest.raises(PtsError) as e:
-            S.submit_eval(c, _x(16 * q))
+            S.submit_eval(c, _x(64 * q))
         assert e.value.code == binding.PTS_EBUDGET
         with pytest.raises(PtsError) as e:
             S.add_cloud(*_cloud(1 << 20))
