@@ -1,18 +1,24 @@
 #!/usr/bin/env python3
 """Throughput of the pointwise SDF hot path on one MI355X.
 
-Workload (one "step"): the mid-size plain-method configuration -- a
-131,072-point cloud on the union of 8 random ellipsoids / ring tori with
-sigma = 0.002 position noise and analytic coefficients, queried on the 128^3
-lattice over its bounding box padded by 10% per side.  A step runs the whole
-path through the C ABI: torus fitting (pts_cloud_build), the farthest-point
-sweep, the blend sweep and the split combine (pts_eval_far / _blend /
-_combine).  Inputs are resident in device memory before timing starts.
+Workload (one "step"): the large photogrammetry-like configuration -- a
+2^20-point cloud on the union of 32 random ellipsoids / ring tori with density
+varying 10x across the surface, sigma = 0.005 position noise, 3% outliers
+uniform in the bounding box with random normals, and analytic coefficients,
+queried at 2^20 points uniform in its bounding box padded by 10% per side.  A
+step runs the whole path through the C ABI: torus fitting (pts_cloud_build),
+the farthest-point sweep, the blend sweep and the split combine
+(pts_eval_far / _blend / _combine).  Inputs are resident in device memory
+before timing starts.
 
 Prints one JSON line (rank 0): value = query x point SDF evaluations per
 second (pairs/s), with a `roofline` object for the dominant kernel (the blend
 sweep, timed with HIP events on the stream it runs on) and a `cpu_baseline`
-object (the FP64 oracle on a bounded sample, on this host's cores).
+object (the FP64 oracle on a bounded sample, on this host's cores).  Beside
+it: the same workload's 1024^2 x 64-step sphere trace, the mid workload
+(131,072 points, 128^3 lattice), the radius-limited, error-bounded and
+baseline evaluators, the differentiation workload, serving, and every
+configuration beside the oracle.
 """
 
 from __future__ import annotations
@@ -65,20 +71,22 @@ PUBLISHED_FP32_TFLOPS = 157.3
 BLEND_CYCLES = (BLEND_PLAIN + BLEND_FMA) / ARITH_LANES_PER_CLK + BLEND_TRANS / TRANS_LANES_PER_CLK
 PEAK_PAIRS = CUS * CLOCK_HZ / BLEND_CYCLES                   # 1.97e12 pairs/s
 PEAK_TFLOPS = BLEND_FLOP * PEAK_PAIRS / 1e12                 # 76.7 TFLOP/s
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_blend_mid_traffic.json")
+TRAFFIC_FILES = {w: os.path.join(ROOT, "profiles", f"k_blend_{w}_traffic.json") for w in ("large", "mid")}
 
 
-def measured_traffic():
-    """HBM bytes per k_blend launch from the committed counter summary, if it
-    was taken on the current kernel source (else None)."""
+def measured_traffic(workload: str):
+    """HBM bytes per k_blend launch on a workload from the committed counter
+    summary, if it was taken on the current kernel source (else None)."""
     import hashlib
     try:
-        rec = json.load(open(TRAFFIC_FILE))
-    except (OSError, ValueError):
+        rec = json.load(open(TRAFFIC_FILES[workload]))
+    except (OSError, ValueError, KeyError):
         return None
     src = os.path.join(ROOT, "paper_2607_16946_amd", "csrc", "pts_eval.hip")
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    return rec.get("bytes_per_launch") if rec.get("pts_eval_sha256") == h else None
+    if rec.get("pts_eval_sha256") != h:
+        return None
+    return {"bytes_per_launch": rec.get("bytes_per_launch"), "over_algorithmic": rec.get("over_algorithmic")}
 
 
 def log(*a):
@@ -141,7 +149,7 @@ def cpu_baseline(cl, x, sample: int):
     oracle.eval_sdf(cl.p, tor, x1, nthreads=1)
     t4 = time.perf_counter()
     return {"value": pairs / (t2 - t1), "unit": "pairs/s", "cores": threads, "kind": "oracle",
-            "sample": f"{xs.shape[0]} seeded queries of the {x.shape[0]}-query lattice x all {cl.N} points "
+            "sample": f"{xs.shape[0]} seeded queries of the workload's {x.shape[0]} x all {cl.N} points "
                       f"({pairs:.3g} pairs), FP64, after a {t1 - t0:.2f} s torus fit",
             "seconds": t2 - t1,
             "one_core": {"value": x1.shape[0] * cl.N / (t4 - t3), "queries": x1.shape[0], "seconds": t4 - t3}}
@@ -352,8 +360,9 @@ def radius_bench(name: str, cl, x, reps: int = 3):
     ms_prep = _timed(lambda: binding.radius_prepare(rec, cl.N, prm), reps)
     info = binding.radius_info(rec)
     sdf = torch.empty(x.shape[0], dtype=torch.float32, device="cuda")
-    ms_eval = _timed(lambda: binding.eval_radius(rec, cl.N, xd), reps)
-    _, cnt = binding.eval_radius(rec, cl.N, xd, count=True)
+    ws = torch.empty(max(binding.eval_radius_ws_bytes(cl.N, x.shape[0]), 256), dtype=torch.uint8, device="cuda")
+    ms_eval = _timed(lambda: binding.eval_radius(rec, cl.N, xd, ws=ws), reps)
+    _, cnt = binding.eval_radius(rec, cl.N, xd, count=True, ws=ws)
     cnt = cnt.cpu().numpy()
     out = {"workload": name, "N": cl.N, "Q": int(x.shape[0]), "D": info.D, "lambda": float(info.lam),
            "R_eval": float(info.reval), "prepare_ms": ms_prep, "eval_ms": ms_eval,
@@ -362,51 +371,6 @@ def radius_bench(name: str, cl, x, reps: int = 3):
     log(f"radius ({name}): prepare {ms_prep:.2f} ms, eval {ms_eval:.2f} ms ({out['queries_per_s']:.4g} queries/s), "
         f"{100 * out['frac_within_R_eval']:.1f}% within R_eval, {out['mean_points_blended']:.1f} points blended")
     del sdf
-    return out
-
-
-def large_bench(reps: int, trace: bool):
-    """Large photogrammetry-like cloud: N = 2^20 points on 32 primitives (density
-    varying 10x, sigma 0.005 noise, 3% outliers), 2^20 uniform queries; and,
-    if asked, a 1024^2 sphere trace of 64 steps with normals."""
-    import torch
-    from paper_2607_16946_amd import binding, synth
-    t0 = time.perf_counter()
-    cl, x = synth.large()
-    log(f"large: generated N={cl.N} Q={x.shape[0]} in {time.perf_counter() - t0:.1f} s")
-    N, Q = cl.N, x.shape[0]
-    p, n, a, xd = (torch.from_numpy(v).cuda() for v in (cl.p, cl.n, cl.a, x))
-    prm = binding.make_params()
-    rec = binding.cloud_build(p, n, a, prm)
-    ws = torch.empty(binding.eval_ws_bytes(N, Q, prm), dtype=torch.uint8, device="cuda")
-    sdf = torch.empty(Q, dtype=torch.float32, device="cuda")
-    ms_eval = _timed(lambda: binding.eval(rec, N, xd, prm, ws=ws, out=sdf), reps)
-    ms_build = _timed(lambda: binding.cloud_build(p, n, a, prm, rec), reps)
-    out = {"workload": f"large: {N} points on 32 primitives, density varying 10x, sigma 0.005 noise, "
-                       f"3% outliers; {Q} uniform queries", "N": N, "Q": Q,
-           "eval_ms": ms_eval, "build_ms": ms_build, "pairs_per_s": float(N) * Q / (ms_eval * 1e-3)}
-    log(f"large: eval {ms_eval:.1f} ms ({out['pairs_per_s']:.4g} pairs/s), build {ms_build:.2f} ms")
-    out["radius_limited"] = radius_bench("large", cl, x)
-    if trace:
-        import numpy as np
-        lo, hi = cl.p.min(0), cl.p.max(0)
-        D = float(np.linalg.norm(hi - lo))
-        ctr = 0.5 * (lo + hi)
-        o, d = synth.camera_rays(1024, radius=1.5 * D, fov_deg=45.0, seed=5, target=tuple(ctr))
-        d = d.astype(np.float64)
-        d /= np.linalg.norm(d, axis=1, keepdims=True)
-        od, dd = torch.from_numpy(o.astype(np.float32)).cuda(), torch.from_numpy(d.astype(np.float32)).cuda()
-        R = od.shape[0]
-        binding.trace(rec, N, od[:4096], dd[:4096], steps=4, eps=1e-4 * D, tmax=3.0 * D, params=prm)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        t, hit, ns, nrm = binding.trace(rec, N, od, dd, steps=64, eps=1e-4 * D, tmax=3.0 * D, params=prm)
-        torch.cuda.synchronize()
-        sec = time.perf_counter() - t1
-        steps_sum = float(torch.clamp(ns, max=64).sum())
-        out["trace"] = {"rays": R, "steps": 64, "seconds": sec, "hits": int(hit.sum()),
-                        "ray_steps": steps_sum, "pairs_per_s": steps_sum * N / sec}
-        log(f"large: trace {R} rays in {sec:.2f} s, {int(hit.sum())} hits, {steps_sum:.4g} ray-steps")
     return out
 
 
@@ -513,67 +477,16 @@ def serving_bench(n_requests: int, n_warmup: int, loads, n_clouds: int = 64, bud
     return out
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--grid", type=int, default=128, help="query lattice resolution (default 128)")
-    ap.add_argument("--points", type=int, default=131072)
-    ap.add_argument("--cpu-sample", type=int, default=98304,
-                    help="oracle sample (queries); about 10 s on 16 host threads at the default size")
-    ap.add_argument("--no-diff", action="store_true", help="skip the differentiation workload")
-    ap.add_argument("--no-baselines", action="store_true", help="skip the two baselines of the accuracy comparison")
-    ap.add_argument("--no-radius", action="store_true", help="skip the radius-limited evaluation")
-    ap.add_argument("--no-bounded", action="store_true", help="skip the error-bounded evaluation")
-    ap.add_argument("--no-large", action="store_true", help="skip the large (2^20 x 2^20) workload")
-    ap.add_argument("--large-trace", action="store_true", help="also run the 1024^2 x 64-step trace of it")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-probe", action="store_true")
-    ap.add_argument("--no-serving", action="store_true", help="skip the serving-mode measurement")
-    ap.add_argument("--serving-only", action="store_true", help="only the serving-mode measurement")
-    ap.add_argument("--diff-only", action="store_true", help="only the differentiation workload")
-    ap.add_argument("--bounded-only", action="store_true", help="only the error-bounded evaluation")
-    ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per load level")
-    ap.add_argument("--serve-warmup", type=int, default=50)
-    ap.add_argument("--serve-loads", default="0.5,0.9", help="arrival rates as fractions of capacity")
-    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                    help="only run one plain device copy of MIB MiB (calibrates the HBM byte counters) and exit")
-    args = ap.parse_args()
-    if args.copy_calibration:
-        import torch
-        src = torch.ones(args.copy_calibration * (1 << 20) // 4, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": src.numel() * 4}))
-        return
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU figures are not produced "
-                                   "(queries shard across GPUs with no exchange; see the design notes)"}))
-        sys.exit(2)
-
+def step_bench(cl, x, steps: int, warmup: int, label: str):
+    """One step = the whole hot path through the C ABI on resident inputs: torus
+    fitting (pts_cloud_build), the farthest-point sweep, the blend sweep and the
+    split combine (pts_eval_far / _blend / _combine).  Returns wall ms per step
+    (synchronised on both sides of the timed steps) and each stage's mean time
+    from HIP events recorded on the stream the kernels run on."""
     import numpy as np
     import torch
-    from paper_2607_16946_amd import binding, synth
-
-    torch.cuda.set_device(0)
-    log(f"bench: device {torch.cuda.get_device_name(0)}")
-    loads = [float(v) for v in args.serve_loads.split(",") if v]
-    if args.serving_only:
-        print(json.dumps({"serving": serving_bench(args.serve_requests, args.serve_warmup, loads)}))
-        return
-    if args.diff_only:
-        print(json.dumps({"diff": diff_bench(max(3, args.steps))}))
-        return
-    if args.bounded_only:
-        cl, x = synth.mid(N=args.points, grid=args.grid)
-        print(json.dumps({"bounded": bounded_bench(cl, x)}))
-        return
-    cl, x = synth.mid(N=args.points, grid=args.grid)
+    from paper_2607_16946_amd import binding
     N, Q = cl.N, x.shape[0]
-    log(f"bench: workload N={N} Q={Q} pairs/step={N * Q:.4g}")
     p, n, a = (torch.from_numpy(v).cuda() for v in (cl.p, cl.n, cl.a))
     xd = torch.from_numpy(x).cuda()
     prm = binding.make_params()
@@ -598,24 +511,153 @@ def main():
         if ev is not None:
             ev[4].record(stream)
 
-    for i in range(args.warmup):
+    for i in range(warmup):
         step()
-        log(f"bench: warmup step {i + 1}/{args.warmup} done")
+        log(f"bench: {label}: warmup step {i + 1}/{warmup} done")
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         step(evs[i])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / args.steps
+    ms_step = (t1 - t0) * 1e3 / steps
     stage = {k: float(np.mean([e[j].elapsed_time(e[j + 1]) for e in evs]))
              for j, k in enumerate(("build", "far", "blend", "combine"))}
-    log(f"bench: {args.steps} steps, {ms_step:.3f} ms/step; stages (ms) {stage}")
+    log(f"bench: {label}: {steps} steps, {ms_step:.3f} ms/step; stages (ms) {stage}")
+    del rec, ws, sdf, xd, p, n, a
+    torch.cuda.empty_cache()
+    return ms_step, stage
+
+
+def roofline_of(stage, pairs: float, traffic_key: str):
+    """Roofline object of the blend sweep (the dominant kernel) from its event-timed launch."""
+    achieved_tflops = BLEND_FLOP * pairs / (stage["blend"] * 1e-3) / 1e12
+    traffic = measured_traffic(traffic_key)
+    return {
+        "bound": "alu", "unit": "TFLOP/s", "kernel": "k_blend (blend sweep)",
+        "achieved": achieved_tflops, "peak": PEAK_TFLOPS, "frac": achieved_tflops / PEAK_TFLOPS,
+        "traffic": traffic["bytes_per_launch"] if traffic else None,
+        "traffic_over_algorithmic": traffic["over_algorithmic"] if traffic else None,
+        "flop_per_pair": BLEND_FLOP, "pairs_per_launch": pairs, "launch_ms": stage["blend"],
+        "peak_basis": f"issue-slot ceiling of the blend's instruction mix: {CUS} CU x {CLOCK_HZ / 1e9} GHz / "
+                      f"({BLEND_PLAIN + BLEND_FMA} add/mul/FMA at {ARITH_LANES_PER_CLK} lanes/clk + {BLEND_TRANS} "
+                      f"sqrt/exp2 at {TRANS_LANES_PER_CLK} lanes/clk per pair) = {PEAK_PAIRS:.3e} pairs/s x "
+                      f"{BLEND_FLOP} FLOP",
+        "published_fp32_peak": PUBLISHED_FP32_TFLOPS,
+        "frac_of_published_fp32": achieved_tflops / PUBLISHED_FP32_TFLOPS,
+        "far_sweep": {"ms": stage["far"], "flop_per_pair": FAR_FLOP,
+                      "tflops": FAR_FLOP * pairs / (stage["far"] * 1e-3) / 1e12},
+    }
+
+
+def trace_bench(cl, res: int = 1024, steps: int = 64):
+    """The large workload's sphere trace: a res x res pinhole camera at 1.5 D from
+    the bbox centre (45 degree field of view), `steps` evaluations per ray,
+    eps = 1e-4 D, tmax = 3 D, normals at the hits (pts_trace)."""
+    import numpy as np
+    import torch
+    from paper_2607_16946_amd import binding, synth
+    N = cl.N
+    p, n, a = (torch.from_numpy(v).cuda() for v in (cl.p, cl.n, cl.a))
+    prm = binding.make_params()
+    rec = binding.cloud_build(p, n, a, prm)
+    lo, hi = cl.p.min(0), cl.p.max(0)
+    D = float(np.linalg.norm(hi.astype(np.float64) - lo))
+    ctr = 0.5 * (lo + hi)
+    o, d = synth.camera_rays(res, radius=1.5 * D, fov_deg=45.0, seed=5, target=tuple(ctr))
+    d = d.astype(np.float64)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    od, dd = torch.from_numpy(o.astype(np.float32)).cuda(), torch.from_numpy(d.astype(np.float32)).cuda()
+    R = od.shape[0]
+    binding.trace(rec, N, od[:4096], dd[:4096], steps=4, eps=1e-4 * D, tmax=3.0 * D, params=prm)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    t, hit, ns, nrm = binding.trace(rec, N, od, dd, steps=steps, eps=1e-4 * D, tmax=3.0 * D, params=prm)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t1
+    steps_sum = float(torch.clamp(ns, max=steps).sum())
+    out = {"rays": R, "steps": steps, "seconds": sec, "hits": int(hit.sum()), "ray_steps": steps_sum,
+           "pairs_per_s": steps_sum * N / sec,
+           "workload": f"{res}x{res} camera at 1.5 D, 45 deg, {steps} steps, eps 1e-4 D, tmax 3 D, normals"}
+    log(f"trace: {R} rays x {steps} steps in {sec:.2f} s, {out['hits']} hits, {steps_sum:.4g} ray-steps, "
+        f"{out['pairs_per_s']:.4g} pairs/s")
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-sample", type=int, default=8192,
+                    help="oracle sample (queries of the large workload); about 7 s on 16 host threads")
+    ap.add_argument("--no-mid", action="store_true", help="skip the mid workload's step")
+    ap.add_argument("--no-trace", action="store_true", help="skip the large workload's 1024^2 x 64-step trace")
+    ap.add_argument("--no-diff", action="store_true", help="skip the differentiation workload")
+    ap.add_argument("--no-baselines", action="store_true", help="skip the two baselines of the accuracy comparison")
+    ap.add_argument("--no-radius", action="store_true", help="skip the radius-limited evaluation")
+    ap.add_argument("--no-bounded", action="store_true", help="skip the error-bounded evaluation")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the per-configuration GPU-vs-oracle table")
+    ap.add_argument("--no-probe", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-mode measurement")
+    ap.add_argument("--serving-only", action="store_true", help="only the serving-mode measurement")
+    ap.add_argument("--diff-only", action="store_true", help="only the differentiation workload")
+    ap.add_argument("--bounded-only", action="store_true", help="only the error-bounded evaluation")
+    ap.add_argument("--step-only", choices=("large", "mid"), help="only the timed steps of one workload")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per load level")
+    ap.add_argument("--serve-warmup", type=int, default=50)
+    ap.add_argument("--serve-loads", default="0.5,0.9", help="arrival rates as fractions of capacity")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run one plain device copy of MIB MiB (calibrates the HBM byte counters) and exit")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(args.copy_calibration * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 4}))
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU figures are not produced "
+                                   "(queries shard across GPUs with no exchange; see the design notes)"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2607_16946_amd import synth
+
+    torch.cuda.set_device(0)
+    log(f"bench: device {torch.cuda.get_device_name(0)}")
+    loads = [float(v) for v in args.serve_loads.split(",") if v]
+    if args.serving_only:
+        print(json.dumps({"serving": serving_bench(args.serve_requests, args.serve_warmup, loads)}))
+        return
+    if args.diff_only:
+        print(json.dumps({"diff": diff_bench(max(3, args.steps))}))
+        return
+    if args.bounded_only:
+        cl, x = synth.mid()
+        print(json.dumps({"bounded": bounded_bench(cl, x)}))
+        return
+    if args.step_only:
+        cl, x = synth.large() if args.step_only == "large" else synth.mid()
+        ms, stage = step_bench(cl, x, args.steps, args.warmup, args.step_only)
+        print(json.dumps({"workload": args.step_only, "ms_per_step": ms, "stages_ms": stage,
+                          "pairs_per_s": float(cl.N) * x.shape[0] / (ms * 1e-3)}))
+        return
+
+    t0 = time.perf_counter()
+    cl, x = synth.large()
+    N, Q = cl.N, x.shape[0]
+    log(f"bench: large workload N={N} Q={Q} pairs/step={N * Q:.4g} (generated in {time.perf_counter() - t0:.1f} s)")
+    ms_step, stage = step_bench(cl, x, args.steps, args.warmup, "large")
     pairs = float(N) * Q
     value = pairs / (ms_step * 1e-3)
-
+    roofline = roofline_of(stage, pairs, "large")
     probe = None
     if not args.no_probe:
         try:
@@ -624,48 +666,49 @@ def main():
                 log(f"bench: probe {k:16s} {v:.4g} lane-instr/s  clock {probe['shader_clock_hz'].get(k, 0):.4g}")
         except Exception as e:
             log(f"bench: probe failed: {e}")
-    achieved_tflops = BLEND_FLOP * pairs / (stage["blend"] * 1e-3) / 1e12
-    roofline = {
-        "bound": "alu", "unit": "TFLOP/s", "kernel": "k_blend (blend sweep)",
-        "achieved": achieved_tflops, "peak": PEAK_TFLOPS, "frac": achieved_tflops / PEAK_TFLOPS,
-        "traffic": measured_traffic(),
-        "flop_per_pair": BLEND_FLOP, "pairs_per_launch": pairs, "launch_ms": stage["blend"],
-        "peak_basis": f"{CUS} CU x {CLOCK_HZ / 1e9} GHz / ({BLEND_PLAIN + BLEND_FMA} add/mul/FMA at "
-                      f"{ARITH_LANES_PER_CLK} lanes/clk + {BLEND_TRANS} sqrt/exp2 at {TRANS_LANES_PER_CLK} lanes/clk "
-                      f"per pair) = {PEAK_PAIRS:.3e} pairs/s x {BLEND_FLOP} FLOP",
-        "frac_of_published_fp32": achieved_tflops / PUBLISHED_FP32_TFLOPS,
-        "far_sweep": {"ms": stage["far"], "flop_per_pair": FAR_FLOP,
-                      "tflops": FAR_FLOP * pairs / (stage["far"] * 1e-3) / 1e12},
-    }
     if probe:
         roofline["probe"] = probe
     out = {
         "metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"mid: {N} points on 8 random ellipsoids/ring tori, sigma 0.002 noise; "
-                               f"{args.grid}^3 lattice over the bbox padded 10%", "N": N, "Q": Q,
+        "config": {"workload": f"large photogrammetry-like: {N} points on 32 random ellipsoids/ring tori, density "
+                               f"varying 10x, sigma 0.005 noise, 3% outliers with random normals; {Q} queries "
+                               f"uniform in the bbox padded 10%", "N": N, "Q": Q,
                    "C": 64.0, "parallelism": "single GPU"},
         "stages_ms": stage,
         "roofline": roofline,
     }
+    if not args.no_trace:
+        out["trace"] = trace_bench(cl)
     if not args.no_radius:
-        out["radius_limited"] = radius_bench("mid", cl, x)
-    if not args.no_baselines:
-        out["baselines"] = baseline_bench(cl, x)
-    if not args.no_bounded:
-        out["bounded"] = bounded_bench(cl, x)
-    if not args.no_diff:
-        out["diff"] = diff_bench(5)
-    if not args.no_large:
-        out["large"] = large_bench(3, args.large_trace)
-    if not args.no_serving:
-        out["serving"] = serving_bench(args.serve_requests, args.serve_warmup, loads)
+        out["radius_limited_large"] = radius_bench("large", cl, x)
     if not args.no_cpu_baseline:
         log("bench: timing the FP64 oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(cl, x, args.cpu_sample)
         log(f"bench: oracle {out['cpu_baseline']['value']:.3g} pairs/s on {out['cpu_baseline']['cores']} threads")
-        out["configs"] = configs_bench(out["cpu_baseline"]["cores"])
+    del cl, x
+    mid_cl, mid_x = synth.mid()
+    if not args.no_mid:
+        ms_mid, st_mid = step_bench(mid_cl, mid_x, 5, 1, "mid")
+        pm = float(mid_cl.N) * mid_x.shape[0]
+        out["mid"] = {"workload": f"mid: {mid_cl.N} points on 8 random ellipsoids/ring tori, sigma 0.002 noise; "
+                                  f"128^3 lattice over the bbox padded 10%", "N": mid_cl.N, "Q": int(mid_x.shape[0]),
+                      "ms_per_step": ms_mid, "pairs_per_s": pm / (ms_mid * 1e-3), "stages_ms": st_mid,
+                      "roofline": roofline_of(st_mid, pm, "mid")}
+    if not args.no_radius:
+        out["radius_limited_mid"] = radius_bench("mid", mid_cl, mid_x)
+    if not args.no_baselines:
+        out["baselines"] = baseline_bench(mid_cl, mid_x)
+    if not args.no_bounded:
+        out["bounded"] = bounded_bench(mid_cl, mid_x)
+    del mid_cl, mid_x
+    if not args.no_diff:
+        out["diff"] = diff_bench(5)
+    if not args.no_serving:
+        out["serving"] = serving_bench(args.serve_requests, args.serve_warmup, loads)
+    if not args.no_configs:
+        out["configs"] = configs_bench(min(16, os.cpu_count() or 1))
     print(json.dumps(out))
 
 
