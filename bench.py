@@ -42,12 +42,26 @@ sys.path.insert(0, ROOT)
 # of 1.7 of wall time and p50 latency 3.5 instead of 2.0 ms at 90% load); with
 # 8 it does not.  Must be set before HIP initialises; raised to 8 unless the
 # environment already allows more.
-try:
-    _hwq = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
-except ValueError:
-    _hwq = 4
-if _hwq < 8:
-    os.environ["GPU_MAX_HW_QUEUES"] = "8"
+# `--hw-queues K` sets it to K instead (the serving leg at HIP's default of 4
+# runs in a child process started that way).
+def _hw_queues_arg():
+    for i, a in enumerate(sys.argv):
+        if a == "--hw-queues" and i + 1 < len(sys.argv):
+            return sys.argv[i + 1]
+        if a.startswith("--hw-queues="):
+            return a.split("=", 1)[1]
+    return None
+
+
+if _hw_queues_arg() is not None:
+    os.environ["GPU_MAX_HW_QUEUES"] = str(int(_hw_queues_arg()))
+else:
+    try:
+        _hwq = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
+    except ValueError:
+        _hwq = 4
+    if _hwq < 8:
+        os.environ["GPU_MAX_HW_QUEUES"] = "8"
 
 METRIC = "query×point SDF evals/sec (FP32, % of VALU peak); p50/p99 latency in serving mode"
 
@@ -375,7 +389,7 @@ def radius_bench(name: str, cl, x, reps: int = 3):
 
 
 def serving_bench(n_requests: int, n_warmup: int, loads, n_clouds: int = 64, budget_gib: int = 64,
-                  mock: bool = False):
+                  mock: bool = False, quantum: float = 0.0):
     """Serving workload: resident clouds, Poisson arrivals of query / trace requests.
 
     64 clouds, cloud j from the sphere generator with N log-uniform in
@@ -391,7 +405,9 @@ def serving_bench(n_requests: int, n_warmup: int, loads, n_clouds: int = 64, bud
 
     t_setup = time.perf_counter()
     clouds = [synth.serving_cloud(j) for j in range(n_clouds)]
-    S = Server(budget_bytes=budget_gib << 30, max_inflight=64, mock=mock, mock_pairs_per_s=1e12)
+    S = Server(budget_bytes=budget_gib << 30, max_inflight=64, mock=mock, mock_pairs_per_s=1e12,
+               quantum_pairs=quantum)
+    quantum = quantum if quantum > 0 else 4e9  # 0: the server's default quantum_pairs
     ids = [S.add_cloud(c.p, c.n, c.a) for c in clouds]
     Ns = np.array([c.N for c in clouds], dtype=np.float64)
     diag = [float(np.linalg.norm(c.p.max(0) - c.p.min(0))) for c in clouds]
@@ -449,7 +465,7 @@ def serving_bench(n_requests: int, n_warmup: int, loads, n_clouds: int = 64, bud
     out = {"workload": f"{n_clouds} resident clouds (sphere generator, N log-uniform 1024..262144); 90% query "
                        f"requests Q log-uniform 1..65536, 10% 256x256 sphere traces of 48 steps with normals",
            "budget_gib": budget_gib, "clouds": n_clouds, "points_resident": int(Ns.sum()),
-           "gpu_max_hw_queues": os.environ.get("GPU_MAX_HW_QUEUES"),
+           "gpu_max_hw_queues": os.environ.get("GPU_MAX_HW_QUEUES"), "quantum_pairs": quantum,
            "capacity_req_s": cap, "capacity_pairs_s": st["pairs"] / wall, "capacity_requests": len(burst),
            "capacity_launches": st["launches"], "capacity_busy_frac": st["busy_s"] / wall, "loads": []}
     log(f"serving: capacity {cap:.1f} req/s, {st['pairs'] / wall:.3g} pairs/s over {len(burst)} requests "
@@ -586,6 +602,23 @@ def trace_bench(cl, res: int = 1024, steps: int = 64):
     return out
 
 
+def serving_child(hw_queues: int, n_requests: int, n_warmup: int, loads: str, quantum: float = 0.0):
+    """The serving leg in a child process started with GPU_MAX_HW_QUEUES = hw_queues
+    (it must be set before HIP initialises, so not in this process)."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--serving-only", "--hw-queues", str(hw_queues),
+           "--serve-requests", str(n_requests), "--serve-warmup", str(n_warmup), "--serve-loads", loads,
+           "--serve-quantum", str(quantum)]
+    log(f"serving: child process with GPU_MAX_HW_QUEUES={hw_queues} ...")
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+    for line in r.stderr.splitlines():
+        if line.startswith("serving:"):
+            log(f"[{hw_queues} queues] {line}")
+    if r.returncode != 0:
+        return {"error": f"child exited with {r.returncode}", "stderr_tail": r.stderr[-2000:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])["serving"]
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -610,6 +643,12 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per load level")
     ap.add_argument("--serve-warmup", type=int, default=50)
     ap.add_argument("--serve-loads", default="0.5,0.9", help="arrival rates as fractions of capacity")
+    ap.add_argument("--serve-quantum", type=float, default=0.0,
+                    help="pairs per packed launch of the server (0 = its default, 4e9)")
+    ap.add_argument("--hw-queues", type=int, default=None,
+                    help="GPU_MAX_HW_QUEUES for this process (default: raised to 8)")
+    ap.add_argument("--no-serving-default-queues", action="store_true",
+                    help="skip the serving leg at HIP's default of 4 hardware queues (a child process)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run one plain device copy of MIB MiB (calibrates the HBM byte counters) and exit")
     args = ap.parse_args()
@@ -634,7 +673,8 @@ def main():
     log(f"bench: device {torch.cuda.get_device_name(0)}")
     loads = [float(v) for v in args.serve_loads.split(",") if v]
     if args.serving_only:
-        print(json.dumps({"serving": serving_bench(args.serve_requests, args.serve_warmup, loads)}))
+        print(json.dumps({"serving": serving_bench(args.serve_requests, args.serve_warmup, loads,
+                                                   quantum=args.serve_quantum)}))
         return
     if args.diff_only:
         print(json.dumps({"diff": diff_bench(max(3, args.steps))}))
@@ -706,7 +746,10 @@ def main():
     if not args.no_diff:
         out["diff"] = diff_bench(5)
     if not args.no_serving:
-        out["serving"] = serving_bench(args.serve_requests, args.serve_warmup, loads)
+        out["serving"] = serving_bench(args.serve_requests, args.serve_warmup, loads, quantum=args.serve_quantum)
+        if not args.no_serving_default_queues:
+            out["serving_4_hw_queues"] = serving_child(4, args.serve_requests, args.serve_warmup, args.serve_loads,
+                                                       args.serve_quantum)
     if not args.no_configs:
         out["configs"] = configs_bench(min(16, os.cpu_count() or 1))
     print(json.dumps(out))

@@ -456,13 +456,15 @@ int pts_eval_radius(const void* rec, int64_t N, const float* x, int64_t Q, float
  * requests (phi at queries, or a sphere trace) from client threads.  A
  * scheduler thread admits queued requests in arrival order while fewer than
  * max_inflight are running and their device buffers fit the memory budget,
- * packs every runnable piece of work (whole query requests and the next step
- * of every trace request) into one launch of the evaluation kernels, and keeps
- * up to two such launches in flight on two streams, so requests that arrive
- * while the device is busy are admitted and start as soon as memory and a
- * launch slot free up.  Trace requests advance one step per launch and are
- * repacked until every ray has stopped; then normals are computed at the hit
- * rays.  The two launches overlap on the device only if HIP maps the two
+ * packs runnable work (query requests and the next step of every trace
+ * request) into one launch of the evaluation kernels, and keeps up to two
+ * such launches in flight on two streams, so requests that arrive while the
+ * device is busy are admitted and start as soon as memory and a launch slot
+ * free up.  A launch takes at most quantum_pairs of work, so a long request
+ * (a trace step of many rays, many queries on a large cloud) runs as several
+ * launches and a request behind it waits about one quantum.  Trace requests
+ * advance one step at a time and are repacked until every ray has stopped;
+ * then normals are computed at the hit rays.  The two launches overlap on the device only if HIP maps the two
  * streams to different hardware queues; with HIP's default of 4 queues per
  * process that depends on how many streams the process created earlier, so
  * a process that runs a server beside other GPU work should start with
@@ -507,6 +509,13 @@ typedef struct pts_server_cfg {
   int mock_fail_count;      /* mock only: query requests of exactly this count
                                fail with PTS_EHIP (0 = never) */
   double mock_pairs_per_s;  /* mock only; 0 = 1e12 */
+  double quantum_pairs;     /* query x point pairs one packed launch takes on
+                               (about that many / 1.1e12 seconds of device
+                               time); 0 = 4e9.  A request with more work is
+                               spread over several launches in chunks of
+                               512-query blocks (results do not depend on
+                               it), so a request that arrives behind it waits
+                               about one quantum for a launch slot. */
 } pts_server_cfg;
 
 #define PTS_REQ_EVAL 0
@@ -584,7 +593,8 @@ int pts_server_wait(pts_server* srv, uint64_t ticket, int timeout_ms);
 int pts_server_cancel(pts_server* srv, uint64_t ticket);
 
 /* Forget a finished request (its ticket becomes unknown). PTS_EBUSY if it
- * has not finished. */
+ * has not finished or another thread is still inside pts_server_wait on it
+ * (release it once that wait has returned). */
 int pts_server_release(pts_server* srv, uint64_t ticket);
 
 /* Counters and latency percentiles since creation or the last reset. */

@@ -52,7 +52,8 @@ class RadiusInfo(ctypes.Structure):
 class ServerCfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_inflight", ctypes.c_int), ("max_queue", ctypes.c_int),
                 ("max_batch_work", ctypes.c_int64), ("C", ctypes.c_float), ("kfloor_rel", ctypes.c_float),
-                ("mock", ctypes.c_int), ("mock_fail_count", ctypes.c_int), ("mock_pairs_per_s", ctypes.c_double)]
+                ("mock", ctypes.c_int), ("mock_fail_count", ctypes.c_int), ("mock_pairs_per_s", ctypes.c_double),
+                ("quantum_pairs", ctypes.c_double)]
 
 
 class Request(ctypes.Structure):

@@ -63,6 +63,7 @@ using Clock = std::chrono::steady_clock;
 double now_s() { return std::chrono::duration<double>(Clock::now().time_since_epoch()).count(); }
 
 constexpr int kSlots = 2;  // launches in flight at once
+constexpr double kDefaultQuantum = 4e9;  // query x point pairs per packed launch (~4 ms of device time)
 
 // First-fit allocator over byte offsets [0, size) with coalescing.
 class Arena {
@@ -168,17 +169,6 @@ ReqLayout req_layout(int kind, int64_t n, const Plan& plan, const pts_params& P,
 // Pinned staging bytes: inputs, then outputs.
 size_t stage_bytes_of(int kind, int64_t n) { return size_t(n) * (kind == PTS_REQ_EVAL ? 16 : 48); }
 
-int64_t work_descs(int64_t n, int S) {
-  const int64_t per = int64_t(kBlock) * multi_qpl();
-  return ((n + per - 1) / per) * S;
-}
-// Packed combine workgroups: kBlock queries each, or kBlock / 64 once the
-// splits are summed by a wavefront per query (S > kLaneSplitsMax).
-int64_t comb_descs(int64_t n, int S) {
-  const int64_t per = S <= kLaneSplitsMax ? kBlock : kBlock / 64;
-  return (n + per - 1) / per;
-}
-
 enum {
   ST_QUEUED = PTS_STATE_QUEUED,
   ST_RUNNING = PTS_STATE_RUNNING,
@@ -189,6 +179,7 @@ enum {
 
 struct Req {
   uint64_t ticket = 0;
+  int waiters = 0;  // threads inside pts_server_wait on this request (release refuses meanwhile)
   pts_request r{};
   int state = ST_QUEUED;
   int status = PTS_OK;
@@ -205,6 +196,7 @@ struct Req {
   // device progress (scheduler thread only)
   int in_batch = -1;
   int64_t n_active = 0;
+  int64_t next_blk = 0;   // first work block of the current evaluation / trace step not yet launched
   int step = 0;
   bool finalizing = false;
   bool fin_hits = false;  // normals asked for: the hit count is on its way to the host
@@ -218,10 +210,13 @@ struct Req {
 
 struct Batch {
   bool active = false;
+  bool whole = false;  // one long request run whole, beyond the quantum
   int rc = PTS_OK;
   hipStream_t stream = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::vector<Req*> reqs;
+  std::vector<int64_t> blk0, blk1;  // each request's chunk of work blocks in this launch
+  std::vector<char> last;           // the chunk ends the request's evaluation / trace step
   WorkDesc* h_work = nullptr;
   CombDesc* h_comb = nullptr;
   int32_t* h_counts = nullptr;
@@ -253,6 +248,7 @@ class Server {
     P_.offset = 0.0f;
     max_work_ = cfg_.max_batch_work;
     max_comb_ = cfg_.max_batch_work;
+    quantum_ = cfg_.quantum_pairs > 0 ? cfg_.quantum_pairs : kDefaultQuantum;
     if (!cfg_.mock) {
       if (int rc = check_hip(hipGetDevice(&dev_), "server device")) return rc;
       if (hipMalloc(&base_, cfg_.hbm_budget_bytes) != hipSuccess) {
@@ -383,13 +379,17 @@ class Server {
     const int64_t n = r->count;
     if (n > 0) {
       // query requests: pts_eval's own plan (its results bit for bit), or, if
-      // one launch cannot hold that many workgroups, the largest power-of-two
-      // split <= 64 that fits (pts_eval with pts_params.splits set to it);
-      // trace requests: the march's split, a function of N only
+      // one launch cannot hold the workgroups of one block of queries, the
+      // largest power-of-two split <= 64 that fits (pts_eval with
+      // pts_params.splits set to it); trace requests: the march's split, a
+      // function of N only.  Launches take a request in chunks of blocks.
+      const int64_t bq = int64_t(kBlock) * multi_qpl();
+      auto fits = [&](const Plan& pl) {
+        return pl.S <= max_work_ && (bq + comb_per(pl.S) - 1) / comb_per(pl.S) <= max_comb_;
+      };
       if (r->kind == PTS_REQ_EVAL) {
         q->plan = make_plan(c.N, n, &P_, kPlainSplitMax);
-        for (int cap = kAutoSplitMax; cap >= 1 && (work_descs(n, q->plan.S) > max_work_ ||
-                                                    comb_descs(n, q->plan.S) > max_comb_); cap /= 2) {
+        for (int cap = kAutoSplitMax; cap >= 1 && !fits(q->plan); cap /= 2) {
           pts_params F = P_;
           F.splits = cap;
           q->plan = make_plan(c.N, n, &F);
@@ -397,10 +397,10 @@ class Server {
       } else {
         q->plan = march_plan(c.N, n, P_, kServerSplitCap);
       }
-      if (work_descs(n, q->plan.S) > max_work_ || comb_descs(n, q->plan.S) > max_comb_) {
+      if (!fits(q->plan)) {
         std::lock_guard<std::mutex> lk(mu_);
         ++rejected_;
-        return fail(PTS_EINVAL, "request needs more workgroups than one launch holds; split it");
+        return fail(PTS_EINVAL, "one block of the request needs more workgroups than a launch holds");
       }
       q->lay = req_layout(r->kind, n, q->plan, P_, c.N);
     }
@@ -457,9 +457,11 @@ class Server {
     Req* q = it->second.get();
     auto done = [q] { return q->state >= ST_DONE; };
     ++waiters_;  // shutdown waits for waiters to leave before the server is freed
+    ++q->waiters;  // and release() for this request's waiters, so q stays valid
     bool ok = true;
     if (timeout_ms < 0) cv_done_.wait(lk, done);
     else ok = cv_done_.wait_for(lk, std::chrono::milliseconds(timeout_ms), done);
+    --q->waiters;
     --waiters_;
     cv_done_.notify_all();
     if (!ok) return fail(PTS_ETIMEOUT, "request still queued or running");
@@ -488,6 +490,7 @@ class Server {
     auto it = reqs_.find(t);
     if (it == reqs_.end()) return fail(PTS_ENOTFOUND, "unknown ticket");
     if (it->second->state < ST_DONE) return fail(PTS_EBUSY, "request has not finished");
+    if (it->second->waiters > 0) return fail(PTS_EBUSY, "another thread is waiting on the request");
     reqs_.erase(it);
     return PTS_OK;
   }
@@ -665,6 +668,7 @@ class Server {
       q->admitted = true;
       q->state = ST_RUNNING;
       q->n_active = q->r.count;
+      q->next_blk = 0;
       q->step = 0;
       running_.push_back(q);
       fresh_.push_back(q);
@@ -763,6 +767,7 @@ class Server {
       for (size_t i = 0; i < b.reqs.size(); ++i) {
         Req* q = b.reqs[i];
         q->in_batch = -1;
+        q->next_blk = b.last[i] ? 0 : b.blk1[i];
         const int64_t n = q->r.count;
         const bool mock_fail =
             cfg_.mock && q->r.kind == PTS_REQ_EVAL && cfg_.mock_fail_count > 0 && n == cfg_.mock_fail_count;
@@ -772,6 +777,8 @@ class Server {
         } else if (b.rc != PTS_OK || mock_fail) {
           finish_locked(q, ST_FAILED, mock_fail ? PTS_EHIP : b.rc, mock_fail ? "mock failure" : "launch failed");
           free_req_locked(q);
+        } else if (!b.last[i]) {
+          // more chunks of this evaluation / step to launch
         } else if (q->r.kind == PTS_REQ_EVAL) {
           if (cfg_.mock) {
             for (int64_t j = 0; j < n; ++j) q->r.out_sdf[j] = float(q->r.cloud) + 1e-3f * float(j % 1000);
@@ -791,6 +798,10 @@ class Server {
         }
       }
       b.reqs.clear();
+      b.whole = false;
+      b.blk0.clear();
+      b.blk1.clear();
+      b.last.clear();
       b.active = false;
       b.rc = PTS_OK;
     }
@@ -924,8 +935,17 @@ class Server {
     return any;
   }
 
-  // Pack every runnable request (in admission order, while the descriptors
-  // fit) into one launch on an idle slot.
+  // Queries per packed-combine workgroup, and the combine workgroups of work
+  // blocks [k0, k1) of a request's current evaluation / step.
+  static int64_t comb_per(int S) { return S <= kLaneSplitsMax ? kBlock : kBlock / 64; }
+  static int64_t chunk_comb_descs(const Req* q, int64_t k0, int64_t k1) {
+    const int64_t bq = int64_t(kBlock) * multi_qpl();
+    const int64_t q0 = k0 * bq, q1 = std::min(q->n_active, k1 * bq);
+    return (q1 - q0 + comb_per(q->plan.S) - 1) / comb_per(q->plan.S);
+  }
+
+  // Pack runnable requests (in admission order, chunks of at most a quantum
+  // of work in all) into one launch on an idle slot.
   bool launch_batch() {
     int slot = -1;
     for (int bi = 0; bi < kSlots; ++bi)
@@ -948,14 +968,74 @@ class Server {
           ++i;
         }
       }
+      // Each request contributes a chunk of its work blocks (kBlock * qpl
+      // queries each, from next_blk on): first one block for every runnable
+      // request (admission order), then the rest of a quantum of pairs to
+      // them in the same order.  A long request is thus spread over several
+      // launches, and a request that arrives meanwhile joins the next launch
+      // on either slot, waiting about one quantum.  One exception keeps long
+      // requests fast when the device is not contended: if the first
+      // runnable request alone exceeds the quantum and the other slot does
+      // not hold such a launch, it runs whole, alone -- so at most one launch
+      // in flight exceeds the quantum, and the other slot keeps serving
+      // everything else a quantum at a time.
+      const int64_t bq = int64_t(kBlock) * multi_qpl();
+      const bool other_whole = batches_[1 - slot].active && batches_[1 - slot].whole;
+      b.whole = false;
+      std::vector<int64_t> take;
+      auto nblk_of = [&](const Req* q) { return (q->n_active + bq - 1) / bq; };
+      auto fits = [&](const Req* q, int64_t k) {
+        return nw + k * q->plan.S <= max_work_ &&
+               nc + chunk_comb_descs(q, q->next_blk, q->next_blk + k) <= max_comb_;
+      };
+      double budget = quantum_;
       for (Req* q : running_) {
         if (q->in_batch >= 0 || q->finalizing || q->n_active <= 0) continue;
         if (int64_t(work.size()) >= cfg_.max_inflight) break;
-        const int64_t w = work_descs(q->n_active, q->plan.S), c = comb_descs(q->n_active, q->plan.S);
-        if (nw + w > max_work_ || nc + c > max_comb_) break;  // leads the next launch
-        nw += w;
-        nc += c;
+        const int64_t rem = nblk_of(q) - q->next_blk;
+        const double per = double(bq) * double(q->N);
+        if (work.empty() && !other_whole && double(rem) * per > quantum_ && fits(q, rem)) {
+          work.push_back(q);
+          take.push_back(rem);
+          b.whole = true;
+          break;
+        }
+        if (!fits(q, 1)) break;  // leads the next launch
+        nw += q->plan.S;
+        nc += chunk_comb_descs(q, q->next_blk, q->next_blk + 1);
+        budget -= per;
         work.push_back(q);
+        take.push_back(1);
+      }
+      for (size_t i = 0; i < work.size() && !b.whole && budget > 0.0; ++i) {
+        Req* q = work[i];
+        const double per = double(bq) * double(q->N);
+        const int64_t fit = int64_t(std::min(budget / per, 1e15));  // (a huge quantum must not overflow)
+        int64_t more = std::min<int64_t>(nblk_of(q) - q->next_blk - take[i], fit);
+        while (more > 0) {
+          const int64_t w = more * q->plan.S;
+          const int64_t c = chunk_comb_descs(q, q->next_blk, q->next_blk + take[i] + more) -
+                            chunk_comb_descs(q, q->next_blk, q->next_blk + take[i]);
+          if (nw + w <= max_work_ && nc + c <= max_comb_) {
+            nw += w;
+            nc += c;
+            break;
+          }
+          more /= 2;
+        }
+        if (more <= 0) continue;
+        take[i] += more;
+        budget -= double(more) * per;
+      }
+      if (b.whole) {
+        nw = take[0] * work[0]->plan.S;
+        nc = chunk_comb_descs(work[0], work[0]->next_blk, work[0]->next_blk + take[0]);
+      }
+      for (size_t i = 0; i < work.size(); ++i) {
+        Req* q = work[i];
+        b.blk0.push_back(q->next_blk);
+        b.blk1.push_back(q->next_blk + take[i]);
+        b.last.push_back(q->next_blk + take[i] == nblk_of(q));
       }
     }
     if (work.empty()) return false;
@@ -964,7 +1044,8 @@ class Server {
     double pairs = 0;
     int64_t iw = 0, ic = 0;
     bool fold = false;
-    for (Req* q : work) {
+    for (size_t wi = 0; wi < work.size(); ++wi) {
+      Req* q = work[wi];
       fold = fold || q->plan.S > kLaneSplitsMax;
       const int64_t n = q->n_active;
       const Layout L(q->N);
@@ -981,8 +1062,7 @@ class Server {
       }
       const float* x = ev ? dev<float>(q, q->lay.x) : dev<float>(q, q->lay.xq);
       float* out = ev ? dev<float>(q, q->lay.out) : dev<float>(q, q->lay.phi);
-      const int64_t nqb = (n + int64_t(kBlock) * qpl - 1) / (int64_t(kBlock) * qpl);
-      for (int64_t qb = 0; qb < nqb; ++qb)
+      for (int64_t qb = b.blk0[wi]; qb < b.blk1[wi]; ++qb)
         for (int s = 0; s < q->plan.S; ++s) {
           WorkDesc& d = b.h_work[iw++];
           d.rec = cfg_.mock ? nullptr : base_ + q->cloud_off;
@@ -998,7 +1078,10 @@ class Server {
           d.split = s;
           d.pad = 0;
         }
-      for (int64_t qb = 0; qb < comb_descs(n, q->plan.S); ++qb) {
+      const int64_t cper = comb_per(q->plan.S);
+      const int64_t cb0 = b.blk0[wi] * (int64_t(kBlock) * qpl) / cper;
+      const int64_t cb1 = cb0 + chunk_comb_descs(q, b.blk0[wi], b.blk1[wi]);
+      for (int64_t qb = cb0; qb < cb1; ++qb) {
         CombDesc& cd = b.h_comb[ic++];
         cd.far2 = far2;
         cd.part = part;
@@ -1007,7 +1090,8 @@ class Server {
         cd.S = q->plan.S;
         cd.qb = int32_t(qb);
       }
-      pairs += double(n) * double(q->N);
+      pairs += double(std::min(n, b.blk1[wi] * int64_t(kBlock) * qpl) - b.blk0[wi] * int64_t(kBlock) * qpl) *
+               double(q->N);
     }
     b.reqs = work;
     b.rc = PTS_OK;
@@ -1019,10 +1103,12 @@ class Server {
       WorkDesc* d_work = reinterpret_cast<WorkDesc*>(base_ + b.d_work_off);
       CombDesc* d_comb = reinterpret_cast<CombDesc*>(base_ + b.d_comb_off);
       int rc = check_hip(hipEventRecord(b.ev0, st), "launch event");
-      for (Req* q : work)
-        if (!rc && q->r.kind == PTS_REQ_TRACE)
+      for (size_t i = 0; i < work.size(); ++i) {  // a trace step's positions, before its first chunk
+        Req* q = work[i];
+        if (!rc && q->r.kind == PTS_REQ_TRACE && b.blk0[i] == 0)
           rc = trace_step_pre(q->act, q->n_active, dev<float>(q, q->lay.org), dev<float>(q, q->lay.dir),
                               dev<float>(q, q->lay.t), dev<float>(q, q->lay.xq), st);
+      }
       if (!rc)
         rc = check_hip(hipMemcpyAsync(d_work, b.h_work, size_t(nw) * sizeof(WorkDesc), hipMemcpyHostToDevice, st),
                        "descriptor upload");
@@ -1033,6 +1119,7 @@ class Server {
       for (size_t i = 0; i < work.size() && !rc; ++i) {
         Req* q = work[i];
         const int64_t n = q->r.count;
+        if (!b.last[i]) continue;  // results and the step's end follow its last chunk
         if (q->r.kind == PTS_REQ_EVAL) {
           rc = check_hip(hipMemcpyAsync(q->stage + size_t(n) * 12, dev<float>(q, q->lay.out), size_t(n) * 4,
                                         hipMemcpyDeviceToHost, st),
@@ -1072,6 +1159,7 @@ class Server {
   int dev_ = 0;
   char* base_ = nullptr;
   int64_t max_work_ = 0, max_comb_ = 0;
+  double quantum_ = 0;
   std::mutex mu_;
   std::condition_variable cv_, cv_done_;
   std::thread th_;
@@ -1118,6 +1206,8 @@ int pts_server_create(const pts_server_cfg* cfg, pts_server** out) {
   if (!(c.kfloor_rel == 0.f || (c.kfloor_rel >= pts::kKfloorRelMin && std::isfinite(c.kfloor_rel))))
     return fail(PTS_EINVAL, "kfloor_rel must be 0 (default) or in [1e-12, inf)");
   if (c.mock && !(c.mock_pairs_per_s >= 0)) return fail(PTS_EINVAL, "mock_pairs_per_s must be >= 0");
+  if (!(c.quantum_pairs >= 0) || !std::isfinite(c.quantum_pairs))
+    return fail(PTS_EINVAL, "quantum_pairs must be finite and >= 0");
   auto h = std::make_unique<pts_server>();
   h->s = std::make_unique<pts::Server>(c);
   if (int rc = h->s->init()) return rc;

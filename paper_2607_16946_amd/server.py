@@ -52,10 +52,11 @@ class Server:
 
     def __init__(self, budget_bytes: int = 4 << 30, max_inflight: int = 64, max_queue: int = 0,
                  max_batch_work: int = 0, C: float = 64.0, kfloor_rel: float = 1e-6, mock: bool = False,
-                 mock_fail_count: int = 0, mock_pairs_per_s: float = 0.0):
+                 mock_fail_count: int = 0, mock_pairs_per_s: float = 0.0, quantum_pairs: float = 0.0):
         self._L = binding.lib()
         cfg = ServerCfg(int(budget_bytes), int(max_inflight), int(max_queue), int(max_batch_work), float(C),
-                        float(kfloor_rel), int(bool(mock)), int(mock_fail_count), float(mock_pairs_per_s))
+                        float(kfloor_rel), int(bool(mock)), int(mock_fail_count), float(mock_pairs_per_s),
+                        float(quantum_pairs))
         h = ctypes.c_void_p()
         self._rc(self._L.pts_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

@@ -197,9 +197,11 @@ def test_errors_and_cloud_lifecycle():
         with pytest.raises(PtsError) as e:
             S.submit_eval(c + 100, _x(5))
         assert e.value.code == binding.PTS_ENOTFOUND
-        with pytest.raises(PtsError) as e:     # more workgroups than one launch holds
-            S.submit_eval(c, _x(64 * 512))
-        assert e.value.code == binding.PTS_EINVAL
+        # more workgroups than one launch holds: spread over launches of at most 64 workgroups
+        big = S.submit_eval(c, _x(64 * 512))
+        n0 = S.stats()["launches"]
+        np.testing.assert_allclose(S.wait(big), _pattern(c, 64 * 512), rtol=1e-6)
+        assert S.stats()["launches"] - n0 >= 64 * 2 // 64
         with pytest.raises(PtsError) as e:
             S.submit_trace(c, _x(4), _x(4), steps=-1, eps=1e-3, tmax=1.0)
         assert e.value.code == binding.PTS_EINVAL
@@ -220,6 +222,15 @@ def test_errors_and_cloud_lifecycle():
         c2 = S.add_cloud(*_cloud(10))
         assert c2 != c
         assert S.cloud_plan(c2) == (10, 1)
+    # one block of a trace on a cloud split 8 ways needs 8 workgroups: a 2-workgroup launch cannot hold
+    # it (a query request falls back to a split that fits)
+    with Server(budget_bytes=64 << 20, mock=True, max_batch_work=2, mock_pairs_per_s=1e8) as S:
+        c = S.add_cloud(*_cloud(9000))
+        assert S.cloud_plan(c) == (9000, 8)
+        with pytest.raises(PtsError) as e:
+            S.submit_trace(c, _x(4), np.ones((4, 3), np.float32), steps=2, eps=1e-3, tmax=1.0)
+        assert e.value.code == binding.PTS_EINVAL
+        np.testing.assert_allclose(S.wait(S.submit_eval(c, _x(5))), _pattern(c, 5), rtol=1e-6)
 
 
 def test_close_cancels_waiters():
@@ -275,3 +286,38 @@ def test_many_clients_many_clouds():
         st = S.stats()
         assert st["completed"] == 90 and st["inflight"] == 0 and st["queued"] == 0
         assert st["bytes_inflight"] == 0
+
+
+def test_quantum_spreads_long_requests_and_lets_short_ones_pass():
+    """A launch takes at most quantum_pairs of work, except that one launch in flight may run a single
+    long request whole: a first long query request runs whole, a second one behind it is spread over
+    launches of one quantum each in the other slot, and a short request submitted behind both finishes
+    within a few quanta; every result lands in its own request whichever chunks carried it."""
+    N, big = 4000, 65536                       # 128 blocks of 512 queries, 2.6e8 pairs
+    quantum = 512 * N * 8                      # 8 blocks per launch
+    rate = quantum / 0.02                      # 20 ms per full launch
+    with Server(budget_bytes=256 << 20, mock=True, max_batch_work=1 << 16, mock_pairs_per_s=rate,
+                quantum_pairs=quantum) as S:
+        c = S.add_cloud(*_cloud(N))
+        t_big1, t_big2 = S.submit_eval(c, _x(big)), S.submit_eval(c, _x(big))
+        time.sleep(0.005)
+        t0 = time.time()
+        t_small = S.submit_eval(c, _x(100))
+        np.testing.assert_allclose(S.wait(t_small), _pattern(c, 100), rtol=1e-6)
+        small_s = time.time() - t0
+        assert S.poll(t_big1) == "running" and S.poll(t_big2) == "running"
+        for t in (t_big1, t_big2):
+            np.testing.assert_allclose(S.wait(t), _pattern(c, big), rtol=1e-6)
+        big_s = time.time() - t0
+        st = S.stats()
+        assert st["launches"] >= 1 + 128 // 8            # the first whole, the second in quanta
+        assert small_s < 0.1 < big_s, (small_s, big_s)   # a few quanta against ~16
+        # a trace step of many rays behind a whole launch: chunked, results intact
+        t_big3 = S.submit_eval(c, _x(big))
+        tr = S.submit_trace(c, _x(40000), np.ones((40000, 3), np.float32), steps=5, eps=1e-3, tmax=5.0)
+        r = S.wait(tr)
+        assert np.all(r["t"] == c) and np.array_equal(r["hit"], np.arange(40000) % 2)
+        assert np.all(r["steps"] == 3)
+        S.wait(t_big3)
+    with pytest.raises(PtsError):
+        Server(mock=True, quantum_pairs=-1.0)
