@@ -190,7 +190,7 @@ def configs_bench(threads: int):
         rec = binding.cloud_build(p, n, a, prm)
         ws = torch.empty(max(binding.eval_ws_bytes(N, Q, prm), 256), dtype=torch.uint8, device="cuda")
         sdf = torch.empty(Q, dtype=torch.float32, device="cuda")
-        ms = _timed(lambda: binding.eval(rec, N, xd, prm, ws=ws, out=sdf), 5)
+        ms = _timed(lambda: binding.eval(rec, N, xd, prm, ws=ws, out=sdf), 5 if N * Q > 1e9 else 50, warm=3)
         phi = sdf.cpu().numpy().astype(np.float64)
         idx = np.arange(Q) if Q <= 4096 else np.sort(np.random.default_rng(8192).choice(Q, 8192, replace=False))
         t0 = time.perf_counter()
@@ -493,7 +493,7 @@ def serving_bench(n_requests: int, n_warmup: int, loads, n_clouds: int = 64, bud
     return out
 
 
-def step_bench(cl, x, steps: int, warmup: int, label: str):
+def step_bench(cl, x, steps: int, warmup: int, label: str, splits: int = 0):
     """One step = the whole hot path through the C ABI on resident inputs: torus
     fitting (pts_cloud_build), the farthest-point sweep, the blend sweep and the
     split combine (pts_eval_far / _blend / _combine).  Returns wall ms per step
@@ -505,7 +505,7 @@ def step_bench(cl, x, steps: int, warmup: int, label: str):
     N, Q = cl.N, x.shape[0]
     p, n, a = (torch.from_numpy(v).cuda() for v in (cl.p, cl.n, cl.a))
     xd = torch.from_numpy(x).cuda()
-    prm = binding.make_params()
+    prm = binding.make_params(splits=splits)
     rec = torch.empty(binding.record_bytes(N), dtype=torch.uint8, device="cuda")
     ws = torch.empty(max(binding.eval_ws_bytes(N, Q, prm), 256), dtype=torch.uint8, device="cuda")
     sdf = torch.empty(Q, dtype=torch.float32, device="cuda")
@@ -566,6 +566,28 @@ def roofline_of(stage, pairs: float, traffic_key: str):
         "far_sweep": {"ms": stage["far"], "flop_per_pair": FAR_FLOP,
                       "tflops": FAR_FLOP * pairs / (stage["far"] * 1e-3) / 1e12},
     }
+
+
+def small_bench(reps: int = 100):
+    """Latency of small evaluations (pts_eval, phi only): the tiny cloud (4096
+    points on the unit sphere) and a 262,144-point sphere cloud, at 1 to 65,536
+    uniform queries; median of `reps` HIP-event-timed calls after 5 warm-ups."""
+    import numpy as np
+    import torch
+    from paper_2607_16946_amd import binding, synth
+    out = {}
+    prm = binding.make_params()
+    for name, cl in (("tiny 4096", synth.tiny()[0]), ("sphere 262144", synth.sphere_cloud(262144, 77))):
+        c = binding.Cloud(*(torch.from_numpy(v).cuda() for v in (cl.p, cl.n, cl.a)))
+        for Q in (1, 64, 1024, 4096, 65536):
+            x = torch.from_numpy(np.random.default_rng(Q).uniform(-1.5, 1.5, size=(Q, 3)).astype(np.float32)).cuda()
+            ws = torch.empty(max(binding.eval_ws_bytes(c.N, Q, prm), 256), dtype=torch.uint8, device="cuda")
+            sdf = torch.empty(Q, dtype=torch.float32, device="cuda")
+            ms = _timed(lambda: binding.eval(c.rec, c.N, x, prm, ws=ws, out=sdf), reps, warm=5)
+            out[f"{name}, Q={Q}"] = {"ms": ms, "plan": list(binding.eval_plan(c.N, Q, prm)),
+                                     "pairs_per_s": float(c.N) * Q / (ms * 1e-3)}
+            log(f"small: {name} points, {Q} queries: {ms * 1e3:.1f} us, plan {binding.eval_plan(c.N, Q, prm)}")
+    return out
 
 
 def trace_bench(cl, res: int = 1024, steps: int = 64):
@@ -640,6 +662,10 @@ def main():
     ap.add_argument("--diff-only", action="store_true", help="only the differentiation workload")
     ap.add_argument("--bounded-only", action="store_true", help="only the error-bounded evaluation")
     ap.add_argument("--step-only", choices=("large", "mid"), help="only the timed steps of one workload")
+    ap.add_argument("--radius-only", choices=("large", "mid"), help="only the radius-limited evaluation of one workload")
+    ap.add_argument("--splits", type=int, default=0, help="pts_params.splits of --step-only (0 = automatic)")
+    ap.add_argument("--small-only", action="store_true", help="only the latency of small evaluations")
+    ap.add_argument("--no-small", action="store_true", help="skip the latency of small evaluations")
     ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per load level")
     ap.add_argument("--serve-warmup", type=int, default=50)
     ap.add_argument("--serve-loads", default="0.5,0.9", help="arrival rates as fractions of capacity")
@@ -683,9 +709,16 @@ def main():
         cl, x = synth.mid()
         print(json.dumps({"bounded": bounded_bench(cl, x)}))
         return
+    if args.small_only:
+        print(json.dumps({"small": small_bench()}))
+        return
+    if args.radius_only:
+        cl, x = synth.large() if args.radius_only == "large" else synth.mid()
+        print(json.dumps({"radius_limited": radius_bench(args.radius_only, cl, x)}))
+        return
     if args.step_only:
         cl, x = synth.large() if args.step_only == "large" else synth.mid()
-        ms, stage = step_bench(cl, x, args.steps, args.warmup, args.step_only)
+        ms, stage = step_bench(cl, x, args.steps, args.warmup, args.step_only, args.splits)
         print(json.dumps({"workload": args.step_only, "ms_per_step": ms, "stages_ms": stage,
                           "pairs_per_s": float(cl.N) * x.shape[0] / (ms * 1e-3)}))
         return
@@ -743,6 +776,8 @@ def main():
     if not args.no_bounded:
         out["bounded"] = bounded_bench(mid_cl, mid_x)
     del mid_cl, mid_x
+    if not args.no_small:
+        out["small"] = small_bench()
     if not args.no_diff:
         out["diff"] = diff_bench(5)
     if not args.no_serving:

@@ -157,10 +157,11 @@ int pts_cloud_decode(const void* rec, int64_t N, float* out, void* stream);
 /* Launch plan pts_eval uses for N points and Q queries (a pure function of N,
  * Q and the parameters): queries per lane, number of point splits, and points
  * per split (a multiple of 64; splits * per_split >= N, every split
- * non-empty).  Few queries get many short splits (down to 64 points, at most
- * 1024 splits): a workgroup walks its split serially, so the split length
- * sets the latency of a small evaluation.  For inspection and tests; host
- * only. */
+ * non-empty).  Many points get 8 splits, one per XCD, or 32 when an eighth of
+ * the records would not fit an XCD's L2 (over about 420k points); few
+ * queries get many short splits (down to 64 points, at most 1024): a
+ * workgroup walks its split serially, so the split length sets the latency
+ * of a small evaluation.  For inspection and tests; host only. */
 int pts_eval_plan(int64_t N, int64_t Q, const pts_params* prm, int* qpl, int* splits,
                   int64_t* per_split);
 

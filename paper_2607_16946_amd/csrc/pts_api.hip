@@ -73,6 +73,10 @@ Plan make_plan(int64_t N, int64_t Q, const pts_params* prm, int max_auto_splits)
     // point)
     S = 1;
     while (S < 8 && tiles >= int64_t(2) * S * 2) S *= 2;
+    // four splits per XCD when one XCD's eighth of the records would not fit
+    // its 4 MiB L2: the blend takes an XCD's splits one after the other
+    // (split_block), so its resident workgroups share a quarter of that
+    if (S == 8 && max_auto_splits >= 32 && N * int64_t(kRecF4 * 16) / 8 > (int64_t(4) << 20)) S = 32;
     while (S < max_auto_splits && p.nqb * S < 4096 && gran >= int64_t(2) * S) S *= 2;
   }
   S = int(std::max<int64_t>(1, std::min<int64_t>(S, gran)));

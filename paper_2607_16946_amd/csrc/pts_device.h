@@ -34,6 +34,23 @@ __device__ __forceinline__ QueryIn load_query(const float* __restrict__ x, int64
   return r;
 }
 
+// Split and query block of workgroup b of a sweep over S point splits.  The
+// dispatcher places consecutive workgroups on consecutive XCDs (8 of them),
+// so with S a multiple of 8, XCD k runs splits k, k + 8, ... one after the
+// other, each for every query block (nqb of them): its resident workgroups
+// then read one split's records, which stay in that XCD's L2.  (For S = 8
+// this is split = b % 8, block = b / 8.)  Otherwise split = b % S.
+__device__ __forceinline__ void split_block(unsigned b, int S, int64_t nqb, int& split, int64_t& qb) {
+  if (S % 8 == 0) {
+    const int64_t i = int64_t(b / 8u);
+    split = int(b % 8u) + 8 * int(i / nqb);
+    qb = i % nqb;
+  } else {
+    split = int(b % unsigned(S));
+    qb = int64_t(b / unsigned(S));
+  }
+}
+
 // M and -lambda' = -lambda log2(e) of a query from the per-split maxima of
 // |x - p|^2 (Eq. RelationshipBetweenLambdaAndRadius: lambda_x = 2C/M).
 __device__ __forceinline__ void far_of(const float* __restrict__ far2, int S, int64_t Q, int64_t q, float C2,

@@ -161,8 +161,9 @@ __global__ __launch_bounds__(kBlock) void k_blend(const Header* __restrict__ h, 
                                                   const float* __restrict__ far2, int far_rows, float C2, float S2,
                                                   float2* __restrict__ part) {
   __shared__ float4 tile[kTile2 * kRecF4];
-  const int split = int(blockIdx.x % unsigned(S));
-  const int64_t qb = blockIdx.x / unsigned(S);
+  int split;
+  int64_t qb;
+  split_block(blockIdx.x, S, int64_t(gridDim.x) / S, split, qb);
   const int64_t N = h->N;
   const int64_t nd = h->n_direct;
   float qx[QPL], qy[QPL], qz[QPL], nl[QPL], num[QPL], den[QPL];
@@ -226,7 +227,8 @@ __global__ __launch_bounds__(kBlock) void k_blend(const Header* __restrict__ h, 
 }
 
 // Fixed-order combine of the split partials (pts_device.h): one lane per
-// query up to kLaneSplitsMax splits, one wavefront per query beyond.
+// query, or one wavefront per query for many splits and few queries
+// (combine_by_wave).
 __global__ __launch_bounds__(kBlock) void k_combine(const float2* __restrict__ part, int S, int64_t Q,
                                                     float* __restrict__ sdf, float offset) {
   const int64_t q = int64_t(blockIdx.x) * kBlock + threadIdx.x;
@@ -251,7 +253,7 @@ void launch_far_q(const Header* h, const float4* pos4, const float4* ub, const f
   if (S > 1) {
     hipLaunchKernelGGL((k_far_split<QPL, kArg>), dim3(unsigned(nqb * S)), dim3(kBlock), 0, st, h, pos4, ub, x, Q, S,
                        per_split, far2, farix);
-    if (fold && (farix || S <= kLaneSplitsMax))
+    if (fold && (farix || !combine_by_wave(S, Q)))
       hipLaunchKernelGGL(k_far_fold, dim3(unsigned((Q + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, far2, farix, S,
                          Q);
     else if (fold)
@@ -393,7 +395,7 @@ int launch_eval_plain(const void* rec, int64_t N, const float* x, int64_t Q, flo
 }
 
 int launch_combine(int64_t Q, const Plan& plan, const WsView& ws, float* sdf, hipStream_t st, float offset) {
-  if (plan.S <= kLaneSplitsMax)
+  if (!combine_by_wave(plan.S, Q))
     hipLaunchKernelGGL(k_combine, dim3(unsigned((Q + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, ws.part, plan.S,
                        Q, sdf, offset);
   else

@@ -129,6 +129,12 @@ constexpr int kPlainSplitMax = 1024;
 // partials -- run in one lane up to kLaneSplitsMax splits (the blend then
 // reads the unfolded maxima itself), in one wavefront beyond.
 constexpr int kLaneSplitsMax = 16;
+// The combine, though, stays one lane per query from kLaneCombineMinQ queries
+// on, whatever the split count: a wavefront per query reads a column of the
+// partials (one 8-byte value per 128-byte line), which only pays when there
+// are too few queries to occupy the lanes.
+constexpr int64_t kLaneCombineMinQ = 32768;
+__host__ __device__ inline bool combine_by_wave(int S, int64_t Q) { return S > kLaneSplitsMax && Q < kLaneCombineMinQ; }
 Plan make_plan(int64_t N, int64_t Q, const pts_params* prm, int max_auto_splits = kAutoSplitMax);
 // The same split with a different number of queries per lane.
 inline Plan with_qpl(Plan p, int qpl, int64_t Q) {

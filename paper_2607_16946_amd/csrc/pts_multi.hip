@@ -129,11 +129,16 @@ __global__ __launch_bounds__(kBlock) void k_blend_multi(const WorkDesc* __restri
 }
 
 // Between the two sweeps, for requests with more than kLaneSplitsMax splits:
-// their per-split maxima folded into row 0, one wavefront per query, over
-// the combine's descriptors (kBlock / 64 queries each for such requests).
+// their per-split maxima folded into row 0 over the combine's descriptors,
+// as the combine partitions the queries (a lane or a wavefront per query).
 __global__ __launch_bounds__(kBlock) void k_fold_multi(const CombDesc* __restrict__ descs) {
   const CombDesc c = descs[blockIdx.x];
   if (c.S <= kLaneSplitsMax) return;
+  if (!combine_by_wave(c.S, c.Q)) {  // this descriptor covers kBlock queries: one lane each
+    const int64_t q = int64_t(c.qb) * kBlock + threadIdx.x;
+    if (q < c.Q) c.far2[q] = fold_seq(c.far2, c.S, c.Q, q);
+    return;
+  }
   const int64_t q = int64_t(c.qb) * (kBlock / 64) + threadIdx.x / 64;
   const int lane = int(threadIdx.x & 63);
   const float m = fold_wave(c.far2, c.S, c.Q, q, lane);
@@ -142,10 +147,10 @@ __global__ __launch_bounds__(kBlock) void k_fold_multi(const CombDesc* __restric
 
 // One workgroup per (request, block of queries): the fixed-order combine of
 // pts_device.h, as k_combine / k_combine_wave do it -- kBlock queries one per
-// lane up to kLaneSplitsMax splits, else kBlock / 64 queries one per wave.
+// lane, or, when combine_by_wave, kBlock / 64 queries one per wave.
 __global__ __launch_bounds__(kBlock) void k_combine_multi(const CombDesc* __restrict__ descs) {
   const CombDesc c = descs[blockIdx.x];
-  if (c.S <= kLaneSplitsMax) {
+  if (!combine_by_wave(c.S, c.Q)) {
     const int64_t q = int64_t(c.qb) * kBlock + threadIdx.x;
     if (q >= c.Q) return;
     const float2 v = combine_seq(c.part, c.S, c.Q, q);

@@ -385,7 +385,7 @@ class Server {
       // function of N only.  Launches take a request in chunks of blocks.
       const int64_t bq = int64_t(kBlock) * multi_qpl();
       auto fits = [&](const Plan& pl) {
-        return pl.S <= max_work_ && (bq + comb_per(pl.S) - 1) / comb_per(pl.S) <= max_comb_;
+        return pl.S <= max_work_ && (bq + comb_per(pl.S, n) - 1) / comb_per(pl.S, n) <= max_comb_;
       };
       if (r->kind == PTS_REQ_EVAL) {
         q->plan = make_plan(c.N, n, &P_, kPlainSplitMax);
@@ -937,11 +937,12 @@ class Server {
 
   // Queries per packed-combine workgroup, and the combine workgroups of work
   // blocks [k0, k1) of a request's current evaluation / step.
-  static int64_t comb_per(int S) { return S <= kLaneSplitsMax ? kBlock : kBlock / 64; }
+  static int64_t comb_per(int S, int64_t n) { return combine_by_wave(S, n) ? kBlock / 64 : kBlock; }
   static int64_t chunk_comb_descs(const Req* q, int64_t k0, int64_t k1) {
     const int64_t bq = int64_t(kBlock) * multi_qpl();
     const int64_t q0 = k0 * bq, q1 = std::min(q->n_active, k1 * bq);
-    return (q1 - q0 + comb_per(q->plan.S) - 1) / comb_per(q->plan.S);
+    const int64_t per = comb_per(q->plan.S, q->n_active);
+    return (q1 - q0 + per - 1) / per;
   }
 
   // Pack runnable requests (in admission order, chunks of at most a quantum
@@ -1078,7 +1079,7 @@ class Server {
           d.split = s;
           d.pad = 0;
         }
-      const int64_t cper = comb_per(q->plan.S);
+      const int64_t cper = comb_per(q->plan.S, n);
       const int64_t cb0 = b.blk0[wi] * (int64_t(kBlock) * qpl) / cper;
       const int64_t cb1 = cb0 + chunk_comb_descs(q, b.blk0[wi], b.blk1[wi]);
       for (int64_t qb = cb0; qb < cb1; ++qb) {
