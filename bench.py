@@ -665,6 +665,7 @@ def main():
     ap.add_argument("--radius-only", choices=("large", "mid"), help="only the radius-limited evaluation of one workload")
     ap.add_argument("--splits", type=int, default=0, help="pts_params.splits of --step-only (0 = automatic)")
     ap.add_argument("--small-only", action="store_true", help="only the latency of small evaluations")
+    ap.add_argument("--baselines-only", action="store_true", help="only the two baselines (mid workload)")
     ap.add_argument("--no-small", action="store_true", help="skip the latency of small evaluations")
     ap.add_argument("--serve-requests", type=int, default=2000, help="measured requests per load level")
     ap.add_argument("--serve-warmup", type=int, default=50)
@@ -708,6 +709,10 @@ def main():
     if args.bounded_only:
         cl, x = synth.mid()
         print(json.dumps({"bounded": bounded_bench(cl, x)}))
+        return
+    if args.baselines_only:
+        cl, x = synth.mid()
+        print(json.dumps({"baselines": baseline_bench(cl, x)}))
         return
     if args.small_only:
         print(json.dumps({"small": small_bench()}))

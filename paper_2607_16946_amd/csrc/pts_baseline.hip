@@ -31,9 +31,10 @@ __global__ __launch_bounds__(kBlock) void k_base(const Header* __restrict__ h, c
                                                  const float* __restrict__ x, int64_t Q, int S, int64_t per_split,
                                                  const float* __restrict__ far2, float C, float2* __restrict__ part) {
   __shared__ float4 tile[kTileB * 2];
-  int split;
-  int64_t qb;
-  split_block(blockIdx.x, S, int64_t(gridDim.x) / S, split, qb);
+  // split = b % S: the blend's split-major order (split_block) is not worth
+  // the slower pair-loop schedule hipcc gives this sweep with it
+  const int split = int(blockIdx.x % unsigned(S));
+  const int64_t qb = blockIdx.x / unsigned(S);
   const int64_t N = h->N;
   const float C2 = C * kLog2e, S2 = shift2_of(C);
   float qx[QPL], qy[QPL], qz[QPL], nl[QPL], lam[QPL], num[QPL], den[QPL];

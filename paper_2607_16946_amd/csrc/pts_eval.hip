@@ -155,7 +155,8 @@ __global__ __launch_bounds__(kBlock) void k_far_fold_wave(float* __restrict__ fa
 // ---------------------------------------------------------------------------
 // far_rows: rows of far2 holding per-split maxima (1 once k_far_fold has
 // folded them); the blend takes their maximum itself when the fold is skipped.
-template <int QPL>
+// kMajor: split_major(S), workgroups in split-major order (split_block).
+template <int QPL, bool kMajor>
 __global__ __launch_bounds__(kBlock) void k_blend(const Header* __restrict__ h, const float4* __restrict__ rec,
                                                   const float* __restrict__ x, int64_t Q, int S, int64_t per_split,
                                                   const float* __restrict__ far2, int far_rows, float C2, float S2,
@@ -163,7 +164,12 @@ __global__ __launch_bounds__(kBlock) void k_blend(const Header* __restrict__ h, 
   __shared__ float4 tile[kTile2 * kRecF4];
   int split;
   int64_t qb;
-  split_block(blockIdx.x, S, int64_t(gridDim.x) / S, split, qb);
+  if constexpr (kMajor) {
+    split_block(S, split, qb);
+  } else {
+    split = int(blockIdx.x % unsigned(S));
+    qb = blockIdx.x / unsigned(S);
+  }
   const int64_t N = h->N;
   const int64_t nd = h->n_direct;
   float qx[QPL], qy[QPL], qz[QPL], nl[QPL], num[QPL], den[QPL];
@@ -268,8 +274,12 @@ void launch_far_q(const Header* h, const float4* pos4, const float4* ub, const f
 template <int QPL>
 void launch_blend_q(const Header* h, const float4* rec, const float* x, int64_t Q, const Plan& plan,
                     const float* far2, int far_rows, float2* part, float C2, float S2, hipStream_t st) {
-  hipLaunchKernelGGL(k_blend<QPL>, dim3(unsigned(plan.nqb * plan.S)), dim3(kBlock), 0, st, h, rec, x, Q, plan.S,
-                     plan.per_split, far2, far_rows, C2, S2, part);
+  if (split_major(plan.S))
+    hipLaunchKernelGGL((k_blend<QPL, true>), dim3(unsigned(plan.nqb * plan.S)), dim3(kBlock), 0, st, h, rec, x, Q,
+                       plan.S, plan.per_split, far2, far_rows, C2, S2, part);
+  else
+    hipLaunchKernelGGL((k_blend<QPL, false>), dim3(unsigned(plan.nqb * plan.S)), dim3(kBlock), 0, st, h, rec, x, Q,
+                       plan.S, plan.per_split, far2, far_rows, C2, S2, part);
 }
 
 // The farthest-point sweep's launch shape for an evaluation plan: queries per

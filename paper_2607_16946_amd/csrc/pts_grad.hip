@@ -108,9 +108,10 @@ __global__ __launch_bounds__(kBlock) void k_grad(const Header* __restrict__ h, c
                                                  const float* __restrict__ stats, float C2, float S2,
                                                  float4* __restrict__ gpart, float* __restrict__ vpart) {
   __shared__ float4 tile[kTile2 * kRecF4];
-  int split;
-  int64_t qb;
-  split_block(blockIdx.x, S, int64_t(gridDim.x) / S, split, qb);
+  // split = b % S: the blend's split-major order (split_block) is not worth
+  // the slower pair-loop schedule hipcc gives this sweep with it (10%)
+  const int split = int(blockIdx.x % unsigned(S));
+  const int64_t qb = blockIdx.x / unsigned(S);
   const int64_t N = h->N;
   const int64_t nd = h->n_direct;
   float qx[QPL], qy[QPL], qz[QPL], nl[QPL], ph[QPL];

@@ -108,9 +108,10 @@ __global__ __launch_bounds__(kBlock) void k_lap(const Header* __restrict__ h, co
                                                 const float* __restrict__ stats, float C2, float S2,
                                                 double2* __restrict__ part) {
   __shared__ float4 tile[kTile2 * kRecF4];
-  int split;
-  int64_t qb;
-  split_block(blockIdx.x, S, int64_t(gridDim.x) / S, split, qb);
+  // split = b % S: the blend's split-major order (split_block) is not worth
+  // the slower pair-loop schedule hipcc gives this sweep with it
+  const int split = int(blockIdx.x % unsigned(S));
+  const int64_t qb = blockIdx.x / unsigned(S);
   const int64_t N = h->N;
   const int64_t nd = h->n_direct;
   float qx[QPL], qy[QPL], qz[QPL], nl[QPL], ph[QPL], es[QPL][3];

@@ -160,7 +160,7 @@ def test_split_count_only_changes_rounding():
     bad = np.abs(dec[:, 0:3] - tor.c).max(axis=1) > 2e-6 * (np.abs(tor.c).max(axis=1) + 1.0)
     _say("splits: torus mismatches", int(bad.sum()), np.nonzero(bad)[0][:10])
     outs = {}
-    for S in (0, 1, 2, 8, 32):
+    for S in (0, 1, 2, 8, 16, 32):  # 16 and 32: the split-major blend
         plan = binding.eval_plan(cl.N, x.shape[0], binding.make_params(splits=S))
         o = _build(cl, splits=S)(_dev(x)).cpu().numpy().astype(np.float64)
         outs[S] = o
