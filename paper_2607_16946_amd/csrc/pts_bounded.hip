@@ -89,6 +89,9 @@ __device__ __forceinline__ void pair(float qx, float qy, float qz, float nl, flo
   td += w;
 }
 
+// Blocks taken nearest-first at the start of a wave's sweep.
+constexpr int kNear = 8;
+
 // One wavefront per workgroup: waves sweep, vote and stage independently (a
 // wave never waits on units only another wave keeps).
 constexpr int kBW = 64;
@@ -190,7 +193,8 @@ __device__ __forceinline__ bool vote(const float4& sb, float n, const float* qx,
 }
 
 template <int QPL>
-__global__ __launch_bounds__(kBW) void k_bounded(const Header* __restrict__ h, const float4* __restrict__ rec,
+// 8 waves per SIMD (at most 64 VGPRs)
+__global__ __launch_bounds__(kBW, 8) void k_bounded(const Header* __restrict__ h, const float4* __restrict__ rec,
                                                  const float4* __restrict__ ub, const float4* __restrict__ bb,
                                                  const float* __restrict__ x,
                                                  const int32_t* __restrict__ order, const int32_t* __restrict__ border,
@@ -249,13 +253,53 @@ __global__ __launch_bounds__(kBW) void k_bounded(const Header* __restrict__ h, c
     ustart = nearest_unit(ub, u_beg, u_end, r0.x, r0.y, r0.z, red_v, red_i);
   }
   int32_t kept = 0;
-  // blocks of kBlkU units (their bounding spheres from the build), starting at
-  // the seed's block; within that block, starting at the seed unit
+  // Blocks of kBlkU units (their bounding spheres from the build): the block
+  // of the first unit, then the kNear - 1 blocks nearest to the wave's first
+  // query (by sphere lower bound, ties to the lower index), nearest first,
+  // then the others from the first unit's block on, wrapping.  The kept
+  // denominator is then close to its final value before far blocks are voted
+  // on.  Within the first block the sweep starts at the first unit.
   const int64_t b_beg = u_beg / kBlkU, b_end = (u_end + kBlkU - 1) / kBlkU, nbk = b_end - b_beg;
   const int64_t bstart = ustart / kBlkU;
-  for (int64_t ib = 0; ib < nbk; ++ib) {
-    int64_t b = bstart + ib;
-    if (b >= b_end) b -= nbk;
+  // (eps = 0 skips nothing: index order, whose shared walk keeps the records
+  // that neighbouring waves read in L2)
+  const int n_near = eps_total > 0.f ? int(min<int64_t>(kNear, nbk)) : 1;
+  // the list: lane t holds entry t (read back with readlane, no LDS)
+  int32_t near_l = int32_t(bstart);
+  for (int t = 1; t < n_near; ++t) {
+    float best = 3.0e38f;
+    int32_t bi = INT32_MAX;
+    for (int64_t b = b_beg + threadIdx.x; b < b_end; b += kBW) {
+      bool taken = false;
+      for (int i = 0; i < t; ++i) taken = taken || __builtin_amdgcn_readlane(near_l, i) == int32_t(b);
+      if (taken) continue;
+      const float4 cb = bb[b];
+      const float ex = r0.x - cb.x, ey = r0.y - cb.y, ez = r0.z - cb.z;
+      const float lb = hw_sqrt(fmaf(ez, ez, fmaf(ey, ey, ex * ex))) - cb.w;
+      if (lb < best || (lb == best && int32_t(b) < bi)) { best = lb; bi = int32_t(b); }
+    }
+#pragma unroll
+    for (int o = kBW / 2; o > 0; o >>= 1) {
+      const float v2 = __shfl_xor(best, o, kBW);
+      const int32_t i2 = __shfl_xor(bi, o, kBW);
+      if (v2 < best || (v2 == best && i2 < bi)) { best = v2; bi = i2; }
+    }
+    if (int(threadIdx.x) == t) near_l = bi;
+  }
+  for (int64_t ib = 0, iw = 0; ib < nbk; ++ib) {
+    int64_t b;
+    if (ib < n_near) {
+      b = __builtin_amdgcn_readlane(near_l, int(ib));
+    } else {
+      for (;;) {  // the next block in wrap order not visited among the nearest
+        b = bstart + iw++;
+        if (b >= b_end) b -= nbk;
+        bool taken = false;
+        for (int i = 0; i < n_near; ++i) taken = taken || __builtin_amdgcn_readlane(near_l, i) == int32_t(b);
+        if (!taken) break;
+      }
+      b = __builtin_amdgcn_readfirstlane(int32_t(b));
+    }
     const int64_t bu0 = max(b * kBlkU, u_beg), bu1 = min(b * kBlkU + kBlkU, u_end);
     if (ib > 0 && vote<QPL>(bb[b], float(min(end, bu1 * kUnit) - bu0 * kUnit), qx, qy, qz, nl, S2, A, phimax, gs, ds, den,
                        wseed, eps, live)) continue;
@@ -275,12 +319,14 @@ __global__ __launch_bounds__(kBW) void k_bounded(const Header* __restrict__ h, c
       float tn[QPL], td[QPL];
 #pragma unroll
       for (int k = 0; k < QPL; ++k) { tn[k] = 0.f; td[k] = 0.f; }
+#pragma unroll 2
       for (int j = 0; j < jd; ++j) {
         const float4 P = tile[j * kRecF4 + 0], U = tile[j * kRecF4 + 1], Mv = tile[j * kRecF4 + 2],
                      K = tile[j * kRecF4 + 3], G = tile[j * kRecF4 + 4];
 #pragma unroll
         for (int k = 0; k < QPL; ++k) pair<true>(qx[k], qy[k], qz[k], nl[k], S2, P, U, Mv, K, G, tn[k], td[k]);
       }
+#pragma unroll 2
       for (int j = jd; j < cnt; ++j) {
         const float4 P = tile[j * kRecF4 + 0], U = tile[j * kRecF4 + 1], Mv = tile[j * kRecF4 + 2],
                      K = tile[j * kRecF4 + 3], G = tile[j * kRecF4 + 4];
@@ -416,7 +462,9 @@ int launch_bounded(const void* rec, int64_t N, const float* x, int64_t Q, float 
   const unsigned qblocks = unsigned((Q + kBlock - 1) / kBlock);
   const int32_t* order = nullptr;
   if (int rc = launch_query_order(rec, x, Q, v.key, v.idx, v.rhist, st, &order)) return rc;
-  if (int rc = launch_far_cull(rec, N, x, Q, plan.qpl, v.far2, nullptr, st)) return rc;
+  // M at up to 4 queries per lane (exact in any order: the sweep's own plan
+  // has one)
+  if (int rc = launch_far_cull(rec, N, x, Q, 4, v.far2, nullptr, st)) return rc;
   // heavy query blocks first
   const float C2 = C * kLog2e, S2 = shift2_of(C);
   hipLaunchKernelGGL(k_bwork, dim3(unsigned((plan.nqb + kWorkBlock - 1) / kWorkBlock)), dim3(kWorkBlock), 0, st, h, ub,

@@ -188,27 +188,47 @@ __global__ __launch_bounds__(kBlock) void k_rhist(const uint32_t* __restrict__ k
   if (threadIdx.x < (1 << kSortBits)) hist[int64_t(threadIdx.x) * nb + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// Exclusive scan of n int32 in place (one workgroup of 1024 threads).
+// Exclusive scan of n int32 in place (one workgroup of 1024 threads).  Each
+// round covers 8192 values, 8 consecutive ones per thread: the thread's total,
+// an inclusive scan of the totals within each wavefront (shuffles), the 16
+// wavefront totals through LDS, then the thread writes its 8 prefixes.
 __global__ __launch_bounds__(1024) void k_exscan(int32_t* __restrict__ v, int64_t n) {
-  __shared__ int32_t s[1024];
-  __shared__ int32_t carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (int64_t base = 0; base < n; base += 1024) {
-    const int64_t i = base + threadIdx.x;
-    const int32_t x = i < n ? v[i] : 0;
-    s[threadIdx.x] = x;
-    __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-      const int32_t t = threadIdx.x >= unsigned(o) ? s[threadIdx.x - o] : 0;
-      __syncthreads();
-      s[threadIdx.x] += t;
-      __syncthreads();
+  constexpr int kPer = 8, kWaves = 1024 / 64;
+  __shared__ int32_t wsum[kWaves];
+  const int t = int(threadIdx.x), lane = t & 63, w = t >> 6;
+  int32_t carry = 0;
+  for (int64_t base = 0; base < n; base += int64_t(1024) * kPer) {
+    const int64_t i0 = base + int64_t(t) * kPer;
+    int32_t x[kPer];
+    int32_t tot = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      x[k] = i0 + k < n ? v[i0 + k] : 0;
+      tot += x[k];
     }
-    if (i < n) v[i] = carry + s[threadIdx.x] - x;
+    int32_t inc = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int32_t y = __shfl_up(inc, o, 64);
+      if (lane >= o) inc += y;
+    }
+    if (lane == 63) wsum[w] = inc;
     __syncthreads();
-    if (threadIdx.x == 1023) carry += s[1023];
-    __syncthreads();
+    int32_t before = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) {
+      const int32_t s = wsum[k];
+      before += k < w ? s : 0;
+      all += s;
+    }
+    int32_t run = carry + before + inc - tot;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      if (i0 + k < n) v[i0 + k] = run;
+      run += x[k];
+    }
+    carry += all;
+    __syncthreads();  // wsum is rewritten in the next round
   }
 }
 
