@@ -969,19 +969,28 @@ class Server {
           ++i;
         }
       }
-      // Each request contributes a chunk of its work blocks (kBlock * qpl
-      // queries each, from next_blk on): first one block for every runnable
-      // request (admission order), then the rest of a quantum of pairs to
-      // them in the same order.  A long request is thus spread over several
-      // launches, and a request that arrives meanwhile joins the next launch
-      // on either slot, waiting about one quantum.  One exception keeps long
-      // requests fast when the device is not contended: if the first
-      // runnable request alone exceeds the quantum and the other slot does
-      // not hold such a launch, it runs whole, alone -- so at most one launch
-      // in flight exceeds the quantum, and the other slot keeps serving
-      // everything else a quantum at a time.
+      // Runnable requests are taken query requests first, then trace steps,
+      // each in admission order (a trace runs for many launches anyway; a
+      // query waits on each).  Each contributes a chunk of its work blocks
+      // (kBlock * qpl queries each, from next_blk on): first one block for
+      // every request in that order until a quantum of pairs is reached,
+      // then the rest of the quantum to them in the same order.  A long
+      // request is thus spread over several launches; requests beyond the
+      // quantum are left to the other slot, so both launch slots stay busy;
+      // and a request that arrives meanwhile joins the next launch on either
+      // slot, waiting about one quantum.  One exception keeps a long request
+      // fast when the device is not contended: if it is the only runnable
+      // request, exceeds the quantum and the other slot does not hold such a
+      // launch, it runs whole -- so at most one launch in flight exceeds the
+      // quantum, and a request that arrives meanwhile runs in the other
+      // slot.
       const int64_t bq = int64_t(kBlock) * multi_qpl();
       const bool other_whole = batches_[1 - slot].active && batches_[1 - slot].whole;
+      std::vector<Req*> cand;  // runnable: query requests, then trace steps
+      for (int kind : {int(PTS_REQ_EVAL), int(PTS_REQ_TRACE)})
+        for (Req* q : running_)
+          if (q->r.kind == kind && q->in_batch < 0 && !q->finalizing && q->n_active > 0) cand.push_back(q);
+      const int64_t runnable = int64_t(cand.size());
       b.whole = false;
       std::vector<int64_t> take;
       auto nblk_of = [&](const Req* q) { return (q->n_active + bq - 1) / bq; };
@@ -990,12 +999,11 @@ class Server {
                nc + chunk_comb_descs(q, q->next_blk, q->next_blk + k) <= max_comb_;
       };
       double budget = quantum_;
-      for (Req* q : running_) {
-        if (q->in_batch >= 0 || q->finalizing || q->n_active <= 0) continue;
-        if (int64_t(work.size()) >= cfg_.max_inflight) break;
+      for (Req* q : cand) {
+        if (int64_t(work.size()) >= cfg_.max_inflight || budget <= 0.0) break;
         const int64_t rem = nblk_of(q) - q->next_blk;
         const double per = double(bq) * double(q->N);
-        if (work.empty() && !other_whole && double(rem) * per > quantum_ && fits(q, rem)) {
+        if (work.empty() && runnable == 1 && !other_whole && double(rem) * per > quantum_ && fits(q, rem)) {
           work.push_back(q);
           take.push_back(rem);
           b.whole = true;
