@@ -12,10 +12,11 @@
 // requests in arrival order while fewer than max_inflight run and the
 // request's device buffers fit the arena (first fit; FIFO, so a large request
 // is never overtaken), and uploads their inputs on the upload stream.  Each
-// pass it packs all runnable work -- every admitted query request, and the
-// next step of every trace request -- into the descriptors of one packed
-// launch (pts_multi.hip) on whichever of the two launch streams is idle, so a
-// second launch runs while the first is still on the device.  When a launch's
+// pass it packs runnable work -- admitted query requests first, then the next
+// step of every trace request -- up to a quantum of pairs into the
+// descriptors of one packed launch (pts_multi.hip) on whichever of the two
+// launch streams is idle, so a second launch runs while the first is still on
+// the device (launch_batch has the rules).  When a launch's
 // end event has fired: query requests copy their results out and finish;
 // trace requests take their new active-ray count and are packed again, or,
 // once every ray has stopped or the step budget is spent, finish on the
