@@ -397,7 +397,7 @@ int pts_trace_ws_bytes(int64_t N, int64_t R, const pts_params* prm, size_t* out_
  * budget ran out), normal_out [R,3] float32 or NULL (grad phi / |grad phi| at
  * hits, 0 elsewhere).  Each step evaluates the active rays with the pts_eval
  * kernels.  The point splits depend on N only -- the march uses the largest
- * power of two <= 16 that leaves every split two 512-point tiles
+ * power of two <= 64 that leaves every split two 512-point tiles
  * (pts_params.splits > 0 sets it), the normals at most 8 of them -- so a ray's
  * result does not depend on the other rays.  Blocks: it reads back the active-ray count after
  * every step.  phi overestimates |distance| away from the surface for finite
@@ -476,10 +476,10 @@ int pts_eval_radius(const void* rec, int64_t N, const float* x, int64_t Q, float
  * pts_eval's automatic plan for (N, Q) -- or, if one launch of max_batch_work
  * workgroups cannot hold it, with the largest power-of-two split <= 64 that
  * fits -- and a trace request with the point split pts_server_cloud_plan
- * reports, a function of N only (the march split of pts_trace, capped at 64
- * splits instead of 16).  Results are bitwise the same alone or in any mix,
- * and equal pts_eval (default splits, or the fitting split) and pts_trace
- * (pts_params.splits set to the cloud's split) with the same C, kfloor_rel.
+ * reports, a function of N only (the march split of pts_trace).  Results are
+ * bitwise the same alone or in any mix, and equal pts_eval (default splits,
+ * or the fitting split) and pts_trace (default splits) with the same C,
+ * kfloor_rel.
  *
  * All device memory (records, request buffers, launch descriptors) comes from
  * one allocation of hbm_budget_bytes made at creation; that is the budget

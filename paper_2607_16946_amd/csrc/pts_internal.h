@@ -267,11 +267,11 @@ int launch_backward(const void* rec, int64_t N, const float* p, const float* n, 
 
 // Sphere tracing (point splits fixed by N so that rays do not affect each other).
 // The march's split: the largest power of two <= cap leaving each split two
-// 512-point tiles.  The server uses cap 64 (many small packed requests need
-// the parallelism); pts_trace uses 16 (a large ray set sweeps fastest with few
-// long splits: 16 splits cost the 2^20-point sweep 3%, 64 cost it 10%).
-constexpr int kServerSplitCap = 64;
-constexpr int kTraceSplitCap = 16;
+// 512-point tiles; pts_trace and the server both cap it at 64.  With the
+// blend's split-major order a full-ray sweep costs the same at 16 or 64
+// splits, and the late steps, with few rays still marching, need the
+// parallelism (a walk of one split is their latency).
+constexpr int kMarchSplitCap = 64;
 int march_splits(int64_t N, int cap);
 Plan march_plan(int64_t N, int64_t Q, const pts_params& P, int cap);
 Plan normal_plan(int64_t N, int64_t Q, const pts_params& P);

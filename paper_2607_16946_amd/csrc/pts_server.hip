@@ -161,7 +161,7 @@ ReqLayout req_layout(int kind, int64_t n, const Plan& plan, const pts_params& P,
     L.xq = take(size_t(n) * 12);
     L.phi = take(size_t(n) * 4);
     L.g = take(size_t(n) * 12);
-    L.nws = take(trace_eval_ws_bytes(N, n, P, kServerSplitCap));
+    L.nws = take(trace_eval_ws_bytes(N, n, P, kMarchSplitCap));
   }
   L.total = w;
   return L;
@@ -339,7 +339,7 @@ class Server {
     auto it = clouds_.find(id);
     if (it == clouds_.end()) return fail(PTS_ENOTFOUND, "unknown cloud");
     if (N) *N = it->second.N;
-    if (splits) *splits = march_splits(it->second.N, kServerSplitCap);
+    if (splits) *splits = march_splits(it->second.N, kMarchSplitCap);
     return PTS_OK;
   }
 
@@ -396,7 +396,7 @@ class Server {
           q->plan = make_plan(c.N, n, &F);
         }
       } else {
-        q->plan = march_plan(c.N, n, P_, kServerSplitCap);
+        q->plan = march_plan(c.N, n, P_, kMarchSplitCap);
       }
       if (!fits(q->plan)) {
         std::lock_guard<std::mutex> lk(mu_);

@@ -204,7 +204,7 @@ Plan march_plan(int64_t N, int64_t Q, const pts_params& P, int cap) {
 // workspace grows by 32 bytes per ray and split); also a function of N only.
 Plan normal_plan(int64_t N, int64_t Q, const pts_params& P) {
   pts_params F = P;
-  F.splits = std::min(F.splits > 0 ? F.splits : march_splits(N, kServerSplitCap), 8);
+  F.splits = std::min(F.splits > 0 ? F.splits : march_splits(N, kMarchSplitCap), 8);
   return make_plan(N, Q, &F);
 }
 
@@ -213,7 +213,7 @@ size_t trace_eval_ws_bytes(int64_t N, int64_t R, const pts_params& P, int cap) {
 }
 
 size_t trace_ws_bytes(int64_t N, int64_t R, const pts_params& P) {
-  return trace_fixed_bytes(R) + trace_eval_ws_bytes(N, R, P, kTraceSplitCap);
+  return trace_fixed_bytes(R) + trace_eval_ws_bytes(N, R, P, kMarchSplitCap);
 }
 
 int launch_trace(const void* rec, int64_t N, const float* org, const float* dir, int64_t R, int steps, float eps,
@@ -226,7 +226,7 @@ int launch_trace(const void* rec, int64_t N, const float* org, const float* dir,
   int32_t* nxt = v.act1;
   int64_t na = R;
   for (int k = 0; k < steps && na > 0; ++k) {
-    const Plan plan = march_plan(N, na, P, kTraceSplitCap);
+    const Plan plan = march_plan(N, na, P, kMarchSplitCap);
     const WsView wv = ws_view(plan, na, v.eval);
     hipLaunchKernelGGL(k_positions, dim3(nblk(na)), dim3(kBlock), 0, st, act, na, org, dir, t, v.xq);
     if (int rc = launch_eval_plain(rec, N, v.xq, na, P.C, plan, wv, v.phi, st, P.offset)) return rc;
