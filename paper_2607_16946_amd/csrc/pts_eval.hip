@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_blend(const Header* __restrict__ h, 
                                                   const float* __restrict__ x, int64_t Q, int S, int64_t per_split,
                                                   const float* __restrict__ far2, int far_rows, float C2, float S2,
                                                   float2* __restrict__ part) {
-  __shared__ float4 tile[kTile2 * kRecF4];
+  __shared__ float4 tile[kTileBlend * kRecF4];
   int split;
   int64_t qb;
   if constexpr (kMajor) {
@@ -187,8 +187,8 @@ __global__ __launch_bounds__(kBlock) void k_blend(const Header* __restrict__ h, 
   const float c2 = S2;
   const int64_t beg = int64_t(split) * per_split;
   const int64_t end = min(N, beg + per_split);
-  for (int64_t t0 = beg; t0 < end; t0 += kTile2) {
-    const int cnt = int(min<int64_t>(kTile2, end - t0));
+  for (int64_t t0 = beg; t0 < end; t0 += kTileBlend) {
+    const int cnt = int(min<int64_t>(kTileBlend, end - t0));
     __syncthreads();
     for (int j = threadIdx.x; j < cnt * kRecF4; j += kBlock) tile[j] = rec[t0 * kRecF4 + j];
     __syncthreads();

@@ -15,7 +15,11 @@ namespace pts {
 constexpr uint32_t kMagic = 0x31535450u;  // "PTS1"
 constexpr int kRecordVersion = 3;
 constexpr int kBlock = 256;               // threads per workgroup (4 waves of 64)
-constexpr int kTile2 = 128;               // points per LDS tile, blend pass (80 B each)
+constexpr int kTile2 = 128;               // points per LDS tile of the derivative sweeps (80 B each)
+// Points per LDS tile of the blend (k_blend, and k_blend_multi, which must sum
+// in the same order): 20 KB, half the barriers of 128 (0.6% on the blend; the
+// query-gradient sweep lost 3% with it, so it keeps kTile2).
+constexpr int kTileBlend = 256;
 constexpr int kTile1 = 512;               // points per LDS tile, farthest-point pass (16 B each)
 constexpr int kRecF4 = 5;                 // float4 per point record
 constexpr float kLog2e = 1.4426950408889634f;

@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kBlock) void k_far_multi(const WorkDesc* __restrict
 }
 
 __global__ __launch_bounds__(kBlock) void k_blend_multi(const WorkDesc* __restrict__ descs, float C2, float S2) {
-  __shared__ float4 tile[kTile2 * kRecF4];
+  __shared__ float4 tile[kTileBlend * kRecF4];
   const WorkDesc d = descs[blockIdx.x];
   const Header* h = reinterpret_cast<const Header*>(d.rec);
   const float4* rec = reinterpret_cast<const float4*>(d.rec + d.rec_off);
@@ -83,8 +83,8 @@ __global__ __launch_bounds__(kBlock) void k_blend_multi(const WorkDesc* __restri
   }
   const int64_t beg = int64_t(d.split) * d.per_split;
   const int64_t end = min(N, beg + d.per_split);
-  for (int64_t t0 = beg; t0 < end; t0 += kTile2) {
-    const int cnt = int(min<int64_t>(kTile2, end - t0));
+  for (int64_t t0 = beg; t0 < end; t0 += kTileBlend) {
+    const int cnt = int(min<int64_t>(kTileBlend, end - t0));
     __syncthreads();
     for (int j = threadIdx.x; j < cnt * kRecF4; j += kBlock) tile[j] = rec[t0 * kRecF4 + j];
     __syncthreads();
