@@ -175,15 +175,24 @@ __global__ __launch_bounds__(kBlock) void k_flags(const float* __restrict__ p, c
   if (threadIdx.x == 0) blk[blockIdx.x] = cnt;
 }
 
+// Radix sort blocks: kSortPer chunks of kBlock keys (1024 keys), so that the
+// digit-major histogram the scan walks has 16 entries per 1024 keys.
+constexpr int kSortPer = 4;
+constexpr int64_t kSortBlock = int64_t(kBlock) * kSortPer;
+
 // Radix sort, pass histogram: counts of the 4-bit digit at `shift` in each
-// block of kBlock keys, digit-major: hist[d * nb + block].
+// block of kSortBlock keys, digit-major: hist[d * nb + block].
 __global__ __launch_bounds__(kBlock) void k_rhist(const uint32_t* __restrict__ key, int64_t N, int shift,
                                                   int32_t* __restrict__ hist, int64_t nb) {
   __shared__ int32_t cnt[1 << kSortBits];
   if (threadIdx.x < (1 << kSortBits)) cnt[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (i < N) atomicAdd(&cnt[(key[i] >> shift) & ((1u << kSortBits) - 1)], 1);
+  const int64_t b0 = int64_t(blockIdx.x) * kSortBlock;
+#pragma unroll
+  for (int j = 0; j < kSortPer; ++j) {
+    const int64_t i = b0 + int64_t(j) * kBlock + threadIdx.x;
+    if (i < N) atomicAdd(&cnt[(key[i] >> shift) & ((1u << kSortBits) - 1)], 1);
+  }
   __syncthreads();
   if (threadIdx.x < (1 << kSortBits)) hist[int64_t(threadIdx.x) * nb + blockIdx.x] = cnt[threadIdx.x];
 }
@@ -233,31 +242,48 @@ __global__ __launch_bounds__(1024) void k_exscan(int32_t* __restrict__ v, int64_
 }
 
 // Radix sort, pass scatter: each key goes to its digit's offset for its block
-// plus its rank among the block's keys with the same digit (stable).
+// plus its rank among the block's keys with the same digit (stable): the
+// block's chunks are taken in index order, a key's rank counting the equal
+// digits of the earlier chunks, of the earlier waves of its chunk and of the
+// earlier lanes of its wave.
 __global__ __launch_bounds__(kBlock) void k_rscatter(const uint32_t* __restrict__ kin, const int32_t* __restrict__ iin,
                                                      uint32_t* __restrict__ kout, int32_t* __restrict__ iout,
                                                      int64_t N, int shift, const int32_t* __restrict__ hist,
                                                      int64_t nb) {
   constexpr int kD = 1 << kSortBits;
   __shared__ int32_t wc[kBlock / 64][kD];
-  const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  const bool valid = i < N;
-  const uint32_t k = valid ? kin[i] : 0u;
-  const int d = valid ? int((k >> shift) & (kD - 1)) : kD;
+  __shared__ int32_t seen[kD];  // digits in the block's earlier chunks
+  if (threadIdx.x < kD) seen[threadIdx.x] = 0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  int rank = 0;
-  for (int v = 0; v < kD; ++v) {
-    const uint64_t m = __ballot(d == v);
-    if (lane == 0) wc[wave][v] = __popcll(m);
-    if (d == v) rank = __popcll(m & lt);
+  const int64_t b0 = int64_t(blockIdx.x) * kSortBlock;
+  for (int j = 0; j < kSortPer; ++j) {
+    const int64_t i = b0 + int64_t(j) * kBlock + threadIdx.x;
+    const bool valid = i < N;
+    const uint32_t k = valid ? kin[i] : 0u;
+    const int d = valid ? int((k >> shift) & (kD - 1)) : kD;
+    int rank = 0;
+    for (int v = 0; v < kD; ++v) {
+      const uint64_t m = __ballot(d == v);
+      if (lane == 0) wc[wave][v] = __popcll(m);
+      if (d == v) rank = __popcll(m & lt);
+    }
+    __syncthreads();  // wc of this chunk, and seen from the chunks before it
+    if (valid) {
+      rank += seen[d];
+      for (int w = 0; w < wave; ++w) rank += wc[w][d];
+      const int64_t dst = int64_t(hist[int64_t(d) * nb + blockIdx.x]) + rank;
+      kout[dst] = k;
+      iout[dst] = iin[i];
+    }
+    __syncthreads();  // every read of seen and wc is done
+    if (threadIdx.x < kD) {
+      int32_t add = 0;
+      for (int w = 0; w < kBlock / 64; ++w) add += wc[w][threadIdx.x];
+      seen[threadIdx.x] += add;
+    }
+    __syncthreads();  // seen updated before the next chunk reads it; wc free
   }
-  __syncthreads();
-  if (!valid) return;
-  for (int w = 0; w < wave; ++w) rank += wc[w][d];
-  const int64_t dst = int64_t(hist[int64_t(d) * nb + blockIdx.x]) + rank;
-  kout[dst] = k;
-  iout[dst] = iin[i];
 }
 
 // Exclusive scan of nb block counts in place into blk[nb + b]; header totals.
@@ -414,7 +440,7 @@ __global__ __launch_bounds__(kBlock) void k_decode(const Header* __restrict__ h,
 
 int launch_radix_sort(uint32_t* key[2], int32_t* idx[2], int64_t n, int passes, int32_t* rhist, hipStream_t st,
                       int* out) {
-  const unsigned nb = unsigned((n + kBlock - 1) / kBlock);
+  const unsigned nb = unsigned((n + kSortBlock - 1) / kSortBlock);  // callers size rhist for kBlock-key blocks
   int cur = 0;
   for (int pass = 0; pass < passes; ++pass) {
     const int shift = pass * kSortBits;
