@@ -40,10 +40,11 @@
 //   (radix sort of the keys, pts_build.hip)
 //   k_bwork    per query block: a work estimate (seen from the block's first
 //              query, the units whose skip bound exceeds a 1/(10 U) share of
-//              the budget eps W, W summed from the unit centres), sorted so
-//              that heavy blocks launch first and the tail of the launch is
-//              light (ordering only: a block's result does not depend on
-//              when it runs)
+//              the budget eps W, W summed from the unit centres), sorted by
+//              half-octave buckets of it so that heavy blocks launch first
+//              and the tail of the launch is light, neighbouring blocks
+//              staying together within a bucket (ordering only: a block's
+//              result does not depend on when it runs)
 //   k_bounded  the sweep: a wave votes per block of 64 units (4096 points)
 //              and, in blocks it keeps, per 64-point unit; kept units are
 //              staged and run the blend's pair arithmetic
@@ -161,7 +162,9 @@ __global__ __launch_bounds__(kWorkBlock) void k_bwork(const Header* __restrict__
     const float du = hw_exp2(fmaf(fmaxf(s - cb.w, 0.f), nl, S2));
     cnt += du * (s + cb.w + M + 2.f * A) > thr ? 1u : 0u;
   }
-  key[b] = 0xffffffu - (cnt < 0xffffffu ? cnt : 0xffffffu);   // ascending sort = heaviest first
+  // half-octave buckets of the estimate, heaviest first; the sort is stable
+  // and bricks come in Morton order, so within a bucket they stay in it
+  key[b] = 63u - min(63u, uint32_t(2.f * log2f(float(cnt) + 1.f)));
   idx[b] = int32_t(b);
 }
 
@@ -470,7 +473,7 @@ int launch_bounded(const void* rec, int64_t N, const float* x, int64_t Q, float 
   hipLaunchKernelGGL(k_bwork, dim3(unsigned((plan.nqb + kWorkBlock - 1) / kWorkBlock)), dim3(kWorkBlock), 0, st, h, ub,
                      x, order, Q, plan.nqb, plan.qpl, v.far2, C2, S2, eps, v.bkey[0], v.bidx[0]);
   int bcur = 0;
-  if (int rc = launch_radix_sort(v.bkey, v.bidx, plan.nqb, 6, v.rhist, st, &bcur)) return rc;
+  if (int rc = launch_radix_sort(v.bkey, v.bidx, plan.nqb, 2, v.rhist, st, &bcur)) return rc;
   const int32_t* border = v.bidx[bcur];
   switch (plan.qpl) {
     case 1: launch_bounded_q<1>(h, recs, ub, bb, x, order, border, Q, plan, v.far2, C2, S2, eps, v.part, v.kpart, st); break;
