@@ -127,21 +127,33 @@ __device__ int64_t nearest_unit(const float4* __restrict__ ub, int64_t u0, int64
   return red_i[0];
 }
 
+// The queries in Morton order: the sweeps below read them, and M, by sorted
+// position.
+__global__ __launch_bounds__(kBlock) void k_gather(const float* __restrict__ x, const int32_t* __restrict__ order,
+                                                   int64_t Q, float* __restrict__ xs) {
+  const int64_t j = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (j >= Q) return;
+  const int64_t q = order[j];
+  xs[3 * j] = x[3 * q];
+  xs[3 * j + 1] = x[3 * q + 1];
+  xs[3 * j + 2] = x[3 * q + 2];
+}
+
 // Threads per workgroup of k_bwork: small, so its few thousand threads spread
 // over every compute unit.
 constexpr int kWorkBlock = 64;
 
 __global__ __launch_bounds__(kWorkBlock) void k_bwork(const Header* __restrict__ h, const float4* __restrict__ ub,
-                                                      const float* __restrict__ x, const int32_t* __restrict__ order,
+                                                      const float* __restrict__ xs,
                                                       int64_t Q, int64_t nqb, int qpl, const float* __restrict__ far2,
                                                       float C2, float S2, float eps, uint32_t* __restrict__ key,
                                                       int32_t* __restrict__ idx) {
   const int64_t b = int64_t(blockIdx.x) * kWorkBlock + threadIdx.x;
   if (b >= nqb) return;
-  const int64_t q = order[b * kBW * qpl];
-  const QueryIn r = load_query(x, q, Q, h);
+  const int64_t j = b * kBW * qpl;  // the block's first sorted position
+  const QueryIn r = load_query(xs, j, Q, h);
   float M = 0.f, nl = 0.f;
-  far_of(far2, 1, Q, q, C2, M, nl);
+  far_of(far2, 1, Q, j, C2, M, nl);
   const float A = __uint_as_float(h->a00max_bits);
   const int64_t nunit = (h->N + kUnit - 1) / kUnit;
   // W from the unit centres, then the units whose skip bound (as the vote
@@ -199,8 +211,7 @@ template <int QPL>
 // 8 waves per SIMD (at most 64 VGPRs)
 __global__ __launch_bounds__(kBW, 8) void k_bounded(const Header* __restrict__ h, const float4* __restrict__ rec,
                                                  const float4* __restrict__ ub, const float4* __restrict__ bb,
-                                                 const float* __restrict__ x,
-                                                 const int32_t* __restrict__ order, const int32_t* __restrict__ border,
+                                                 const float* __restrict__ xs, const int32_t* __restrict__ border,
                                                  int64_t Q, int S, int64_t per_split,
                                                  const float* __restrict__ far2, float C2, float S2, float eps_total,
                                                  float4* __restrict__ part, int32_t* __restrict__ kpart) {
@@ -222,12 +233,11 @@ __global__ __launch_bounds__(kBW, 8) void k_bounded(const Header* __restrict__ h
   for (int k = 0; k < QPL; ++k) {
     const int64_t j = j0 + int64_t(threadIdx.x) * QPL + k;
     live[k] = j < Q;
-    const int64_t q = live[k] ? order[j] : 0;
-    const QueryIn qi = load_query(x, q, live[k] ? Q : 0, h);
+    const QueryIn qi = load_query(xs, j, live[k] ? Q : 0, h);
     qx[k] = qi.x; qy[k] = qi.y; qz[k] = qi.z;
     float M = 0.f;
     nl[k] = 0.f;
-    if (qi.valid) far_of(far2, 1, Q, q, C2, M, nl[k]);
+    if (qi.valid) far_of(far2, 1, Q, j, C2, M, nl[k]);
     phimax[k] = M + A;
     num[k] = den[k] = gs[k] = ds[k] = wseed[k] = 0.f;
   }
@@ -236,7 +246,7 @@ __global__ __launch_bounds__(kBW, 8) void k_bounded(const Header* __restrict__ h
   const int64_t u_beg = beg / kUnit, u_end = (end + kUnit - 1) / kUnit;
   const float eps = S > 1 ? eps_total / float(S + 1) : eps_total;
   // the wave's first query, in record coordinates
-  const QueryIn r0 = load_query(x, order[j0], Q, h);
+  const QueryIn r0 = load_query(xs, j0, Q, h);
   const int64_t useed = nearest_unit(ub, 0, (N + kUnit - 1) / kUnit, r0.x, r0.y, r0.z, red_v, red_i);
   int64_t ustart = useed;
   if (useed < u_beg || useed >= u_end) {
@@ -375,17 +385,18 @@ __global__ __launch_bounds__(kBlock) void k_bcombine(const float4* __restrict__ 
 }
 
 template <int QPL>
-void launch_bounded_q(const Header* h, const float4* rec, const float4* ub, const float4* bb, const float* x,
-                      const int32_t* order, const int32_t* border, int64_t Q, const Plan& plan, const float* far2,
+void launch_bounded_q(const Header* h, const float4* rec, const float4* ub, const float4* bb, const float* xs,
+                      const int32_t* border, int64_t Q, const Plan& plan, const float* far2,
                       float C2, float S2, float eps, float4* part, int32_t* kpart, hipStream_t st) {
-  hipLaunchKernelGGL(k_bounded<QPL>, dim3(unsigned(plan.nqb * plan.S)), dim3(kBW), 0, st, h, rec, ub, bb, x, order,
+  hipLaunchKernelGGL(k_bounded<QPL>, dim3(unsigned(plan.nqb * plan.S)), dim3(kBW), 0, st, h, rec, ub, bb, xs,
                      border, Q, plan.S, plan.per_split, far2, C2, S2, eps, part, kpart);
 }
 
 // Workspace: far2 [Q], partials float4 [S][Q], kept int32 [S][Q], keys and
 // indices [2][Q] each, radix histograms.
 struct BoundedWs {
-  float* far2;
+  float* xs;    // the queries in Morton order [Q][3]
+  float* far2;  // M^2 per sorted position
   float4* part;
   int32_t* kpart;
   uint32_t* key[2];
@@ -425,6 +436,7 @@ BoundedWs bounded_ws(const Plan& plan, int64_t Q, void* ws) {
     o += align256(b);
     return r;
   };
+  v.xs = reinterpret_cast<float*>(take(size_t(Q) * 12));
   v.far2 = reinterpret_cast<float*>(take(size_t(Q) * 4));
   v.part = reinterpret_cast<float4*>(take(size_t(plan.S) * size_t(Q) * 16));
   v.kpart = reinterpret_cast<int32_t*>(take(size_t(plan.S) * size_t(Q) * 4));
@@ -465,20 +477,22 @@ int launch_bounded(const void* rec, int64_t N, const float* x, int64_t Q, float 
   const unsigned qblocks = unsigned((Q + kBlock - 1) / kBlock);
   const int32_t* order = nullptr;
   if (int rc = launch_query_order(rec, x, Q, v.key, v.idx, v.rhist, st, &order)) return rc;
-  // M at up to 4 queries per lane (exact in any order: the sweep's own plan
-  // has one)
-  if (int rc = launch_far_cull(rec, N, x, Q, 4, v.far2, nullptr, st)) return rc;
+  hipLaunchKernelGGL(k_gather, dim3(qblocks), dim3(kBlock), 0, st, x, order, Q, v.xs);
+  // M of the sorted queries at up to 4 per lane (exact in any order; the
+  // compact Morton blocks let the culling skip more units than the input's
+  // order would)
+  if (int rc = launch_far_cull(rec, N, v.xs, Q, 4, v.far2, nullptr, st)) return rc;
   // heavy query blocks first
   const float C2 = C * kLog2e, S2 = shift2_of(C);
   hipLaunchKernelGGL(k_bwork, dim3(unsigned((plan.nqb + kWorkBlock - 1) / kWorkBlock)), dim3(kWorkBlock), 0, st, h, ub,
-                     x, order, Q, plan.nqb, plan.qpl, v.far2, C2, S2, eps, v.bkey[0], v.bidx[0]);
+                     v.xs, Q, plan.nqb, plan.qpl, v.far2, C2, S2, eps, v.bkey[0], v.bidx[0]);
   int bcur = 0;
   if (int rc = launch_radix_sort(v.bkey, v.bidx, plan.nqb, 2, v.rhist, st, &bcur)) return rc;
   const int32_t* border = v.bidx[bcur];
   switch (plan.qpl) {
-    case 1: launch_bounded_q<1>(h, recs, ub, bb, x, order, border, Q, plan, v.far2, C2, S2, eps, v.part, v.kpart, st); break;
-    case 2: launch_bounded_q<2>(h, recs, ub, bb, x, order, border, Q, plan, v.far2, C2, S2, eps, v.part, v.kpart, st); break;
-    default: launch_bounded_q<4>(h, recs, ub, bb, x, order, border, Q, plan, v.far2, C2, S2, eps, v.part, v.kpart, st); break;
+    case 1: launch_bounded_q<1>(h, recs, ub, bb, v.xs, border, Q, plan, v.far2, C2, S2, eps, v.part, v.kpart, st); break;
+    case 2: launch_bounded_q<2>(h, recs, ub, bb, v.xs, border, Q, plan, v.far2, C2, S2, eps, v.part, v.kpart, st); break;
+    default: launch_bounded_q<4>(h, recs, ub, bb, v.xs, border, Q, plan, v.far2, C2, S2, eps, v.part, v.kpart, st); break;
   }
   hipLaunchKernelGGL(k_bcombine, dim3(qblocks), dim3(kBlock), 0, st, v.part, v.kpart, order, plan.S, Q, sdf, bound,
                      kept, offset);
