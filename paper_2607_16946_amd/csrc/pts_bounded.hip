@@ -40,7 +40,8 @@
 //   (radix sort of the keys, pts_build.hip)
 //   k_bwork    per query block: a work estimate (seen from the block's first
 //              query, the units whose skip bound exceeds a 1/(10 U) share of
-//              the budget eps W, W summed from the unit centres), sorted by
+//              the budget eps W, W summed from the unit centres; both sums
+//              over every fourth unit, scaled up), sorted by
 //              half-octave buckets of it so that heavy blocks launch first
 //              and the tail of the launch is light, neighbouring blocks
 //              staying together within a bucket (ordering only: a block's
@@ -142,6 +143,10 @@ __global__ __launch_bounds__(kBlock) void k_gather(const float* __restrict__ x, 
 // Threads per workgroup of k_bwork: small, so its few thousand threads spread
 // over every compute unit.
 constexpr int kWorkBlock = 64;
+// k_bwork looks at every kWorkStride-th unit and scales the sums back up: the
+// estimate only orders the blocks, and a quarter of the units orders them as
+// well as all of them.
+constexpr int kWorkStride = 4;
 
 __global__ __launch_bounds__(kWorkBlock) void k_bwork(const Header* __restrict__ h, const float4* __restrict__ ub,
                                                       const float* __restrict__ xs,
@@ -158,16 +163,16 @@ __global__ __launch_bounds__(kWorkBlock) void k_bwork(const Header* __restrict__
   const int64_t nunit = (h->N + kUnit - 1) / kUnit;
   // W from the unit centres, then the units whose skip bound (as the vote
   // prices it) exceeds a share eps W / (10 U) of the budget: those the sweep
-  // must evaluate, about
+  // must evaluate, about; both over every kWorkStride-th unit
   float W = 0.f;
-  for (int64_t u = 0; u < nunit; ++u) {
+  for (int64_t u = 0; u < nunit; u += kWorkStride) {
     const float4 cb = ub[2 * u];
     const float ex = r.x - cb.x, ey = r.y - cb.y, ez = r.z - cb.z;
     W += hw_exp2(fmaf(hw_sqrt(fmaf(ez, ez, fmaf(ey, ey, ex * ex))), nl, S2));
   }
-  const float thr = eps * W / (10.f * float(nunit));
+  const float thr = eps * (float(kWorkStride) * W) / (10.f * float(nunit));
   uint32_t cnt = 0;
-  for (int64_t u = 0; u < nunit; ++u) {
+  for (int64_t u = 0; u < nunit; u += kWorkStride) {
     const float4 cb = ub[2 * u];
     const float ex = r.x - cb.x, ey = r.y - cb.y, ez = r.z - cb.z;
     const float s = hw_sqrt(fmaf(ez, ez, fmaf(ey, ey, ex * ex)));
@@ -176,7 +181,7 @@ __global__ __launch_bounds__(kWorkBlock) void k_bwork(const Header* __restrict__
   }
   // half-octave buckets of the estimate, heaviest first; the sort is stable
   // and bricks come in Morton order, so within a bucket they stay in it
-  key[b] = 63u - min(63u, uint32_t(2.f * log2f(float(cnt) + 1.f)));
+  key[b] = 63u - min(63u, uint32_t(2.f * log2f(float(kWorkStride * cnt) + 1.f)));
   idx[b] = int32_t(b);
 }
 
