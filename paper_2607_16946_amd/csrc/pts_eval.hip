@@ -35,19 +35,21 @@ namespace {
 //   (three FMAs and a max per pair) and |x|^2 is added once at the end.
 // Exact culling by units of kUnit consecutive slots (spatially sorted at
 // build time, with bounding spheres and extreme points; pts_farcull.h), the
-// lower bound here from every unit's extreme point, so M^2 (and, with kArg,
-// the first slot attaining it) is exactly what a sweep over every point gives.
+// units reached through the blocks of kBlkU units and the lower bound equal to
+// the one over every unit's extreme point, so M^2 (and, with kArg, the first
+// slot attaining it) is exactly what a sweep over every point gives.
 // ---------------------------------------------------------------------------
 template <int QPL, bool kArg>
 __global__ __launch_bounds__(kBlock) void k_far_cull(const Header* __restrict__ h, const float4* __restrict__ pos4,
-                                                     const float4* __restrict__ ub, const float* __restrict__ x,
-                                                     int64_t Q, float* __restrict__ far2,
-                                                     int32_t* __restrict__ farix) {
+                                                     const float4* __restrict__ ub, const float4* __restrict__ bb,
+                                                     const float* __restrict__ x, int64_t Q,
+                                                     float* __restrict__ far2, int32_t* __restrict__ farix) {
   __shared__ FarLds L;
+  __shared__ FarBlkLds B;
   const int64_t N = h->N;
   const int64_t U = (N + kUnit - 1) / kUnit;
   const int64_t qb = blockIdx.x;
-  float qx[QPL], qy[QPL], qz[QPL], acc[QPL], lb[QPL];
+  float qx[QPL], qy[QPL], qz[QPL], acc[QPL];
   int32_t ix[QPL];
   bool ok[QPL];
 #pragma unroll
@@ -57,12 +59,8 @@ __global__ __launch_bounds__(kBlock) void k_far_cull(const Header* __restrict__ 
     ok[k] = qi.valid;
     acc[k] = -3.0e38f;
     ix[k] = -1;
-    lb[k] = -1.f;
   }
-  // 1. lower bound from every unit's extreme point; 2./3. the units that can reach it
-  far_bound<QPL>(ub, U, [](int64_t i) { return i; }, qx, qy, qz, lb, L);
-  far_threshold<QPL>(lb, ok);
-  far_sweep<QPL, kArg>(pos4, ub, 0, U, N, qx, qy, qz, ok, lb, acc, ix, L);
+  far_tree<QPL, kArg>(pos4, ub, bb, U, N, qx, qy, qz, ok, acc, ix, L, B);
 #pragma unroll
   for (int k = 0; k < QPL; ++k) {
     const int64_t q = qb * (kBlock * QPL) + k * kBlock + threadIdx.x;
@@ -254,7 +252,8 @@ __global__ __launch_bounds__(kBlock) void k_combine_wave(const float2* __restric
 // fold = false: the split rows are left for the blend to take the maximum of
 // (worth it for a few rows only: every blend workgroup of a query reads them).
 template <int QPL, bool kArg>
-void launch_far_q(const Header* h, const float4* pos4, const float4* ub, const float* x, int64_t Q, int64_t nqb,
+void launch_far_q(const Header* h, const float4* pos4, const float4* ub, const float4* bb, const float* x,
+                  int64_t Q, int64_t nqb,
                   int S, int64_t per_split, float* far2, int32_t* farix, hipStream_t st, bool fold) {
   if (S > 1) {
     hipLaunchKernelGGL((k_far_split<QPL, kArg>), dim3(unsigned(nqb * S)), dim3(kBlock), 0, st, h, pos4, ub, x, Q, S,
@@ -266,8 +265,8 @@ void launch_far_q(const Header* h, const float4* pos4, const float4* ub, const f
       hipLaunchKernelGGL(k_far_fold_wave, dim3(unsigned((Q + kBlock / 64 - 1) / (kBlock / 64))), dim3(kBlock), 0, st,
                          far2, S, Q);
   } else {
-    hipLaunchKernelGGL((k_far_cull<QPL, kArg>), dim3(unsigned(nqb)), dim3(kBlock), 0, st, h, pos4, ub, x, Q, far2,
-                       farix);
+    hipLaunchKernelGGL((k_far_cull<QPL, kArg>), dim3(unsigned(nqb)), dim3(kBlock), 0, st, h, pos4, ub, bb, x, Q,
+                       far2, farix);
   }
 }
 
@@ -334,6 +333,7 @@ int launch_far_cull(const void* rec, int64_t N, const float* x, int64_t Q, int q
   const Header* h = reinterpret_cast<const Header*>(base);
   const float4* pos4 = reinterpret_cast<const float4*>(base + L.pos);
   const float4* ub = reinterpret_cast<const float4*>(base + L.ub);
+  const float4* bb = reinterpret_cast<const float4*>(base + L.bb);
   // one workgroup per query block: keep at least 2048 of them (8 per CU) when
   // there are queries enough, by lowering the queries per lane; with fewer
   // than 1024 query blocks, sweep the point splits as separate workgroups (the
@@ -341,15 +341,15 @@ int launch_far_cull(const void* rec, int64_t N, const float* x, int64_t Q, int q
   const FarShape f = far_shape(qpl, Q, S, per_split);
   if (farix) {
     switch (f.q) {
-      case 1: launch_far_q<1, true>(h, pos4, ub, x, Q, f.nqb, f.S, per_split, far2, farix, st, true); break;
-      case 2: launch_far_q<2, true>(h, pos4, ub, x, Q, f.nqb, f.S, per_split, far2, farix, st, true); break;
-      default: launch_far_q<4, true>(h, pos4, ub, x, Q, f.nqb, f.S, per_split, far2, farix, st, true); break;
+      case 1: launch_far_q<1, true>(h, pos4, ub, bb, x, Q, f.nqb, f.S, per_split, far2, farix, st, true); break;
+      case 2: launch_far_q<2, true>(h, pos4, ub, bb, x, Q, f.nqb, f.S, per_split, far2, farix, st, true); break;
+      default: launch_far_q<4, true>(h, pos4, ub, bb, x, Q, f.nqb, f.S, per_split, far2, farix, st, true); break;
     }
   } else {
     switch (f.q) {
-      case 1: launch_far_q<1, false>(h, pos4, ub, x, Q, f.nqb, f.S, per_split, far2, nullptr, st, true); break;
-      case 2: launch_far_q<2, false>(h, pos4, ub, x, Q, f.nqb, f.S, per_split, far2, nullptr, st, true); break;
-      default: launch_far_q<4, false>(h, pos4, ub, x, Q, f.nqb, f.S, per_split, far2, nullptr, st, true); break;
+      case 1: launch_far_q<1, false>(h, pos4, ub, bb, x, Q, f.nqb, f.S, per_split, far2, nullptr, st, true); break;
+      case 2: launch_far_q<2, false>(h, pos4, ub, bb, x, Q, f.nqb, f.S, per_split, far2, nullptr, st, true); break;
+      default: launch_far_q<4, false>(h, pos4, ub, bb, x, Q, f.nqb, f.S, per_split, far2, nullptr, st, true); break;
     }
   }
   return check_hip(hipGetLastError(), "farthest-point kernel");
@@ -383,14 +383,15 @@ int launch_eval_plain(const void* rec, int64_t N, const float* x, int64_t Q, flo
   const Header* h = reinterpret_cast<const Header*>(base);
   const float4* pos4 = reinterpret_cast<const float4*>(base + L.pos);
   const float4* ub = reinterpret_cast<const float4*>(base + L.ub);
+  const float4* bb = reinterpret_cast<const float4*>(base + L.bb);
   const float4* recs = reinterpret_cast<const float4*>(base + L.rec);
   const FarShape f = far_shape(plan.qpl, Q, plan.S, plan.per_split);
   const bool fold = f.S > kLaneSplitsMax;
   const int rows = fold ? 1 : f.S;
   switch (f.q) {
-    case 1: launch_far_q<1, false>(h, pos4, ub, x, Q, f.nqb, f.S, plan.per_split, ws.far2, nullptr, st, fold); break;
-    case 2: launch_far_q<2, false>(h, pos4, ub, x, Q, f.nqb, f.S, plan.per_split, ws.far2, nullptr, st, fold); break;
-    default: launch_far_q<4, false>(h, pos4, ub, x, Q, f.nqb, f.S, plan.per_split, ws.far2, nullptr, st, fold); break;
+    case 1: launch_far_q<1, false>(h, pos4, ub, bb, x, Q, f.nqb, f.S, plan.per_split, ws.far2, nullptr, st, fold); break;
+    case 2: launch_far_q<2, false>(h, pos4, ub, bb, x, Q, f.nqb, f.S, plan.per_split, ws.far2, nullptr, st, fold); break;
+    default: launch_far_q<4, false>(h, pos4, ub, bb, x, Q, f.nqb, f.S, plan.per_split, ws.far2, nullptr, st, fold); break;
   }
   if (int rc = check_hip(hipGetLastError(), "farthest-point kernel")) return rc;
   const float C2 = C * kLog2e, S2 = shift2_of(C);

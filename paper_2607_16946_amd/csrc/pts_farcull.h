@@ -74,6 +74,43 @@ __device__ __forceinline__ void far_threshold(float (&lb)[QPL], bool (&ok)[QPL])
   }
 }
 
+// The spheres sb[0, cnt) (staged in LDS, mask cleared, both behind a barrier)
+// that some query of the workgroup can reach beyond its threshold lb
+// (|x - c| + r >= lb), as the ascending list of i0 + j in list[0, *count).
+// Ends behind a barrier.
+template <int QPL>
+__device__ __forceinline__ void far_mark(const float4* sb, int cnt, int32_t i0, const float (&qx)[QPL],
+                                         const float (&qy)[QPL], const float (&qz)[QPL], const bool (&ok)[QPL],
+                                         const float (&lb)[QPL], uint32_t* mask, int32_t* list, int32_t* count) {
+  for (int j = 0; j < cnt; ++j) {
+    const float4 C = sb[j];
+    bool need = false;
+#pragma unroll
+    for (int k = 0; k < QPL; ++k) {
+      const float t = lb[k] - C.w;
+      const float dx = qx[k] - C.x, dy = qy[k] - C.y, dz = qz[k] - C.z;
+      const float dc2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+      need = need || (ok[k] && (t <= 0.f || !(dc2 < t * t)));
+    }
+    if (__ballot(need) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&mask[j >> 5], 1u << (j & 31));
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {  // ascending list (first wave)
+    const int w = int(threadIdx.x);
+    const uint32_t bits = w < kChunkU / 32 ? mask[w] : 0u;
+    const int pc = __popc(bits);
+    int incl = pc;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(incl, o);
+      if (w >= o) incl += t;
+    }
+    int pos = incl - pc;
+    for (uint32_t b = bits; b != 0u; b &= b - 1u) list[pos++] = i0 + w * 32 + (__ffs(b) - 1);
+    if (w == 63) *count = incl;
+  }
+  __syncthreads();
+}
+
 // Sweep the units of [u_lo, u_hi) that some query of the workgroup needs:
 // acc[k] = max over their points of |p|^2 - 2<x,p> (slots >= slot_end are
 // padding), and with kArg ix[k] the first slot attaining it.
@@ -89,34 +126,7 @@ __device__ __forceinline__ void far_sweep(const float4* __restrict__ pos4, const
     for (int j = threadIdx.x; j < cnt; j += kBlock) L.sb[j] = ub[2 * (c0 + j)];
     for (int j = threadIdx.x; j < kChunkU / 32; j += kBlock) L.smask[j] = 0u;
     __syncthreads();
-    // mark the needed units
-    for (int j = 0; j < cnt; ++j) {
-      const float4 C = L.sb[j];
-      bool need = false;
-#pragma unroll
-      for (int k = 0; k < QPL; ++k) {
-        const float t = lb[k] - C.w;
-        const float dx = qx[k] - C.x, dy = qy[k] - C.y, dz = qz[k] - C.z;
-        const float dc2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        need = need || (ok[k] && (t <= 0.f || !(dc2 < t * t)));
-      }
-      if (__ballot(need) != 0ull && (threadIdx.x & 63) == 0) atomicOr(&L.smask[j >> 5], 1u << (j & 31));
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {  // ascending list of the needed units (first wave)
-      const int w = int(threadIdx.x);
-      const uint32_t bits = w < kChunkU / 32 ? L.smask[w] : 0u;
-      const int pc = __popc(bits);
-      int incl = pc;
-      for (int o = 1; o < 64; o <<= 1) {
-        const int t = __shfl_up(incl, o);
-        if (w >= o) incl += t;
-      }
-      int pos = incl - pc;
-      for (uint32_t b = bits; b != 0u; b &= b - 1u) L.slist[pos++] = int32_t(c0) + w * 32 + (__ffs(b) - 1);
-      if (w == 63) L.scount = incl;
-    }
-    __syncthreads();
+    far_mark<QPL>(L.sb, cnt, int32_t(c0), qx, qy, qz, ok, lb, L.smask, L.slist, &L.scount);
     // sweep their points, a tile of kBatchU units at a time
     const int nlist = L.scount;
     for (int b0 = 0; b0 < nlist; b0 += kBatchU) {
@@ -152,6 +162,64 @@ __device__ __forceinline__ void far_sweep(const float4* __restrict__ pos4, const
             acc[k] = fmaxf(acc[k], fmaxf(a0, a1));
           }
         }
+      }
+    }
+  }
+}
+
+// The needed blocks of one chunk of block spheres (far_tree).
+struct FarBlkLds {
+  uint32_t mask[kChunkU / 32];
+  int32_t list[kChunkU];
+  int32_t count;
+};
+
+// The sweep over all U units of a cloud, through the blocks of kBlkU units
+// whose spheres bb enclose their units' spheres.  The bound starts from the
+// extreme points of kSampleU units sampled across the cloud and is raised by
+// those of every unit of each block that can reach it; the unit attaining the
+// largest extreme-point distance lies in such a block, so the bound ends equal
+// to the one over every unit.  The blocks that can reach the final threshold
+// are then swept in ascending order (far_sweep over their units); a block
+// that cannot holds no unit that could, so the maximum (and, with kArg, the
+// first slot attaining it) is that of far_sweep over [0, U).
+template <int QPL, bool kArg>
+__device__ __forceinline__ void far_tree(const float4* __restrict__ pos4, const float4* __restrict__ ub,
+                                         const float4* __restrict__ bb, int64_t U, int64_t slot_end,
+                                         const float (&qx)[QPL], const float (&qy)[QPL], const float (&qz)[QPL],
+                                         bool (&ok)[QPL], float (&acc)[QPL], int32_t (&ix)[QPL], FarLds& L,
+                                         FarBlkLds& B) {
+  const int64_t NB = (U + kBlkU - 1) / kBlkU;
+  const int64_t stride = (U + kSampleU - 1) / kSampleU;
+  float lb[QPL];
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) lb[k] = -1.f;
+  far_bound<QPL>(ub, (U + stride - 1) / stride, [=](int64_t i) { return i * stride; }, qx, qy, qz, lb, L);
+  // pass 0 raises the bound over the blocks that reach it; pass 1 sweeps the
+  // blocks that reach the final threshold
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1) far_threshold<QPL>(lb, ok);
+    for (int64_t c0 = 0; c0 < NB; c0 += kChunkU) {
+      const int cnt = int(min<int64_t>(kChunkU, NB - c0));
+      float thr[QPL];
+      bool okt[QPL];
+#pragma unroll
+      for (int k = 0; k < QPL; ++k) {
+        okt[k] = pass == 1 ? ok[k] : (ok[k] && lb[k] >= 0.f);
+        thr[k] = pass == 1 ? lb[k] : sqrtf(fmaxf(lb[k], 0.f)) * (1.f - 1e-5f);
+      }
+      __syncthreads();
+      for (int j = threadIdx.x; j < cnt; j += kBlock) L.sb[j] = bb[c0 + j];
+      for (int j = threadIdx.x; j < kChunkU / 32; j += kBlock) B.mask[j] = 0u;
+      __syncthreads();
+      far_mark<QPL>(L.sb, cnt, int32_t(c0), qx, qy, qz, okt, thr, B.mask, B.list, &B.count);
+      const int nl = B.count;
+      for (int i = 0; i < nl; ++i) {
+        const int64_t u0 = int64_t(B.list[i]) * kBlkU, u1 = min(U, u0 + kBlkU);
+        if (pass == 0)
+          far_bound<QPL>(ub, u1 - u0, [=](int64_t t) { return u0 + t; }, qx, qy, qz, lb, L);
+        else
+          far_sweep<QPL, kArg>(pos4, ub, u0, u1, slot_end, qx, qy, qz, ok, lb, acc, ix, L);
       }
     }
   }
