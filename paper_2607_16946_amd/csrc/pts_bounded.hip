@@ -212,10 +212,47 @@ __device__ __forceinline__ bool vote(const float4& sb, float n, const float* qx,
   return true;
 }
 
+// The same vote for the n points of a unit inside the oriented box B[0..3]
+// (center, then axis and half-extent per axis): with t_k = |<x - c, a_k>|,
+// every point is at least |max(t - e, 0)| and at most |t + e| from x.  The
+// lower bound gives up kSlack of the upper one for the FP32 rounding of t.
+template <int QPL>
+__device__ __forceinline__ bool vote_box(const float4* __restrict__ B, float n, const float* qx, const float* qy,
+                                         const float* qz, const float* nl, float S2, float A, const float* phimax,
+                                         float* gs, float* ds, const float* den, const float* wseed, float eps,
+                                         const bool* live) {
+  const float4 C = B[0], A0 = B[1], A1 = B[2], A2 = B[3];
+  float du[QPL], gu[QPL];
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) {
+    const float ex = qx[k] - C.x, ey = qy[k] - C.y, ez = qz[k] - C.z;
+    const float t0 = fabsf(fmaf(ez, A0.z, fmaf(ey, A0.y, ex * A0.x)));
+    const float t1 = fabsf(fmaf(ez, A1.z, fmaf(ey, A1.y, ex * A1.x)));
+    const float t2 = fabsf(fmaf(ez, A2.z, fmaf(ey, A2.y, ex * A2.x)));
+    const float l0 = fmaxf(t0 - A0.w, 0.f), l1 = fmaxf(t1 - A1.w, 0.f), l2 = fmaxf(t2 - A2.w, 0.f);
+    const float h0 = t0 + A0.w, h1 = t1 + A1.w, h2 = t2 + A2.w;
+    const float dmax = hw_sqrt(fmaf(h2, h2, fmaf(h1, h1, h0 * h0))) * (1.f + kSlack);
+    const float dmin = fmaxf(hw_sqrt(fmaf(l2, l2, fmaf(l1, l1, l0 * l0))) - kSlack * dmax, 0.f);
+    du[k] = n * hw_exp2(fmaf(dmin, nl[k], S2)) * (1.f + kSlack);
+    gu[k] = du[k] * (dmax + A) * (1.f + kSlack);
+    const bool skip = (gs[k] + gu[k]) + phimax[k] * (ds[k] + du[k]) <= eps * (den[k] * (1.f - kSlack) + wseed[k]);
+    ok = ok && (skip || !live[k]);
+  }
+  if (__ballot(!ok) != 0ull) return false;
+#pragma unroll
+  for (int k = 0; k < QPL; ++k) {
+    gs[k] += gu[k];
+    ds[k] += du[k];
+  }
+  return true;
+}
+
 template <int QPL>
 // 8 waves per SIMD (at most 64 VGPRs)
 __global__ __launch_bounds__(kBW, 8) void k_bounded(const Header* __restrict__ h, const float4* __restrict__ rec,
                                                  const float4* __restrict__ ub, const float4* __restrict__ bb,
+                                                 const float4* __restrict__ ob,
                                                  const float* __restrict__ xs, const int32_t* __restrict__ border,
                                                  int64_t Q, int S, int64_t per_split,
                                                  const float* __restrict__ far2, float C2, float S2, float eps_total,
@@ -328,7 +365,8 @@ __global__ __launch_bounds__(kBW, 8) void k_bounded(const Header* __restrict__ h
       if (u >= bu1) u -= nub;
       const int64_t t0 = u * kUnit;
       const int cnt = int(min<int64_t>(kUnit, end - t0));
-      if (vote<QPL>(ub[2 * u], float(cnt), qx, qy, qz, nl, S2, A, phimax, gs, ds, den, wseed, eps, live)) continue;
+      if (vote_box<QPL>(ob + 4 * u, float(cnt), qx, qy, qz, nl, S2, A, phimax, gs, ds, den, wseed, eps, live))
+        continue;
       kept += cnt;
       __syncthreads();                 // the previous unit is read
       for (int j = threadIdx.x; j < cnt * kRecF4; j += kBW) tile[j] = rec[t0 * kRecF4 + j];
@@ -390,10 +428,10 @@ __global__ __launch_bounds__(kBlock) void k_bcombine(const float4* __restrict__ 
 }
 
 template <int QPL>
-void launch_bounded_q(const Header* h, const float4* rec, const float4* ub, const float4* bb, const float* xs,
-                      const int32_t* border, int64_t Q, const Plan& plan, const float* far2,
+void launch_bounded_q(const Header* h, const float4* rec, const float4* ub, const float4* bb, const float4* ob,
+                      const float* xs, const int32_t* border, int64_t Q, const Plan& plan, const float* far2,
                       float C2, float S2, float eps, float4* part, int32_t* kpart, hipStream_t st) {
-  hipLaunchKernelGGL(k_bounded<QPL>, dim3(unsigned(plan.nqb * plan.S)), dim3(kBW), 0, st, h, rec, ub, bb, xs,
+  hipLaunchKernelGGL(k_bounded<QPL>, dim3(unsigned(plan.nqb * plan.S)), dim3(kBW), 0, st, h, rec, ub, bb, ob, xs,
                      border, Q, plan.S, plan.per_split, far2, C2, S2, eps, part, kpart);
 }
 
@@ -478,6 +516,7 @@ int launch_bounded(const void* rec, int64_t N, const float* x, int64_t Q, float 
   const float4* recs = reinterpret_cast<const float4*>(base + L.rec);
   const float4* ub = reinterpret_cast<const float4*>(base + L.ub);
   const float4* bb = reinterpret_cast<const float4*>(base + L.bb);
+  const float4* ob = reinterpret_cast<const float4*>(base + L.ob);
   BoundedWs v = bounded_ws(plan, Q, ws);
   const unsigned qblocks = unsigned((Q + kBlock - 1) / kBlock);
   const int32_t* order = nullptr;
@@ -495,9 +534,9 @@ int launch_bounded(const void* rec, int64_t N, const float* x, int64_t Q, float 
   if (int rc = launch_radix_sort(v.bkey, v.bidx, plan.nqb, 2, v.rhist, st, &bcur)) return rc;
   const int32_t* border = v.bidx[bcur];
   switch (plan.qpl) {
-    case 1: launch_bounded_q<1>(h, recs, ub, bb, v.xs, border, Q, plan, v.far2, C2, S2, eps, v.part, v.kpart, st); break;
-    case 2: launch_bounded_q<2>(h, recs, ub, bb, v.xs, border, Q, plan, v.far2, C2, S2, eps, v.part, v.kpart, st); break;
-    default: launch_bounded_q<4>(h, recs, ub, bb, v.xs, border, Q, plan, v.far2, C2, S2, eps, v.part, v.kpart, st); break;
+    case 1: launch_bounded_q<1>(h, recs, ub, bb, ob, v.xs, border, Q, plan, v.far2, C2, S2, eps, v.part, v.kpart, st); break;
+    case 2: launch_bounded_q<2>(h, recs, ub, bb, ob, v.xs, border, Q, plan, v.far2, C2, S2, eps, v.part, v.kpart, st); break;
+    default: launch_bounded_q<4>(h, recs, ub, bb, ob, v.xs, border, Q, plan, v.far2, C2, S2, eps, v.part, v.kpart, st); break;
   }
   hipLaunchKernelGGL(k_bcombine, dim3(qblocks), dim3(kBlock), 0, st, v.part, v.kpart, order, plan.S, Q, sdf, bound,
                      kept, offset);

@@ -372,9 +372,14 @@ __global__ __launch_bounds__(kBlock) void k_fit(const float* __restrict__ p, con
 
 // Bounds of each unit of kUnit consecutive slots (one wave per unit): center
 // c = midpoint of the unit's box, radius r >= max |p - c| (FP64, rounded up),
-// and the unit's point e farthest from c (lowest slot among ties).
-__global__ __launch_bounds__(kBlock) void k_units(const float4* __restrict__ pos4, int64_t N,
-                                                  float4* __restrict__ ub) {
+// and the unit's point e farthest from c (lowest slot among ties); and the
+// unit's oriented box (ob), whose first axis is the mean of its points' unit
+// normals (each signed to agree with the first point's), the others completing
+// an orthonormal frame, with its center and half-extents measured in FP64 from
+// the stored FP32 center and axes and rounded up, so that every point lies in
+// the box as stored.
+__global__ __launch_bounds__(kBlock) void k_units(const float4* __restrict__ pos4, const float4* __restrict__ bas,
+                                                  int64_t N, float4* __restrict__ ub, float4* __restrict__ ob) {
   const int64_t u = int64_t(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int64_t nunit = (N + kUnit - 1) / kUnit;
@@ -406,6 +411,60 @@ __global__ __launch_bounds__(kBlock) void k_units(const float4* __restrict__ pos
   if (lane == 0) {
     ub[2 * u] = make_float4(cx, cy, cz, float(d * (1.0 + 1e-6)) + 1e-30f);
     ub[2 * u + 1] = make_float4(ex, ey, ez, 0.f);
+  }
+  // the oriented box
+  float nx = 0.f, ny = 0.f, nz = 0.f;
+  if (valid) {
+    const float4 B = bas[2 * s + 1];
+    nx = B.x; ny = B.y; nz = B.z;
+  }
+  const float fx = __shfl(nx, 0), fy = __shfl(ny, 0), fz = __shfl(nz, 0);
+  const float sg = fx * nx + fy * ny + fz * nz < 0.f ? -1.f : 1.f;
+  float m[3] = {sg * nx, sg * ny, sg * nz};
+  for (int o = 32; o > 0; o >>= 1)
+    for (int k = 0; k < 3; ++k) m[k] += __shfl_xor(m[k], o);
+  float ax[3][3];
+  const float mn = sqrtf(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+  if (mn > 1e-6f) {
+    for (int k = 0; k < 3; ++k) ax[0][k] = m[k] / mn;
+  } else {
+    ax[0][0] = 0.f; ax[0][1] = 0.f; ax[0][2] = 1.f;
+  }
+  const float tx = fabsf(ax[0][0]) < 0.9f ? 1.f : 0.f, ty = 1.f - tx;  // (1,0,0) or (0,1,0)
+  float c1[3] = {ax[0][1] * 0.f - ax[0][2] * ty, ax[0][2] * tx - ax[0][0] * 0.f, ax[0][0] * ty - ax[0][1] * tx};
+  const float cn = sqrtf(c1[0] * c1[0] + c1[1] * c1[1] + c1[2] * c1[2]);
+  for (int k = 0; k < 3; ++k) ax[1][k] = c1[k] / cn;
+  ax[2][0] = ax[0][1] * ax[1][2] - ax[0][2] * ax[1][1];
+  ax[2][1] = ax[0][2] * ax[1][0] - ax[0][0] * ax[1][2];
+  ax[2][2] = ax[0][0] * ax[1][1] - ax[0][1] * ax[1][0];
+  // center: the midpoint of the extents along the axes
+  double plo[3], phi[3];
+  for (int k = 0; k < 3; ++k) {
+    const double t = double(px) * ax[k][0] + double(py) * ax[k][1] + double(pz) * ax[k][2];
+    plo[k] = valid ? t : 1e300;
+    phi[k] = valid ? t : -1e300;
+  }
+  for (int o = 32; o > 0; o >>= 1)
+    for (int k = 0; k < 3; ++k) {
+      plo[k] = fmin(plo[k], __shfl_xor(plo[k], o));
+      phi[k] = fmax(phi[k], __shfl_xor(phi[k], o));
+    }
+  double cd[3] = {0.0, 0.0, 0.0};
+  for (int k = 0; k < 3; ++k)
+    for (int j = 0; j < 3; ++j) cd[j] += 0.5 * (plo[k] + phi[k]) * ax[k][j];
+  const float bx = float(cd[0]), by = float(cd[1]), bz = float(cd[2]);
+  // half-extents about the stored center along the stored axes
+  double e[3];
+  for (int k = 0; k < 3; ++k) {
+    const double t = (double(px) - bx) * ax[k][0] + (double(py) - by) * ax[k][1] + (double(pz) - bz) * ax[k][2];
+    e[k] = valid ? fabs(t) : 0.0;
+  }
+  for (int o = 32; o > 0; o >>= 1)
+    for (int k = 0; k < 3; ++k) e[k] = fmax(e[k], __shfl_xor(e[k], o));
+  if (lane == 0) {
+    ob[4 * u] = make_float4(bx, by, bz, 0.f);
+    for (int k = 0; k < 3; ++k)
+      ob[4 * u + 1 + k] = make_float4(ax[k][0], ax[k][1], ax[k][2], float(e[k] * (1.0 + 1e-6)) + 1e-30f);
   }
 }
 
@@ -478,8 +537,9 @@ int launch_build(const float* p, const float* n, const float* a, int64_t N, floa
   hipLaunchKernelGGL(k_fit, dim3(nb), dim3(kBlock), 0, st, p, n, a, N, kfloor_rel, h, idx[cur], pos4,
                      reinterpret_cast<float4*>(base + L.rec), reinterpret_cast<int32_t*>(base + L.perm),
                      reinterpret_cast<float4*>(base + L.base), h);
-  hipLaunchKernelGGL(k_units, dim3(unsigned((L.nunit + 3) / 4)), dim3(kBlock), 0, st, pos4, N,
-                     reinterpret_cast<float4*>(base + L.ub));
+  hipLaunchKernelGGL(k_units, dim3(unsigned((L.nunit + 3) / 4)), dim3(kBlock), 0, st, pos4,
+                     reinterpret_cast<const float4*>(base + L.base), N, reinterpret_cast<float4*>(base + L.ub),
+                     reinterpret_cast<float4*>(base + L.ob));
   if (int rc = check_hip(hipGetLastError(), "build kernels")) return rc;
   return launch_blocks(rec, N, st);
 }

@@ -13,7 +13,7 @@
 namespace pts {
 
 constexpr uint32_t kMagic = 0x31535450u;  // "PTS1"
-constexpr int kRecordVersion = 3;
+constexpr int kRecordVersion = 4;
 constexpr int kBlock = 256;               // threads per workgroup (4 waves of 64)
 constexpr int kTile2 = 128;               // points per LDS tile of the derivative sweeps (80 B each)
 // Points per LDS tile of the blend (k_blend, and k_blend_multi, which must sum
@@ -85,6 +85,9 @@ __host__ __device__ inline size_t align256(size_t b) { return (b + 255) & ~size_
 //   ub    [U][2]  float4 bounds of each kUnit-point unit of slots, U = ceil(N / kUnit):
 //                 (center c, radius r) and (the unit's point farthest from c, 0)
 //   bb    [B]     float4 (center, radius) of each block of kBlkU units, B = ceil(U / kBlkU)
+//   ob    [U][4]  float4 oriented box of each unit: (center c, 0), then (a_k, e_k) for
+//                 k = 0..2, axes a_k (a_0 the unit's mean normal) and half-extents e_k with
+//                 |<p - c, a_k>| <= e_k for every point p of the unit
 //   base  [N][2]  float4 (p, A) and (n / |n|, -<p, n / |n|>): the baseline evaluators'
 //                 point record (A = area weight, 1 unless set by pts_set_areas)
 //   flag  [N]     int32 build scratch (direct-form flag)
@@ -92,7 +95,7 @@ __host__ __device__ inline size_t align256(size_t b) { return (b + 255) & ~size_
 //   key, idx [2][N] uint32 / int32 build scratch (sort keys and indices, ping-pong)
 //   rhist [16*nb] int32 build scratch (radix histograms)
 struct Layout {
-  size_t pos, rec, perm, ub, bb, base, flag, blk, key, idx, rhist, total;
+  size_t pos, rec, perm, ub, bb, ob, base, flag, blk, key, idx, rhist, total;
   int64_t nblk, nunit, nbk;
   __host__ __device__ explicit Layout(int64_t N) {
     nblk = (N + kBlock - 1) / kBlock;
@@ -103,7 +106,8 @@ struct Layout {
     perm = rec + align256(size_t(N) * 16 * kRecF4);
     ub = perm + align256(size_t(N) * 4);
     bb = ub + align256(size_t(nunit) * 32);
-    base = bb + align256(size_t(nbk) * 16);
+    ob = bb + align256(size_t(nbk) * 16);
+    base = ob + align256(size_t(nunit) * 64);
     flag = base + align256(size_t(N) * 32);
     blk = flag + align256(size_t(N) * 4);
     key = blk + align256(size_t(nblk) * 8);
