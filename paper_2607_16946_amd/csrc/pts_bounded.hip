@@ -3,10 +3,17 @@
 //
 // The bound.  Every torus passes through its anchor o_i = p_i + a00_i n_i
 // (Sec. 4.1), so |g_i(x)| <= |x - o_i| <= |x - p_i| + A with A = max |a00|.
-// For a unit of n points inside the sphere (c, r) and a query x at
-// s = |x - c|, every weight is at most w_u = exp(-lambda_x (max(s - r, 0) - sigma_x))
-// and every |g_i| at most s + r + A, so the unit adds at most
-//   d_u = n w_u  to the denominator,  g_u = d_u (s + r + A)  to |numerator|.
+// For a unit of n points whose distances to a query x lie in [d_lo, d_hi],
+// every weight is at most w_u = exp(-lambda_x (d_lo - sigma_x)) and every
+// |g_i| at most d_hi + A, so the unit adds at most
+//   d_u = n w_u  to the denominator,  g_u = d_u (d_hi + A)  to |numerator|.
+// A 4096-point block takes d_lo = max(s - r, 0), d_hi = s + r from its
+// bounding sphere (c, r), s = |x - c|; a 64-point unit takes them from its
+// oriented box (the build's unit boxes, first axis along the unit's mean
+// normal): with t_k = |<x - c, a_k>| and half-extents e_k,
+// d_lo = |max(t - e, 0)| and d_hi = |t + e|.  Surface patches are thin along
+// their normal, so the box's d_lo is well above the sphere's for queries off
+// the surface.
 // If the skipped units' totals are D_s <= sum d_u and G_s <= sum g_u and the
 // kept sums give phi' = N_k / D_k, then
 //   |phi - phi'| = |N_s - phi' D_s| / (D_k + D_s) <= (G_s + |phi'| D_s) / D_k,

@@ -98,3 +98,45 @@ def test_bounded_edge_cases():
     # one point: nothing to skip
     one = synth.Cloud(cl.p[:1].copy(), cl.n[:1].copy(), cl.a[:1].copy(), {})
     _check(one, x, 1e-2, what="one point")
+
+
+def _a256(n):
+    return (n + 255) // 256 * 256
+
+
+@pytest.mark.parametrize("which", ["mid", "mixed", "ragged"])
+def test_unit_boxes_hold_their_points(which):
+    # the build's oriented unit boxes, read from the record buffer at the
+    # offsets of its layout (pts_internal.h): every point lies inside its
+    # unit's box as stored (FP64 check), the frame is orthonormal, and the box
+    # is thin along its first axis (the mean normal) on a smooth surface
+    if which == "mid":
+        cl, _ = synth.mid(N=20000, grid=4)
+    elif which == "mixed":
+        cl = synth.mixed_forms_cloud(5000)
+    else:
+        cl, _ = synth.mid(N=4097, grid=4)
+    c = binding.Cloud(_dev(cl.p), _dev(cl.n), _dev(cl.a))
+    N = c.N
+    U = (N + 63) // 64
+    NB = (U + 63) // 64
+    pos = 256
+    rec = pos + _a256(N * 16)
+    perm = rec + _a256(N * 80)
+    ub = perm + _a256(N * 4)
+    bb = ub + _a256(U * 32)
+    ob = bb + _a256(NB * 16)
+    raw = c.rec.cpu().numpy()
+    recs = raw[rec:rec + N * 80].view(np.float32).reshape(N, 5, 4)
+    box = raw[ob:ob + U * 64].view(np.float32).reshape(U, 4, 4).astype(np.float64)
+    p = recs[:, 0, :3].astype(np.float64)
+    slots = np.arange(N)
+    u = slots // 64
+    ax = box[u, 1:, :3]                                # [N, 3, 3]
+    t = np.abs(np.einsum("nkj,nj->nk", ax, p - box[u, 0, :3]))
+    assert np.all(t <= box[u, 1:, 3]), (t - box[u, 1:, 3]).max()
+    gram = np.einsum("ukj,ulj->ukl", box[:, 1:, :3], box[:, 1:, :3])
+    assert np.abs(gram - np.eye(3)).max() < 1e-6
+    if which == "mid":
+        e = box[:, 1:, 3]
+        assert np.median(e[:, 0]) < 0.5 * np.median(e[:, 1])
