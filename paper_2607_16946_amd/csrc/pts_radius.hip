@@ -40,6 +40,7 @@ struct Tree {
   const float4* pos4;  // (-2p, |p|^2) per slot
   const float4* ub;    // per unit: (c, r), (e, 0)
   const float4* bb;    // per block: (c, r)
+  const float4* ob;    // per unit: oriented box (c, 0), (a_k, e_k)
   int64_t N, nunit, nbk;
 };
 
@@ -50,6 +51,7 @@ __device__ __forceinline__ Tree tree_of(const void* rec, int64_t N) {
   t.pos4 = reinterpret_cast<const float4*>(base + L.pos);
   t.ub = reinterpret_cast<const float4*>(base + L.ub);
   t.bb = reinterpret_cast<const float4*>(base + L.bb);
+  t.ob = reinterpret_cast<const float4*>(base + L.ob);
   t.N = N;
   t.nunit = L.nunit;
   t.nbk = L.nbk;
@@ -67,6 +69,22 @@ __device__ __forceinline__ bool reaches(float x, float y, float z, const float4&
   const float dx = x - S.x, dy = y - S.y, dz = z - S.z;
   const float lim = fmaf(rad, 1.00001f, S.w);
   return fmaf(dz, dz, fmaf(dy, dy, dx * dx)) <= lim * lim;
+}
+
+// The same question for a unit's oriented box B[0..3] (center, then axis and
+// half-extent per axis): its nearest distance is |max(t - e, 0)| with
+// t_k = |<x - c, a_k>|.  Asked after the sphere test passes; the limit adds
+// 1e-6 of the farthest distance for the FP32 rounding of t.
+__device__ __forceinline__ bool reaches_box(float x, float y, float z, const float4* __restrict__ B, float rad) {
+  const float4 C = B[0], A0 = B[1], A1 = B[2], A2 = B[3];
+  const float ex = x - C.x, ey = y - C.y, ez = z - C.z;
+  const float t0 = fabsf(fmaf(ez, A0.z, fmaf(ey, A0.y, ex * A0.x)));
+  const float t1 = fabsf(fmaf(ez, A1.z, fmaf(ey, A1.y, ex * A1.x)));
+  const float t2 = fabsf(fmaf(ez, A2.z, fmaf(ey, A2.y, ex * A2.x)));
+  const float l0 = fmaxf(t0 - A0.w, 0.f), l1 = fmaxf(t1 - A1.w, 0.f), l2 = fmaxf(t2 - A2.w, 0.f);
+  const float hsum = (t0 + A0.w) + (t1 + A1.w) + (t2 + A2.w);
+  const float lim = fmaf(rad, 1.00001f, 1e-6f * hsum);
+  return fmaf(l2, l2, fmaf(l1, l1, l0 * l0)) <= lim * lim;
 }
 
 template <int K>
@@ -115,7 +133,7 @@ __device__ void knn(const Tree& T, float x, float y, float z, int64_t self, floa
     if (!reaches(x, y, z, T.bb[b], rad)) continue;
     const int64_t v1 = min(T.nunit, (b + 1) * kBlkU);
     for (int64_t u = b * kBlkU; u < v1; ++u) {
-      if (u == su || !reaches(x, y, z, T.ub[2 * u], rad)) continue;
+      if (u == su || !reaches(x, y, z, T.ub[2 * u], rad) || !reaches_box(x, y, z, T.ob + 4 * u, rad)) continue;
       const int64_t e = min(T.N, (u + 1) * kUnit);
       for (int64_t s = u * kUnit; s < e; ++s) {
         if (s == self) continue;
@@ -139,7 +157,7 @@ __device__ int blend_within(const Tree& T, const float4* rec, int64_t nd, float 
     if (!reaches(x, y, z, T.bb[b], rad)) continue;
     const int64_t v1 = min(T.nunit, (b + 1) * kBlkU);
     for (int64_t u = b * kBlkU; u < v1; ++u) {
-      if (!reaches(x, y, z, T.ub[2 * u], rad)) continue;
+      if (!reaches(x, y, z, T.ub[2 * u], rad) || !reaches_box(x, y, z, T.ob + 4 * u, rad)) continue;
       const int64_t e = min(T.N, (u + 1) * kUnit);
       for (int64_t s = u * kUnit; s < e; ++s) {
         const float d2 = dist2(x, y, z, T.pos4[s]);
