@@ -621,6 +621,25 @@ def trace_bench(cl, res: int = 1024, steps: int = 64):
            "workload": f"{res}x{res} camera at 1.5 D, 45 deg, {steps} steps, eps 1e-4 D, tmax 3 D, normals"}
     log(f"trace: {R} rays x {steps} steps in {sec:.2f} s, {out['hits']} hits, {steps_sum:.4g} ray-steps, "
         f"{out['pairs_per_s']:.4g} pairs/s")
+    # the same march with each step's phi from the error-bounded evaluation
+    # (pts_trace_bounded), 1e-6 D per step against the 1e-4 D hit threshold
+    ee = 1e-6 * D
+    binding.trace(rec, N, od[:4096], dd[:4096], steps=4, eps=1e-4 * D, tmax=3.0 * D, params=prm, eval_eps=ee)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tb, hb, nsb, nrb = binding.trace(rec, N, od, dd, steps=steps, eps=1e-4 * D, tmax=3.0 * D, params=prm,
+                                     eval_eps=ee)
+    torch.cuda.synchronize()
+    secb = time.perf_counter() - t1
+    both = hit & hb
+    dt = float((tb[both] - t[both]).abs().max()) if bool(both.any()) else 0.0
+    steps_b = float(torch.clamp(nsb, max=steps).sum())
+    out["bounded"] = {"eval_eps_over_D": 1e-6, "seconds": secb, "speedup": sec / secb, "hits": int(hb.sum()),
+                      "ray_steps": steps_b, "effective_pairs_per_s": steps_b * N / secb,
+                      "hit_disagreements": int((hit != hb).sum()), "max_abs_dt_over_D": dt / D,
+                      "max_normal_diff": float((nrb[both] - nrm[both]).abs().max()) if bool(both.any()) else 0.0}
+    log(f"trace (bounded phi, eval_eps 1e-6 D): {secb:.2f} s ({sec / secb:.2f}x), {out['bounded']['hits']} hits, "
+        f"{out['bounded']['hit_disagreements']} rays differ in hit, max |dt| {dt / D:.2e} D")
     return out
 
 
@@ -650,6 +669,7 @@ def main():
                     help="oracle sample (queries of the large workload); about 7 s on 16 host threads")
     ap.add_argument("--no-mid", action="store_true", help="skip the mid workload's step")
     ap.add_argument("--no-trace", action="store_true", help="skip the large workload's 1024^2 x 64-step trace")
+    ap.add_argument("--trace-only", action="store_true", help="only the large workload's traces (exact and bounded)")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation workload")
     ap.add_argument("--no-baselines", action="store_true", help="skip the two baselines of the accuracy comparison")
     ap.add_argument("--no-radius", action="store_true", help="skip the radius-limited evaluation")
@@ -716,6 +736,10 @@ def main():
         return
     if args.small_only:
         print(json.dumps({"small": small_bench()}))
+        return
+    if args.trace_only:
+        cl, _ = synth.large()
+        print(json.dumps({"trace": trace_bench(cl)}))
         return
     if args.radius_only:
         cl, x = synth.large() if args.radius_only == "large" else synth.mid()

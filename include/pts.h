@@ -220,10 +220,12 @@ int pts_eval_bounded_ws_bytes(int64_t N, int64_t Q, const pts_params* prm, size_
  * units, >= 0), on top of the FP32 rounding pts_eval has.  The bound rests on
  * each torus passing through its anchor o_i = p_i + a00_i n_i (Sec. 4.1), so
  * |g_i(x)| <= |x - p_i| + max|a00|, and on the shifted weights of
- * Eq. (BasicFormulaShifted): a 64-point unit in the sphere (c, r) adds at most
- * n exp(-lambda_x (|x - c| - r - sigma_x)) to the denominator.  A unit is
- * skipped (by a whole wavefront of queries, processed in Morton order) only
- * while the skipped bounds stay within eps times the denominator kept so far.
+ * Eq. (BasicFormulaShifted): n points at distance >= d_lo from x add at most
+ * n exp(-lambda_x (d_lo - sigma_x)) to the denominator, d_lo taken from the
+ * bounding sphere of a 4096-point block or the oriented box of a 64-point
+ * unit (both built with the record).  A unit or block is skipped (by a whole
+ * wavefront of queries, processed in Morton order) only while the skipped
+ * bounds stay within eps times the denominator kept so far.
  *   bound [Q] (may be NULL)  the bound actually incurred, (G_s + |phi| D_s)/D_k
  *                            (<= eps up to FP32 rounding of the bound itself);
  *   kept [Q]  (may be NULL)  points evaluated for the query (N without skips).
@@ -405,6 +407,23 @@ int pts_trace_ws_bytes(int64_t N, int64_t R, const pts_params* prm, size_t* out_
 int pts_trace(const void* rec, int64_t N, const float* origin, const float* dir, int64_t R, int steps,
               float eps, float tmax, float* t_out, float* normal_out, int32_t* hit_out,
               int32_t* steps_out, const pts_params* prm, void* ws, size_t ws_bytes, void* stream);
+
+/* Scratch bytes for pts_trace_bounded with R rays (enough for any number of
+ * rays still marching). */
+int pts_trace_bounded_ws_bytes(int64_t N, int64_t R, const pts_params* prm, size_t* out_bytes);
+
+/* pts_trace with every step's phi from the error-bounded evaluation of
+ * pts_eval_bounded at eval_eps (finite, >= 0, the cloud's distance units):
+ * each step's phi is within eval_eps of pts_trace's (plus FP32 rounding), so
+ * with eval_eps well below eps the march takes the same steps up to
+ * differences of order steps x eval_eps in t, and a ray near the hit
+ * threshold may stop one step apart.  The normals at hits are pts_trace's
+ * (the exact gradient).  A ray's phi depends on the rays marching beside it
+ * (they share the evaluation's wavefront votes) only within eval_eps.
+ * Arguments otherwise as pts_trace; ws_bytes >= pts_trace_bounded_ws_bytes. */
+int pts_trace_bounded(const void* rec, int64_t N, const float* origin, const float* dir, int64_t R, int steps,
+                      float eps, float tmax, float eval_eps, float* t_out, float* normal_out, int32_t* hit_out,
+                      int32_t* steps_out, const pts_params* prm, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Radius-limited evaluation (Sec. 4.2, "Acceleration and adaptive lambda"):

@@ -116,8 +116,11 @@ SIGNATURES = {
     "pts_backward_points": (ctypes.c_int, [_P, _I64, _P, _P, _P, _P, _I64, _P, _P, _P, _P, _P,
                                            ctypes.POINTER(Params), _P, _SZ, _P]),
     "pts_trace_ws_bytes": (ctypes.c_int, [_I64, _I64, ctypes.POINTER(Params), ctypes.POINTER(_SZ)]),
+    "pts_trace_bounded_ws_bytes": (ctypes.c_int, [_I64, _I64, ctypes.POINTER(Params), ctypes.POINTER(_SZ)]),
     "pts_trace": (ctypes.c_int, [_P, _I64, _P, _P, _I64, ctypes.c_int, ctypes.c_float, ctypes.c_float, _P, _P, _P, _P,
                                  ctypes.POINTER(Params), _P, _SZ, _P]),
+    "pts_trace_bounded": (ctypes.c_int, [_P, _I64, _P, _P, _I64, ctypes.c_int, ctypes.c_float, ctypes.c_float,
+                                         ctypes.c_float, _P, _P, _P, _P, ctypes.POINTER(Params), _P, _SZ, _P]),
     "pts_radius_prepare": (ctypes.c_int, [_P, _I64, ctypes.POINTER(Params), _P]),
     "pts_radius_info_get": (ctypes.c_int, [_P, ctypes.POINTER(RadiusInfo), _P]),
     "pts_eval_radius_ws_bytes": (ctypes.c_int, [_I64, _I64, ctypes.POINTER(_SZ)]),
@@ -495,8 +498,12 @@ def backward_points(rec: torch.Tensor, p: torch.Tensor, n: torch.Tensor, a: torc
 
 
 def trace(rec: torch.Tensor, N: int, origin: torch.Tensor, direction: torch.Tensor, steps: int, eps: float,
-          tmax: float, params: Params | None = None, normals: bool = True, ws: torch.Tensor | None = None):
-    """Sphere tracing (Sec. 5.3): returns (t [R], hit [R] bool, steps [R] int32, normals [R,3] or None)."""
+          tmax: float, params: Params | None = None, normals: bool = True, ws: torch.Tensor | None = None,
+          eval_eps: float | None = None):
+    """Sphere tracing (Sec. 5.3): returns (t [R], hit [R] bool, steps [R] int32, normals [R,3] or None).
+
+    With eval_eps (>= 0) every step evaluates phi with the error-bounded
+    evaluation at that eps (pts_trace_bounded)."""
     _dev(origin, "origin", 3)
     _dev(direction, "direction", 3)
     R = origin.shape[0]
@@ -508,12 +515,20 @@ def trace(rec: torch.Tensor, N: int, origin: torch.Tensor, direction: torch.Tens
     ns = torch.empty(R, dtype=torch.int32, device=origin.device)
     nrm = torch.empty((R, 3), dtype=torch.float32, device=origin.device) if normals else None
     out = _SZ(0)
-    _check(lib().pts_trace_ws_bytes(int(N), R, ctypes.byref(prm), ctypes.byref(out)))
+    if eval_eps is None:
+        _check(lib().pts_trace_ws_bytes(int(N), R, ctypes.byref(prm), ctypes.byref(out)))
+    else:
+        _check(lib().pts_trace_bounded_ws_bytes(int(N), R, ctypes.byref(prm), ctypes.byref(out)))
     if ws is None or ws.numel() < out.value:
         ws = torch.empty(max(out.value, 256), dtype=torch.uint8, device=origin.device)
-    _check(lib().pts_trace(_ptr(rec), int(N), _ptr(origin), _ptr(direction), R, int(steps), float(eps), float(tmax),
-                           _ptr(t), _ptr(nrm), _ptr(hit), _ptr(ns), ctypes.byref(prm), _ptr(ws), ws.numel(),
-                           _stream()))
+    if eval_eps is None:
+        _check(lib().pts_trace(_ptr(rec), int(N), _ptr(origin), _ptr(direction), R, int(steps), float(eps),
+                               float(tmax), _ptr(t), _ptr(nrm), _ptr(hit), _ptr(ns), ctypes.byref(prm), _ptr(ws),
+                               ws.numel(), _stream()))
+    else:
+        _check(lib().pts_trace_bounded(_ptr(rec), int(N), _ptr(origin), _ptr(direction), R, int(steps), float(eps),
+                                       float(tmax), float(eval_eps), _ptr(t), _ptr(nrm), _ptr(hit), _ptr(ns),
+                                       ctypes.byref(prm), _ptr(ws), ws.numel(), _stream()))
     return t, hit.bool(), ns, nrm
 
 

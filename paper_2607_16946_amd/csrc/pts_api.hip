@@ -461,4 +461,31 @@ int pts_trace(const void* rec, int64_t N, const float* origin, const float* dir,
                       ws_bytes, static_cast<hipStream_t>(stream));
 }
 
+int pts_trace_bounded_ws_bytes(int64_t N, int64_t R, const pts_params* prm, size_t* out_bytes) {
+  if (!out_bytes) return fail(PTS_EINVAL, "out_bytes is NULL");
+  if (N < 1 || R < 0) return fail(PTS_EINVAL, "N must be >= 1 and R >= 0");
+  if (R > (int64_t(1) << 31) - 1) return fail(PTS_EINVAL, "R must be < 2^31");
+  const pts_params P = resolve(prm);
+  if (int rc = check_params(P)) return rc;
+  *out_bytes = R == 0 ? 0 : trace_bounded_ws_bytes(N, R, P);
+  return PTS_OK;
+}
+
+int pts_trace_bounded(const void* rec, int64_t N, const float* origin, const float* dir, int64_t R, int steps,
+                      float eps, float tmax, float eval_eps, float* t_out, float* normal_out, int32_t* hit_out,
+                      int32_t* steps_out, const pts_params* prm, void* ws, size_t ws_bytes, void* stream) {
+  if (N < 1 || R < 0) return fail(PTS_EINVAL, "N must be >= 1 and R >= 0");
+  if (R > (int64_t(1) << 31) - 1) return fail(PTS_EINVAL, "R must be < 2^31");
+  if (steps < 0) return fail(PTS_EINVAL, "steps must be >= 0");
+  if (!(eps >= 0.f) || !(tmax >= 0.f)) return fail(PTS_EINVAL, "eps and tmax must be >= 0");
+  if (!(eval_eps >= 0.f) || !std::isfinite(eval_eps)) return fail(PTS_EINVAL, "eval_eps must be finite and >= 0");
+  if (R == 0) return PTS_OK;
+  if (!rec || !origin || !dir || !t_out || !hit_out || !ws) return fail(PTS_EINVAL, "null pointer");
+  const pts_params P = resolve(prm);
+  if (int rc = check_params(P)) return rc;
+  if (ws_bytes < trace_bounded_ws_bytes(N, R, P)) return fail(PTS_EINVAL, "workspace too small");
+  return launch_trace(rec, N, origin, dir, R, steps, eps, tmax, t_out, normal_out, hit_out, steps_out, P, ws,
+                      ws_bytes, static_cast<hipStream_t>(stream), eval_eps);
+}
+
 }  // extern "C"

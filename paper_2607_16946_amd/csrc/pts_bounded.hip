@@ -59,6 +59,8 @@
 //   k_bcombine fixed-order sum over splits, phi', the bound, kept counts
 #include "pts_device.h"
 
+#include <algorithm>
+
 namespace pts {
 namespace {
 
@@ -502,6 +504,19 @@ BoundedWs bounded_ws(const Plan& plan, int64_t Q, void* ws) {
 }  // namespace
 
 size_t bounded_ws_bytes(const Plan& plan, int64_t Q) { return bounded_ws(plan, Q, nullptr).bytes; }
+
+// The largest workspace of any query count 1..R.  Every section but the
+// partials grows with Q; the partials are S x Q, with S constant while the
+// query block count nqb stays in [2^k, 2^(k+1) - 1] (bounded_plan doubles S
+// while nqb S < 8192), so the largest Q of each such range, and R, cover it.
+size_t bounded_ws_max(int64_t N, int64_t R) {
+  size_t m = bounded_ws_bytes(bounded_plan(N, R), R);
+  for (int64_t nb = 1; nb <= 2 * 8192; nb *= 2) {
+    const int64_t q = std::min<int64_t>(R, (2 * nb - 1) * int64_t(kBW));
+    m = std::max(m, bounded_ws_bytes(bounded_plan(N, q), q));
+  }
+  return m;
+}
 
 int launch_query_order(const void* rec, const float* x, int64_t Q, uint32_t* key[2], int32_t* idx[2],
                        int32_t* rhist, hipStream_t st, const int32_t** order) {

@@ -196,6 +196,7 @@ int launch_query_order(const void* rec, const float* x, int64_t Q, uint32_t* key
 // skipped while a proven bound on the change of phi stays within eps.
 Plan bounded_plan(int64_t N, int64_t Q);
 size_t bounded_ws_bytes(const Plan& plan, int64_t Q);
+size_t bounded_ws_max(int64_t N, int64_t R);  // over every query count 1..R
 int launch_bounded(const void* rec, int64_t N, const float* x, int64_t Q, float eps, float C, const Plan& plan,
                    void* ws, float* sdf, float* bound, int32_t* kept, hipStream_t st, float offset = 0.f);
 
@@ -285,9 +286,12 @@ Plan march_plan(int64_t N, int64_t Q, const pts_params& P, int cap);
 Plan normal_plan(int64_t N, int64_t Q, const pts_params& P);
 size_t trace_eval_ws_bytes(int64_t N, int64_t R, const pts_params& P, int cap);  // evaluation part of the workspace
 size_t trace_ws_bytes(int64_t N, int64_t R, const pts_params& P);
+// eval_eps < 0: every step evaluates phi exactly (pts_eval's kernels); >= 0:
+// with the error-bounded evaluation at that eps (workspace trace_bounded_ws_bytes).
+size_t trace_bounded_ws_bytes(int64_t N, int64_t R, const pts_params& P);
 int launch_trace(const void* rec, int64_t N, const float* org, const float* dir, int64_t R, int steps, float eps,
                  float tmax, float* t, float* nrm, int32_t* hit, int32_t* nsteps, const pts_params& P, void* ws,
-                 size_t ws_bytes, hipStream_t st);
+                 size_t ws_bytes, hipStream_t st, float eval_eps = -1.f);
 // Single steps of the march with the active-ray count left on the device.
 int trace_init(int64_t R, int steps, float* t, int32_t* hit, int32_t* nsteps, int32_t* act, float* nrm,
                hipStream_t st);

@@ -216,9 +216,13 @@ size_t trace_ws_bytes(int64_t N, int64_t R, const pts_params& P) {
   return trace_fixed_bytes(R) + trace_eval_ws_bytes(N, R, P, kMarchSplitCap);
 }
 
+size_t trace_bounded_ws_bytes(int64_t N, int64_t R, const pts_params& P) {
+  return trace_fixed_bytes(R) + std::max(bounded_ws_max(N, R), grad_ws_bytes(normal_plan(N, R, P), R));
+}
+
 int launch_trace(const void* rec, int64_t N, const float* org, const float* dir, int64_t R, int steps, float eps,
                  float tmax, float* t, float* nrm, int32_t* hit, int32_t* nsteps_out, const pts_params& P, void* ws,
-                 size_t ws_bytes, hipStream_t st) {
+                 size_t ws_bytes, hipStream_t st, float eval_eps) {
   const TraceWs v = trace_ws(ws, R, ws_bytes);
   int32_t* nsteps = nsteps_out ? nsteps_out : v.nsteps;
   hipLaunchKernelGGL(k_init_rays, dim3(nblk(R)), dim3(kBlock), 0, st, R, steps, t, hit, nsteps, v.act0, nrm);
@@ -226,10 +230,17 @@ int launch_trace(const void* rec, int64_t N, const float* org, const float* dir,
   int32_t* nxt = v.act1;
   int64_t na = R;
   for (int k = 0; k < steps && na > 0; ++k) {
-    const Plan plan = march_plan(N, na, P, kMarchSplitCap);
-    const WsView wv = ws_view(plan, na, v.eval);
     hipLaunchKernelGGL(k_positions, dim3(nblk(na)), dim3(kBlock), 0, st, act, na, org, dir, t, v.xq);
-    if (int rc = launch_eval_plain(rec, N, v.xq, na, P.C, plan, wv, v.phi, st, P.offset)) return rc;
+    if (eval_eps >= 0.f) {
+      const Plan plan = bounded_plan(N, na);
+      if (int rc = launch_bounded(rec, N, v.xq, na, eval_eps, P.C, plan, v.eval, v.phi, nullptr, nullptr, st,
+                                  P.offset))
+        return rc;
+    } else {
+      const Plan plan = march_plan(N, na, P, kMarchSplitCap);
+      const WsView wv = ws_view(plan, na, v.eval);
+      if (int rc = launch_eval_plain(rec, N, v.xq, na, P.C, plan, wv, v.phi, st, P.offset)) return rc;
+    }
     hipLaunchKernelGGL(k_advance, dim3(nblk(na)), dim3(kBlock), 0, st, act, na, v.phi, eps, tmax, k, t, hit, nsteps,
                        v.keep);
     int64_t nn = 0;

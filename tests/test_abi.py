@@ -74,6 +74,27 @@ def test_host_side_errors(L):
     assert wp.value >= wa.value * 12 // 8 + 3000 * (4 + 4 + 48)
 
 
+def test_bounded_trace_host_checks(L):
+    # argument checks before any device work, and a workspace that covers the
+    # bounded evaluation at every number of rays still marching (its point
+    # splits grow as the active set shrinks)
+    prm = binding.make_params()
+    args = (None, 1000, None, None, 5, 8, 1e-3, 1.0)
+    tail = (None, None, None, None, ctypes.byref(prm), None, 0, None)
+    assert L.pts_trace_bounded(*args, -1.0, *tail) == binding.PTS_EINVAL
+    assert b"eval_eps" in L.pts_last_error()
+    assert L.pts_trace_bounded(*args, float("inf"), *tail) == binding.PTS_EINVAL
+    assert L.pts_trace_bounded(None, 1000, None, None, 0, 8, 1e-3, 1.0, 0.0, *tail) == binding.PTS_OK
+    out, q = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    for N, R in ((4096, 5000), (131072, 70000), (1 << 20, 1 << 20)):
+        assert L.pts_trace_bounded_ws_bytes(N, R, ctypes.byref(prm), ctypes.byref(out)) == binding.PTS_OK
+        for Q in sorted({1, 63, 64, 65, 4095, 4096, 8191, 65536, 65535 * 2, R // 3, R - 1, R} - {0}):
+            if Q > R:
+                continue
+            assert L.pts_eval_bounded_ws_bytes(N, Q, ctypes.byref(prm), ctypes.byref(q)) == binding.PTS_OK
+            assert out.value >= q.value, (N, R, Q)
+
+
 def test_parameter_ranges(L):
     """C in (0, 75] (the weights' FP32 range with the shift min(C, 64)); kfloor_rel >= 1e-12."""
     out = ctypes.c_size_t(0)
