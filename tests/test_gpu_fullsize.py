@@ -124,3 +124,36 @@ def test_mid_full_size_baselines_and_bounded_sampled():
     print(f"mid full size bounded (eps 1e-6 D): max err {err:.3e}, {100 * frac:.1f}% of pairs evaluated", flush=True)
     assert err <= eps + TOL * D and float(bd.max().item()) <= eps * (1 + 1e-3)
     assert frac < 0.5
+
+
+def test_farthest_point_over_two_block_chunks():
+    # 1,200,000 points make 293 blocks of 4096 slots, so the culled
+    # farthest-point sweep marks its block spheres in two chunks of 256;
+    # 2^18 queries keep the unsplit launch (one workgroup per query block).
+    # M and the direction to the farthest point (statistics: the sweep that
+    # also tracks the farthest slot), and phi of both sweeps, on a sample.
+    cl, x = synth.large(N=1_200_000, Q=1 << 18)
+    c = binding.Cloud(_dev(cl.p), _dev(cl.n), _dev(cl.a))
+    xs = _dev(x)
+    phi_s, st = c(xs, stats=True)
+    phi = c(xs).cpu().numpy().astype(np.float64)
+    phi_s, st = phi_s.cpu().numpy().astype(np.float64), st.cpu().numpy().astype(np.float64)
+    idx = np.sort(np.random.default_rng(80).choice(x.shape[0], 96, replace=False))
+    p = cl.p.astype(np.float64)
+    M_ref, e_ref, decided = [], [], []
+    for q in idx:
+        d = np.linalg.norm(x[q].astype(np.float64) - p, axis=1)
+        top = np.argpartition(d, -2)[-2:]
+        top = top[np.argsort(d[top])]
+        M_ref.append(d[top[1]])
+        e_ref.append((x[q] - p[top[1]]) / d[top[1]])
+        decided.append(d[top[1]] - d[top[0]] > 1e-5 * d[top[1]])
+    M_ref, e_ref, decided = np.array(M_ref), np.array(e_ref), np.array(decided)
+    assert np.all(np.abs(st[idx, 0] - M_ref) <= 1e-6 * M_ref)
+    assert np.abs(st[idx[decided], 3:6] - e_ref[decided]).max() < 1e-5
+    D = oracle.bbox_diag(cl.p)
+    ref = oracle.sdf(cl.p, cl.n, cl.a, x[idx])
+    print(f"1.2M points, 2^18 queries: max |phi - oracle| {np.abs(phi[idx] - ref).max():.3e} "
+          f"(stats sweep {np.abs(phi_s[idx] - ref).max():.3e}), tolerance {TOL * D:.3e}", flush=True)
+    assert np.abs(phi[idx] - ref).max() <= TOL * D
+    assert np.abs(phi_s[idx] - ref).max() <= TOL * D
