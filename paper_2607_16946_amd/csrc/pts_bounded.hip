@@ -221,6 +221,9 @@ __device__ __forceinline__ bool vote(const float4& sb, float n, const float* qx,
   return true;
 }
 
+// The largest share of the remaining budget one unit's skip may spend.
+constexpr float kSkipShare = 0.25f;
+
 // The same vote for the n points of a unit inside the oriented box B[0..3]
 // (center, then axis and half-extent per axis): with t_k = |<x - c, a_k>|,
 // every point is at least |max(t - e, 0)| and at most |t + e| from x.  The
@@ -245,8 +248,14 @@ __device__ __forceinline__ bool vote_box(const float4* __restrict__ B, float n, 
     const float dmin = fmaxf(hw_sqrt(fmaf(l2, l2, fmaf(l1, l1, l0 * l0))) - kSlack * dmax, 0.f);
     du[k] = n * hw_exp2(fmaf(dmin, nl[k], S2)) * (1.f + kSlack);
     gu[k] = du[k] * (dmax + A) * (1.f + kSlack);
-    const bool skip = (gs[k] + gu[k]) + phimax[k] * (ds[k] + du[k]) <= eps * (den[k] * (1.f - kSlack) + wseed[k]);
-    ok = ok && (skip || !live[k]);
+    const float budget = eps * (den[k] * (1.f - kSlack) + wseed[k]);
+    const bool fits = (gs[k] + gu[k]) + phimax[k] * (ds[k] + du[k]) <= budget;
+    // and no more than kSkipShare of what is left of the budget (or a share
+    // of it below FP32 resolution): skips that would spend much of it are
+    // kept, so the budget lasts for the many cheap units further out
+    const float cost = gu[k] + phimax[k] * du[k];
+    const bool share = cost <= kSkipShare * (budget - (gs[k] + phimax[k] * ds[k])) || cost <= 1e-7f * budget;
+    ok = ok && ((fits && share) || !live[k]);
   }
   if (__ballot(!ok) != 0ull) return false;
 #pragma unroll
