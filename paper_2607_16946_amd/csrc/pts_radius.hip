@@ -99,7 +99,11 @@ __device__ __forceinline__ void list_insert(float (&a)[K], float v) {
 
 // The K smallest squared distances from x to the points (slot `self` excluded),
 // ascending in a[]; entries stay kInf when there are fewer than K points.
-template <int K>
+// kSeedFirst walks the seed's block before the others (the order does not
+// change the result): measured faster for the per-point search of the
+// preparation (every query on the surface), slower for the evaluation's
+// lattice queries, whose waves then split over different seed blocks.
+template <int K, bool kSeedFirst>
 __device__ void knn(const Tree& T, float x, float y, float z, int64_t self, float (&a)[K]) {
 #pragma unroll
   for (int i = 0; i < K; ++i) a[i] = kInf;
@@ -128,9 +132,11 @@ __device__ void knn(const Tree& T, float x, float y, float z, int64_t self, floa
     if (d2 < a[K - 1]) list_insert(a, d2);
   }
   float rad = a[K - 1] < kInf ? sqrtf(a[K - 1]) : kInf;
-  // every other unit the current radius can reach, in slot order
-  for (int64_t b = 0; b < T.nbk; ++b) {
-    if (!reaches(x, y, z, T.bb[b], rad)) continue;
+  // every other unit the current radius can reach, in slot order (with
+  // kSeedFirst the seed's block first, so that the radius is near its final
+  // value before the other blocks are tested)
+  auto walk = [&](int64_t b) {
+    if (!reaches(x, y, z, T.bb[b], rad)) return;
     const int64_t v1 = min(T.nunit, (b + 1) * kBlkU);
     for (int64_t u = b * kBlkU; u < v1; ++u) {
       if (u == su || !reaches(x, y, z, T.ub[2 * u], rad) || !reaches_box(x, y, z, T.ob + 4 * u, rad)) continue;
@@ -144,7 +150,10 @@ __device__ void knn(const Tree& T, float x, float y, float z, int64_t self, floa
         }
       }
     }
-  }
+  };
+  if (kSeedFirst) walk(sb);
+  for (int64_t b = 0; b < T.nbk; ++b)
+    if (!kSeedFirst || b != sb) walk(b);
 }
 
 // Blend over every point with squared distance <= lim2:
@@ -213,7 +222,7 @@ __global__ __launch_bounds__(kBlock) void k_knn_mean(const Header* __restrict__ 
   const Tree T = tree_of(rec, N);
   const float4 P = T.pos4[s];
   float a[kKnnD];
-  knn<kKnnD>(T, -0.5f * P.x, -0.5f * P.y, -0.5f * P.z, s, a);
+  knn<kKnnD, true>(T, -0.5f * P.x, -0.5f * P.y, -0.5f * P.z, s, a);
   const int kk = int(min<int64_t>(kKnnD, N - 1));
   double sum = 0.0;
   for (int i = 0; i < kKnnD; ++i)
@@ -272,7 +281,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_radius(const Header* __restrict
   int cnt = blend_within(T, rec, h->n_direct, qi.x, qi.y, qi.z, reval * reval, h->rl_shift, lam2, num, den);
   if (cnt == 0) {
     float a[kKnnFb];
-    knn<kKnnFb>(T, qi.x, qi.y, qi.z, -1, a);
+    knn<kKnnFb, false>(T, qi.x, qi.y, qi.z, -1, a);
     const float lim2 = a[kKnnFb - 1];            // kInf when N < 32: every point
     cnt = -blend_within(T, rec, h->n_direct, qi.x, qi.y, qi.z, lim2, sqrtf(a[0]), lam2, num, den);
   }
