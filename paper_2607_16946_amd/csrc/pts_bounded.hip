@@ -22,7 +22,9 @@
 // eps D_run, the kept denominator so far; D_run <= D_k, so the final bound
 // (G_s + |phi'| D_s) / D_k <= eps.  The kernel reports that bound per query.
 // Bounds carry a relative slack of 1e-4 for FP32 rounding of s, the exponent
-// and D_run; the returned phi' itself has the rounding of the plain blend.
+// and D_run, and the budget gives up U 2^-23 (U units) for the bounds that
+// the FP32 running sums of G_s and D_s absorb; the returned phi' itself has
+// the rounding of the plain blend.
 //
 // Making skips pay.  A unit's work is skipped by a whole wave or not at all,
 // so the wave's queries must agree: queries are processed in Morton order of
@@ -304,7 +306,11 @@ __global__ __launch_bounds__(kBW, 8) void k_bounded(const Header* __restrict__ h
   const int64_t beg = int64_t(split) * per_split;
   const int64_t end = min(N, beg + per_split);
   const int64_t u_beg = beg / kUnit, u_end = (end + kUnit - 1) / kUnit;
-  const float eps = S > 1 ? eps_total / float(S + 1) : eps_total;
+  // every skip adds its bounds to FP32 sums, and each addition may lose up
+  // to 2^-24 of the sum it lands in; with at most one addition per unit and
+  // per block, the budget gives that up front (U 2^-23, U units)
+  const float absorb = fminf(0.5f, float((N + kUnit - 1) / kUnit) * 0x1p-23f);
+  const float eps = (S > 1 ? eps_total / float(S + 1) : eps_total) * (1.f - absorb);
   // the wave's first query, in record coordinates
   const QueryIn r0 = load_query(xs, j0, Q, h);
   const int64_t useed = nearest_unit(ub, 0, (N + kUnit - 1) / kUnit, r0.x, r0.y, r0.z, red_v, red_i);
