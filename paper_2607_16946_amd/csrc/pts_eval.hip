@@ -73,14 +73,15 @@ __global__ __launch_bounds__(kBlock) void k_far_cull(const Header* __restrict__ 
 
 // The same sweep for calls with few query blocks, over the blend's point
 // splits as well: workgroup b covers split b % S of query block b / S, with
-// the bound of pts_farcull.h's far_bound_split (splits of at most
+// the bound of pts_farcull.h's far_bound_split_reach (splits of at most
 // kFarPlainMax points are swept whole), and writes row `split` of far2 (and
 // farix).  A split may miss its own maximum but never the cloud's;
 // k_far_fold keeps the largest row and, among equal ones, the first split
 // (the lowest slots), so row 0 ends up bitwise what k_far_cull writes.
 template <int QPL, bool kArg>
 __global__ __launch_bounds__(kBlock) void k_far_split(const Header* __restrict__ h, const float4* __restrict__ pos4,
-                                                      const float4* __restrict__ ub, const float* __restrict__ x,
+                                                      const float4* __restrict__ ub, const float4* __restrict__ bb,
+                                                      const float* __restrict__ x,
                                                       int64_t Q, int S, int64_t per_split, float* __restrict__ far2,
                                                       int32_t* __restrict__ farix) {
   __shared__ FarLds L;
@@ -106,9 +107,10 @@ __global__ __launch_bounds__(kBlock) void k_far_split(const Header* __restrict__
     far_sweep_plain<QPL, kArg>(pos4, beg, end, qx, qy, qz, acc, ix, L);
   } else {
     const int64_t u_lo = beg / kUnit, u_hi = max(u_lo, (end + kUnit - 1) / kUnit);
-    far_bound_split<QPL>(ub, U, u_lo, u_hi, qx, qy, qz, lb, L);
-    far_threshold<QPL>(lb, ok);
-    far_sweep<QPL, kArg>(pos4, ub, u_lo, u_hi, end, qx, qy, qz, ok, lb, acc, ix, L);
+    if (far_bound_split_reach<QPL>(ub, bb, U, u_lo, u_hi, qx, qy, qz, ok, lb, L)) {
+      far_threshold<QPL>(lb, ok);
+      far_sweep<QPL, kArg>(pos4, ub, u_lo, u_hi, end, qx, qy, qz, ok, lb, acc, ix, L);
+    }
   }
 #pragma unroll
   for (int k = 0; k < QPL; ++k) {
@@ -256,8 +258,8 @@ void launch_far_q(const Header* h, const float4* pos4, const float4* ub, const f
                   int64_t Q, int64_t nqb,
                   int S, int64_t per_split, float* far2, int32_t* farix, hipStream_t st, bool fold) {
   if (S > 1) {
-    hipLaunchKernelGGL((k_far_split<QPL, kArg>), dim3(unsigned(nqb * S)), dim3(kBlock), 0, st, h, pos4, ub, x, Q, S,
-                       per_split, far2, farix);
+    hipLaunchKernelGGL((k_far_split<QPL, kArg>), dim3(unsigned(nqb * S)), dim3(kBlock), 0, st, h, pos4, ub, bb, x, Q,
+                       S, per_split, far2, farix);
     if (fold && (farix || !combine_by_wave(S, Q)))
       hipLaunchKernelGGL(k_far_fold, dim3(unsigned((Q + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, far2, farix, S,
                          Q);

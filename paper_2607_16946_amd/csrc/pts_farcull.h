@@ -50,17 +50,36 @@ __device__ __forceinline__ void far_bound(const float4* __restrict__ ub, int64_t
   }
 }
 
-// The bound of a sweep over the point split [beg, end) of a cloud of U
-// units: the extreme points of every stride-th unit (kSampleU of them) and of
-// the split's own units [u_lo, u_hi).
+// The bound of a sweep over the point split [u_lo, u_hi) of a cloud of U
+// units, in two steps so that a split no query can reach costs only the
+// sample: the extreme points of kSampleU units sampled across the cloud
+// first; then, only if some block sphere (bb) over the split's units
+// [u_lo, u_hi) reaches that bound's threshold for some query of the
+// workgroup, those of the split's own units.  Returns false (uniform across
+// the workgroup) when none does: the split then holds no point at any
+// query's farthest distance, and nothing of it needs sweeping.
 template <int QPL>
-__device__ __forceinline__ void far_bound_split(const float4* __restrict__ ub, int64_t U, int64_t u_lo, int64_t u_hi,
-                                                const float (&qx)[QPL], const float (&qy)[QPL],
-                                                const float (&qz)[QPL], float (&lb)[QPL], FarLds& L) {
+__device__ __forceinline__ bool far_bound_split_reach(const float4* __restrict__ ub, const float4* __restrict__ bb,
+                                                      int64_t U, int64_t u_lo, int64_t u_hi, const float (&qx)[QPL],
+                                                      const float (&qy)[QPL], const float (&qz)[QPL],
+                                                      const bool (&ok)[QPL], float (&lb)[QPL], FarLds& L) {
   const int64_t stride = (U + kSampleU - 1) / kSampleU;
   const int64_t n_samp = (U + stride - 1) / stride;
-  far_bound<QPL>(ub, n_samp + (u_hi - u_lo),
-                 [=](int64_t i) { return i < n_samp ? i * stride : u_lo + (i - n_samp); }, qx, qy, qz, lb, L);
+  far_bound<QPL>(ub, n_samp, [=](int64_t i) { return i * stride; }, qx, qy, qz, lb, L);
+  bool reach = false;
+  for (int64_t b = u_lo / kBlkU; b < (u_hi + kBlkU - 1) / kBlkU; ++b) {
+    const float4 C = bb[b];
+#pragma unroll
+    for (int k = 0; k < QPL; ++k) {
+      const float t = sqrtf(fmaxf(lb[k], 0.f)) * (1.f - 1e-5f) - C.w;
+      const float dx = qx[k] - C.x, dy = qy[k] - C.y, dz = qz[k] - C.z;
+      const float dc2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+      reach = reach || (ok[k] && lb[k] >= 0.f && (t <= 0.f || !(dc2 < t * t)));
+    }
+  }
+  if (!__syncthreads_or(reach)) return false;
+  far_bound<QPL>(ub, u_hi - u_lo, [=](int64_t i) { return u_lo + i; }, qx, qy, qz, lb, L);
+  return true;
 }
 
 // The squared bound becomes the cull threshold LB (1 - 1e-5); a query with a

@@ -16,8 +16,9 @@ namespace {
 constexpr int kQpl = 2;
 // Farthest point per query and point split, culled (pts_farcull.h) within
 // the split: the lower bound comes from the extreme points of a fixed sample
-// of the cloud's units and of the split's own units, and only the split's
-// units that can reach it are swept.  A split may then miss its own maximum,
+// of the cloud's units (a split whose block spheres cannot reach it stops
+// there) and of the split's own units, and only the split's units that can
+// reach it are swept.  A split may then miss its own maximum,
 // but never the cloud's: the unit holding the farthest point is always swept,
 // with the same arithmetic as a full sweep, and the blend reads only the
 // maximum over splits, so M is bitwise that of a full sweep.
@@ -48,11 +49,14 @@ __global__ __launch_bounds__(kBlock) void k_far_multi(const WorkDesc* __restrict
     far_sweep_plain<kQpl, false>(pos4, beg, end, qx, qy, qz, acc, ix, L);
   } else {
     const int64_t u_lo = beg / kUnit, u_hi = max(u_lo, (end + kUnit - 1) / kUnit);
-    // 1. lower bound: extreme points of sampled units and of the split's units
-    far_bound_split<kQpl>(ub, U, u_lo, u_hi, qx, qy, qz, lb, L);
-    far_threshold<kQpl>(lb, ok);
-    // 2./3. the split's units that can reach it
-    far_sweep<kQpl, false>(pos4, ub, u_lo, u_hi, end, qx, qy, qz, ok, lb, acc, ix, L);
+    // 1. lower bound: extreme points of sampled units and, if the split's
+    // block spheres reach it, of the split's units; 2./3. the split's units
+    // that can reach it
+    const float4* bb = reinterpret_cast<const float4*>(d.rec + lay.bb);
+    if (far_bound_split_reach<kQpl>(ub, bb, U, u_lo, u_hi, qx, qy, qz, ok, lb, L)) {
+      far_threshold<kQpl>(lb, ok);
+      far_sweep<kQpl, false>(pos4, ub, u_lo, u_hi, end, qx, qy, qz, ok, lb, acc, ix, L);
+    }
   }
 #pragma unroll
   for (int k = 0; k < kQpl; ++k) {
