@@ -66,7 +66,7 @@ extern "C" {
 #define PTS_ENOTFOUND 7   /* unknown cloud id or ticket                      */
 #define PTS_ETIMEOUT 8    /* wait timed out                                  */
 
-/* Library version (major * 100 + minor). */
+/* Library version (major * 100 + minor): 101 (1.01 adds pts_trace_bounded). */
 int pts_version(void);
 
 /* Message for the last non-zero status returned on the calling thread. */
@@ -140,7 +140,8 @@ typedef struct pts_cloud_info {
   float bbox_lo[3], bbox_hi[3];
   float diag;         /* bbox diagonal D */
   float kfloor;       /* curvature floor used */
-  int version;
+  int version;        /* record layout version: 4 (with the oriented unit boxes);
+                         a record is built and read by the same library */
   int reserved;
 } pts_cloud_info;
 int pts_cloud_info_get(const void* rec, pts_cloud_info* out, void* stream);

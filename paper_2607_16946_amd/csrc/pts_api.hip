@@ -93,7 +93,7 @@ using namespace pts;
 
 extern "C" {
 
-int pts_version(void) { return 100; }
+int pts_version(void) { return 101; }
 
 const char* pts_last_error(void) { return g_last_error.c_str(); }
 
