@@ -570,11 +570,10 @@ int launch_bounded(const void* rec, int64_t N, const float* x, int64_t Q, float 
   int bcur = 0;
   if (int rc = launch_radix_sort(v.bkey, v.bidx, plan.nqb, 2, v.rhist, st, &bcur)) return rc;
   const int32_t* border = v.bidx[bcur];
-  switch (plan.qpl) {
-    case 1: launch_bounded_q<1>(h, recs, ub, bb, ob, v.xs, border, Q, plan, v.far2, C2, S2, eps, v.part, v.kpart, st); break;
-    case 2: launch_bounded_q<2>(h, recs, ub, bb, ob, v.xs, border, Q, plan, v.far2, C2, S2, eps, v.part, v.kpart, st); break;
-    default: launch_bounded_q<4>(h, recs, ub, bb, ob, v.xs, border, Q, plan, v.far2, C2, S2, eps, v.part, v.kpart, st); break;
-  }
+  // one query per lane (bounded_plan); the kernel is written for QPL queries
+  // per lane, but more than one needs more than 64 VGPRs at 8 waves per SIMD
+  if (plan.qpl != 1) return fail(PTS_EINVAL, "bounded evaluation plans one query per lane");
+  launch_bounded_q<1>(h, recs, ub, bb, ob, v.xs, border, Q, plan, v.far2, C2, S2, eps, v.part, v.kpart, st);
   hipLaunchKernelGGL(k_bcombine, dim3(qblocks), dim3(kBlock), 0, st, v.part, v.kpart, order, plan.S, Q, sdf, bound,
                      kept, offset);
   return check_hip(hipGetLastError(), "bounded evaluation kernels");
