@@ -297,6 +297,9 @@ __global__ __launch_bounds__(kBW, 8) void k_bounded(const Header* __restrict__ h
     live[k] = j < Q;
     const QueryIn qi = load_query(xs, j, live[k] ? Q : 0, h);
     qx[k] = qi.x; qy[k] = qi.y; qz[k] = qi.z;
+    // a query with a non-finite coordinate (its phi is NaN) takes no part in
+    // the votes, which its NaN bounds would otherwise block for the wave
+    live[k] = live[k] && isfinite(qi.x) && isfinite(qi.y) && isfinite(qi.z);
     float M = 0.f;
     nl[k] = 0.f;
     if (qi.valid) far_of(far2, 1, Q, j, C2, M, nl[k]);
@@ -311,8 +314,18 @@ __global__ __launch_bounds__(kBW, 8) void k_bounded(const Header* __restrict__ h
   // per block, the budget gives that up front (U 2^-23, U units)
   const float absorb = fminf(0.5f, float((N + kUnit - 1) / kUnit) * 0x1p-23f);
   const float eps = (S > 1 ? eps_total / float(S + 1) : eps_total) * (1.f - absorb);
-  // the wave's first query, in record coordinates
-  const QueryIn r0 = load_query(xs, j0, Q, h);
+  // the wave's first query with finite coordinates (in lane order; the first
+  // query if none is), in record coordinates: it seeds the sweep's order
+  QueryIn r0 = load_query(xs, j0, Q, h);
+  {
+    const unsigned long long fin = __ballot(live[0]);
+    if (fin != 0ull) {
+      const int src = __builtin_ctzll(fin);
+      r0.x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qx[0]), src));
+      r0.y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qy[0]), src));
+      r0.z = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qz[0]), src));
+    }
+  }
   const int64_t useed = nearest_unit(ub, 0, (N + kUnit - 1) / kUnit, r0.x, r0.y, r0.z, red_v, red_i);
   int64_t ustart = useed;
   if (useed < u_beg || useed >= u_end) {
@@ -354,7 +367,11 @@ __global__ __launch_bounds__(kBW, 8) void k_bounded(const Header* __restrict__ h
       if (taken) continue;
       const float4 cb = bb[b];
       const float ex = r0.x - cb.x, ey = r0.y - cb.y, ez = r0.z - cb.z;
-      const float lb = hw_sqrt(fmaf(ez, ez, fmaf(ey, ey, ex * ex))) - cb.w;
+      float lb = hw_sqrt(fmaf(ez, ez, fmaf(ey, ey, ex * ex))) - cb.w;
+      // a NaN or overflowing bound (seed not finite, or too far out) counts as
+      // the largest: such blocks tie and the lowest index wins, so every
+      // round of the search picks a block
+      lb = lb < 3.0e38f ? lb : 3.0e38f;
       if (lb < best || (lb == best && int32_t(b) < bi)) { best = lb; bi = int32_t(b); }
     }
 #pragma unroll

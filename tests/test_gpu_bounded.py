@@ -166,3 +166,29 @@ def test_bounded_far_queries():
         _check(cl, x, eps_rel, what="far queries", scale_phi=True)
         frac, _ = _check(cl, clus, eps_rel, what="far cluster", scale_phi=True)
         assert frac < 0.95
+
+
+def test_bounded_nan_query_keeps_its_wave_skipping():
+    # one query with a NaN coordinate among a coherent cluster: NaN for it,
+    # and the same points evaluated for its neighbours as without it
+    cl, _ = synth.mid(N=6000, grid=4)
+    D = oracle.bbox_diag(cl.p)
+    ctr = 0.5 * (cl.p.min(0) + cl.p.max(0))
+    rng = np.random.default_rng(13)
+    clus = (ctr + np.array([2.0, 0.3, -0.2]) * D + rng.normal(scale=0.02 * D, size=(1024, 3))).astype(np.float32)
+    c = binding.Cloud(_dev(cl.p), _dev(cl.n), _dev(cl.a))
+    _, _, k0 = binding.eval_bounded(c.rec, c.N, _dev(clus), 1e-4 * D, c.params, bound=True, kept=True)
+    bad = clus.copy()
+    bad[100, 1] = np.nan
+    phi, _, k1 = binding.eval_bounded(c.rec, c.N, _dev(bad), 1e-4 * D, c.params, bound=True, kept=True)
+    phi, k0, k1 = phi.cpu().numpy(), k0.cpu().numpy(), k1.cpu().numpy()
+    assert np.isnan(phi[100]) and np.all(np.isfinite(np.delete(phi, 100)))
+    assert np.delete(k1, 100).mean() <= 1.02 * np.delete(k0, 100).mean()
+    assert k0.mean() < 0.95 * c.N
+    # a whole wave of NaN queries (they sort first): its sweep order is seeded
+    # from no finite query, and the others are unaffected
+    bad = clus.copy()
+    bad[:64, 0] = np.nan
+    phi, bd, k2 = binding.eval_bounded(c.rec, c.N, _dev(bad), 1e-4 * D, c.params, bound=True, kept=True)
+    phi = phi.cpu().numpy()
+    assert np.all(np.isnan(phi[:64])) and np.all(np.isfinite(phi[64:]))
