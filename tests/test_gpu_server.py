@@ -229,3 +229,33 @@ def test_overlapping_launches_and_edge_requests():
               f"device busy {st['busy_s'] * 1e3:.1f} ms over {wall * 1e3:.1f} ms wall", flush=True)
         assert st["completed"] == 41
         assert st["overlapped_launches"] > 0
+
+
+def test_nonfinite_queries_and_rays_in_requests():
+    # NaN / inf queries inside a query request and NaN ray origins inside a
+    # trace request: non-finite results (no hit) for them, and the others
+    # bitwise those of the clean requests
+    cl = synth.mid(N=20000, grid=4)[0]
+    x = _queries(cl, 3000, 55)
+    xb = x.copy()
+    bad = np.array([0, 9, 700, 2999] + list(range(1200, 1270)))
+    xb[bad[0::2], 0] = np.nan
+    xb[bad[1::2], 2] = np.inf
+    good = np.ones(len(x), bool)
+    good[bad] = False
+    o, d = _rays(32, 3)
+    ob = o.copy()
+    rbad = np.array([1, 100, 500])
+    ob[rbad, 1] = np.nan
+    ok = np.ones(len(o), bool)
+    ok[rbad] = False
+    with Server(budget_bytes=1 << 30) as S:
+        cid = S.add_cloud(cl.p, cl.n, cl.a)
+        a = S.wait(S.submit_eval(cid, x))
+        b = S.wait(S.submit_eval(cid, xb))
+        assert not np.isfinite(b[~good]).any() and np.array_equal(a[good], b[good])
+        ta = S.wait(S.submit_trace(cid, o, d, steps=24, eps=1e-4, tmax=6.0, normals=True))
+        tb = S.wait(S.submit_trace(cid, ob, d, steps=24, eps=1e-4, tmax=6.0, normals=True))
+        assert not tb["hit"][~ok].any()
+        for k in ("t", "hit", "steps", "normal"):
+            assert np.array_equal(ta[k][ok], tb[k][ok]), k
