@@ -438,6 +438,8 @@ int pts_trace_bounded(const void* rec, int64_t N, const float* origin, const flo
  *            w_i = exp(-lambda (|x - p_i| - sigma));
  *   if no point lies within R_eval: the same blend over the 32 nearest points
  *   (all if N < 32), shifted by the nearest distance instead of sigma.
+ * A cloud whose every point has 64 or more coincident copies has D = 0, an
+ * infinite lambda and NaN results; it has no scale for this form.
  * ------------------------------------------------------------------------- */
 
 typedef struct pts_radius_info {
