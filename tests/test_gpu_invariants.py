@@ -12,7 +12,10 @@ case):
 * translation of points and queries leaves phi unchanged;
 * a permutation of the points leaves phi unchanged;
 * a rotation of an isotropic cloud (a01 = a10 = a11 = 0, a02 = a20) leaves
-  phi unchanged.
+  phi unchanged;
+* every point taken twice doubles every weight and leaves phi (a ratio of
+  weighted sums) and grad phi unchanged; the error-bounded evaluation of the
+  doubled cloud stays within its eps of it.
 
 The first four run on a curved cloud (mostly direct tori) and on a nearly
 flat cap (every torus in the anchored form).
@@ -104,3 +107,17 @@ def test_rotation_of_an_isotropic_cloud():
     phi = _phi(p, n, a, x)
     phi2 = _phi(p @ q.T, n @ q.T, a, x @ q.T)
     _report("rotation", np.abs(phi - phi2).max(), 2 * TOL_REL * D)
+
+
+def test_duplicated_points(cloud):
+    p, n, a, x, D = cloud
+    c1 = binding.Cloud(_dev(p), _dev(n), _dev(a))
+    c2 = binding.Cloud(_dev(np.concatenate([p, p])), _dev(np.concatenate([n, n])), _dev(np.concatenate([a, a])))
+    xs = _dev(x)
+    phi1, g1 = (t.cpu().numpy().astype(np.float64) for t in c1(xs, grad=True))
+    phi2, g2 = (t.cpu().numpy().astype(np.float64) for t in c2(xs, grad=True))
+    _report("duplicated points", np.abs(phi2 - phi1).max(), 2 * TOL_REL * D)
+    _report("duplicated points, grad", np.abs(g2 - g1).max(), 2e-4)
+    eps = 1e-6 * D
+    pb = binding.eval_bounded(c2.rec, c2.N, xs, eps, c2.params).cpu().numpy().astype(np.float64)
+    _report("duplicated points, bounded", np.abs(pb - phi1).max(), eps + 2 * TOL_REL * D)
