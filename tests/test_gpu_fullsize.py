@@ -157,3 +157,19 @@ def test_farthest_point_over_two_block_chunks():
           f"(stats sweep {np.abs(phi_s[idx] - ref).max():.3e}), tolerance {TOL * D:.3e}", flush=True)
     assert np.abs(phi[idx] - ref).max() <= TOL * D
     assert np.abs(phi_s[idx] - ref).max() <= TOL * D
+
+
+def test_farthest_point_tiny_cloud_many_queries():
+    # 100 points (two units, one block) under 2^18 queries: the culled
+    # unsplit sweep with its block pass over a single partial block
+    cl = synth.sphere_cloud(100, seed=81, jitter=0.02)
+    x = np.random.default_rng(82).uniform(-1.5, 1.5, size=(1 << 18, 3)).astype(np.float32)
+    c = binding.Cloud(_dev(cl.p), _dev(cl.n), _dev(cl.a))
+    phi, st = c(_dev(x), stats=True)
+    phi, st = phi.cpu().numpy().astype(np.float64), st.cpu().numpy().astype(np.float64)
+    idx = np.sort(np.random.default_rng(83).choice(x.shape[0], 400, replace=False))
+    d = np.linalg.norm(x[idx, None, :].astype(np.float64) - cl.p[None].astype(np.float64), axis=2)
+    assert np.all(np.abs(st[idx, 0] - d.max(1)) <= 1e-6 * d.max(1))
+    ref = oracle.sdf(cl.p, cl.n, cl.a, x[idx])
+    D = oracle.bbox_diag(cl.p)
+    assert np.abs(phi[idx] - ref).max() <= TOL * D
