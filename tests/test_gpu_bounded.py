@@ -86,6 +86,23 @@ def test_bounded_benchmark_size_sampled():
     assert frac < 0.5
 
 
+def test_bounded_many_ranges_few_queries():
+    # 100 queries on the 131072-point cloud: two query blocks, so the plan
+    # splits the points into 64 ranges that share one seed unit's weights
+    # (random queries over the whole box: every wave spans the cloud and
+    # skips nothing; a tight cluster: the ranges far from it skip)
+    cl, _ = synth.mid(N=131072, grid=4)
+    lo, hi = synth.padded_bbox(cl.p, 0.1)
+    rng = np.random.default_rng(14)
+    x = rng.uniform(lo, hi, size=(100, 3)).astype(np.float32)
+    clus = (cl.p[7] + rng.normal(scale=0.01, size=(100, 3))).astype(np.float32)
+    for eps_rel in (0.0, 1e-6, 1e-4):
+        _check(cl, x, eps_rel, what="64 ranges, random")
+        frac, _ = _check(cl, clus, eps_rel, what="64 ranges, cluster")
+        if eps_rel > 0:
+            assert frac < 0.9
+
+
 def test_bounded_edge_cases():
     cl, x = synth.tiny(Q=50, N=700)
     c = binding.Cloud(_dev(cl.p), _dev(cl.n), _dev(cl.a))
