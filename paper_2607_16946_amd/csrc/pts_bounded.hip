@@ -21,6 +21,9 @@
 // is skipped only while G_s + Phi D_s (totals including it) stays within
 // eps D_run, the kept denominator so far; D_run <= D_k, so the final bound
 // (G_s + |phi'| D_s) / D_k <= eps.  The kernel reports that bound per query.
+// Which skips to take is free within that rule: a unit's skip may also spend
+// no more than a quarter of the budget still left, so that early, expensive
+// skips do not use up what the many cheap far units would need.
 // Bounds carry a relative slack of 1e-4 for FP32 rounding of s, the exponent
 // and D_run, and the budget gives up U 2^-23 (U units) for the bounds that
 // the FP32 running sums of G_s and D_s absorb; the returned phi' itself has
