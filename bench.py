@@ -709,7 +709,7 @@ def main():
         print(json.dumps({"copy_bytes": src.numel() * 4}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU figures are not produced "
+        print(json.dumps({"error": "the benchmark runs on one GPU; multi-GPU figures are not produced "
                                    "(queries shard across GPUs with no exchange; see the design notes)"}))
         sys.exit(2)
 
