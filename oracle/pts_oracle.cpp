@@ -58,7 +58,7 @@
 //             of Eq. (RelationshipBetweenLambdaAndRadius), as the blend does
 //             (the equations write sigma_x; lambda is the same heuristic).
 //   R-base-A  area weights A_i are an input; absent, A_i = 1 (the library
-//             Voronoi areas the paper uses are not part of this build).
+//             Voronoi areas the paper uses are not computed here).
 //   R-base-n  <x - p_i, n_i> uses the normal scaled to unit length.
 //   R-shc-zero    a double-layer sum of exactly 0 gives +inf (sign(0) = +1).
 //   R-shc-onpoint a query on a point (d_i = 0) gives NaN.
