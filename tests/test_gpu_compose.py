@@ -50,13 +50,15 @@ def test_offset_is_phi_minus_c_everywhere():
 
 
 @pytest.mark.parametrize("off", [0.25, -0.3])
-def test_trace_offset_sphere(off):
+@pytest.mark.parametrize("eval_eps", [None, 1e-7])
+def test_trace_offset_sphere(off, eval_eps):
+    # eval_eps: the march on the error-bounded phi (pts_trace_bounded)
     cl = synth.sphere_cloud(2000, seed=9, jitter=0.0)
     c = binding.Cloud(_dev(cl.p), _dev(cl.n), _dev(cl.a))
     org, d = synth.camera_rays(32, radius=3.0, fov_deg=40.0, seed=0)
     d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
     t, hit, _, nrm = binding.trace(c.rec, c.N, _dev(org), _dev(d), steps=64, eps=1e-5, tmax=8.0,
-                                   params=binding.make_params(offset=off))
+                                   params=binding.make_params(offset=off), eval_eps=eval_eps)
     t, hit, nrm = t.cpu().numpy(), hit.cpu().numpy(), nrm.cpu().numpy()
     o, dd = org.astype(np.float64), d.astype(np.float64)
     R = 1.0 + off
